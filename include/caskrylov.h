@@ -1,0 +1,246 @@
+/*
+ * caskrylov: SpMV-driven Krylov solvers with a cascaded kernel predictor and
+ * asynchronous kernel switching, for AMD Instinct MI355X (gfx950).
+ *
+ * The method is that of "Cascaded Prediction and Asynchronous Execution of
+ * Iterative Algorithms on Heterogeneous Platforms" (Gao, Liu, Wang, Ji,
+ * Huang; arXiv 2411.10143):
+ *   - solve A x = b with CG or restarted GMRES, whose dominant kernel is
+ *     sparse matrix-vector multiplication (Introduction);
+ *   - choose the SpMV configuration in three cascaded stages -- storage
+ *     format, then algorithm, then kernel parameter -- from 15 matrix
+ *     features (Section III-B-1, feature table; Section III-C-1, cascaded
+ *     prediction figure);
+ *   - start the solve at once on a default configuration and swap in each
+ *     stage's choice at the next iteration boundary after it is ready, while
+ *     features, inference and format conversion run concurrently
+ *     (Section III-C-2, asynchronous execution).
+ *
+ * Conventions for every entry point
+ *   - Pointers named d_* are DEVICE pointers (hipMalloc'd or torch-allocated
+ *     HIP memory on the current device); all others are host pointers.
+ *   - Index arrays are int32; values are IEEE binary64 unless "f32" says so.
+ *   - Every call returns ck_status and never aborts, throws or exits.  On a
+ *     non-OK status, ck_last_error() returns a thread-local message.
+ *   - HIP failures return CK_E_HIP (the hipError_t text is in the message).
+ *   - Streams: hipStream_t values owned by the caller; 0 is the null stream.
+ *     Enqueued work is ordered on the given stream only.
+ */
+#ifndef CASKRYLOV_H
+#define CASKRYLOV_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CK_OK = 0,
+    CK_E_INVALID = -1,        /* bad argument or malformed CSR              */
+    CK_E_NOMEM = -2,          /* device allocation failed                   */
+    CK_E_HIP = -3,            /* a HIP runtime call failed                  */
+    CK_E_NOT_CONVERGED = -4,  /* iteration budget spent above tolerance     */
+    CK_E_BREAKDOWN = -5,      /* CG: p.Ap <= 0 (A not SPD); GMRES: singular */
+    CK_E_UNSUPPORTED = -6,    /* e.g. ELL refused because of padding fill   */
+    CK_E_CANCELLED = -7       /* work abandoned before it finished          */
+} ck_status;
+
+/* Opaque matrix handle: owns device copies of the CSR arrays and of every
+ * other format built from them. */
+typedef struct ck_matrix *ck_handle;
+
+/* ---- SpMV configuration space (Section III-B-2, configuration figure) ----
+ * format    : CK_FMT_CSR, CK_FMT_ELL or CK_FMT_COO
+ * algorithm : for CSR only -- CK_ALG_SCALAR (one lane per row, row block
+ *             staged through LDS), CK_ALG_VECTOR (`lanes` lanes per row),
+ *             CK_ALG_MERGE (merge-path load balancing)
+ * lanes     : for CSR-vector, 1, 2, 4, 8, 16, 32 or 64 lanes per row
+ * stages_done: how many cascade stages produced this configuration (0-3)
+ * Eleven configurations in all: 7 CSR-vector lane counts, CSR-scalar,
+ * CSR-merge, ELL, COO.  ck_config_id() numbers them 0..10 in that order. */
+enum { CK_FMT_CSR = 0, CK_FMT_ELL = 1, CK_FMT_COO = 2 };
+enum { CK_ALG_SCALAR = 0, CK_ALG_VECTOR = 1, CK_ALG_MERGE = 2 };
+#define CK_NUM_CONFIGS 11
+
+typedef struct {
+    int32_t format;
+    int32_t algorithm;
+    int32_t lanes;
+    int32_t stages_done;
+} ck_config;
+
+/* ---- Features (feature table, Section III-B-1) ----
+ * Integer accumulators are exact.  The derived values are computed on the
+ * host from the integers only:
+ *   density = nnz/(nrows*ncols)        mean = nnz/nrows
+ *   sd = sqrt(nrows*sum_r2 - sum_r^2)/nrows (radicand exact in 128 bits)
+ *   cov = sd/mean (0 if mean = 0)      maxavg = max_r - mean
+ *   distavg = span_sum/nrows           clusteravg = cluster_sum/nrows
+ *   fill = nrows*max_r/nnz             diagfill = nrows*ndiag/nnz (0 if nnz=0)
+ * span_sum = sum over rows of (last column - first column); cluster_sum =
+ * sum over rows of the longest run of consecutive column indices; ndiag =
+ * number of distinct (column - row) among stored entries; diag_nnz = stored
+ * main-diagonal entries; hist[0] = empty rows, hist[b] = rows with length in
+ * [2^(b-1), 2^b), hist[15] open-ended; is_symmetric = square with every
+ * stored a_ij matched by a stored a_ji of equal value. */
+typedef struct {
+    int64_t nrows, ncols, nnz, sum_r, sum_r2, max_r, min_r, span_sum, cluster_sum,
+        ndiag, diag_nnz, hist[16], is_symmetric;
+    double density, mean, sd, cov, maxavg, distavg, clusteravg, fill, diagfill;
+} ck_features;
+
+/* ---- Solver options and results ---- */
+enum { CK_PREC_FP64 = 0, CK_PREC_MIXED = 1 };
+
+typedef struct {
+    double tol;            /* stop when ||b - A x||_2 / ||b||_2 <= tol        */
+    int32_t max_iter;      /* budget of SpMV-bearing iterations               */
+    int32_t restart;       /* GMRES restart length m (<= 64); CG ignores it   */
+    int32_t precision;     /* CK_PREC_FP64 or CK_PREC_MIXED (FP32 inner solve
+                              + FP64 refinement; needs CK_KEEP_FP32)          */
+    int32_t async;         /* 1: start on the default configuration and swap
+                              in the cascade's choices mid-solve              */
+    int32_t check_every;   /* iterations between host convergence polls       */
+    int32_t use_config;    /* 1: run every SpMV with `config` (async ignored) */
+    ck_config config;
+} ck_solve_opts;
+
+typedef struct {
+    int32_t status;          /* ck_status of the solve                        */
+    int32_t iterations;      /* SpMV-bearing iterations performed             */
+    int32_t switch_iter[3];  /* iteration at which stage 1/2/3's choice took
+                                effect; -1 if it never did                    */
+    int32_t outer_steps;     /* restarts (CG) / cycles (GMRES) / refinements  */
+    double true_relres;      /* ||b - A x||/||b|| recomputed in FP64 at exit  */
+    double t_features_us, t_infer_us, t_convert_us, t_total_us;
+    ck_config final_config;
+} ck_solve_result;
+
+/* Flags for spmv_create */
+#define CK_KEEP_FP32 0x1u  /* also keep an FP32 copy of the values (mixed)   */
+
+/* ------------------------------------------------------------------------ */
+
+/* spmv_create -- ingest a CSR matrix (problem statement A x = b, Introduction;
+ * the CSR format of the configuration space, Section III-B-2).
+ * d_rowptr int32[nrows+1], d_col int32[nnz], d_val double[nnz] on the device.
+ * The arrays are COPIED (the caller may free them afterwards) and validated:
+ * rowptr[0] = 0, nondecreasing, rowptr[nrows] = nnz, 0 <= col < ncols,
+ * columns strictly increasing inside each row.  Malformed input gives
+ * CK_E_INVALID and *out = NULL.  Blocks until the copy is validated.
+ * The active configuration starts as ck_default_config(). */
+ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
+                      const int32_t *d_rowptr, const int32_t *d_col, const double *d_val,
+                      uint32_t flags, hipStream_t s);
+
+/* spmv_destroy -- free every device copy.  The caller must have finished all
+ * work that uses the handle.  NULL is ignored. */
+void spmv_destroy(ck_handle h);
+
+/* spmv_features -- the 15 features of the feature table (Section III-B-1),
+ * computed by GPU kernels on stream s; blocks until *out is filled. */
+ck_status spmv_features(ck_handle h, ck_features *out, hipStream_t s);
+
+/* spmv_select -- host-only cascaded inference (Section III-C-1): stage 1
+ * format, stage 2 CSR algorithm (only if CSR), stage 3 lanes (only if
+ * CSR-vector).  model_path: a cascade model file, or NULL for the model
+ * shipped next to the library.  A stage that does not run keeps the default
+ * configuration's value for its field.  *out->stages_done = stages run. */
+ck_status spmv_select(const ck_features *f, const char *model_path, ck_config *out);
+
+/* ck_select_stages -- the same inference, reporting each stage's raw class:
+ * stage[0] format, stage[1] algorithm (-1 if not run), stage[2] log2(lanes)
+ * (-1 if not run). */
+ck_status ck_select_stages(const ck_features *f, const char *model_path, int32_t stage[3]);
+
+/* ck_default_config -- the configuration a solve starts from before any
+ * prediction: CSR-vector with lanes = clamp(2^floor(log2(max(1, nnz/nrows))),
+ * 2, 64), which needs only the O(1) features. */
+ck_status ck_default_config(ck_handle h, ck_config *out);
+
+/* spmv_convert -- build the format `cfg` needs (Section III-C-1: a format
+ * switch converts the matrix).  CSR needs nothing.  ELL: column-major,
+ * K = longest row, pitch = nrows rounded up to 64, padding column -1 and
+ * value +0.0; refused with CK_E_UNSUPPORTED when K*pitch > 8*nnz.  COO: a
+ * row-index array (column and value arrays are shared with CSR).  Enqueued
+ * on s; the copy is usable by later work on s.  Idempotent. */
+ck_status spmv_convert(ck_handle h, const ck_config *cfg, hipStream_t s);
+
+/* ck_set_active / ck_get_active -- the configuration spmv_apply uses when
+ * given NULL.  Setting a format that has not been converted gives
+ * CK_E_INVALID. */
+ck_status ck_set_active(ck_handle h, const ck_config *cfg);
+ck_status ck_get_active(ck_handle h, ck_config *out);
+
+/* spmv_apply -- y = alpha*A*x + beta*y (the SpMV kernel of every Krylov
+ * iteration, Introduction).  cfg = NULL uses the active configuration; the
+ * format it names must have been converted.  beta = 0: y is not read.
+ * d_x has ncols entries, d_y nrows; they must not overlap.  Asynchronous:
+ * enqueued on s, returns at once. */
+ck_status spmv_apply(ck_handle h, const ck_config *cfg, double alpha, const double *d_x,
+                     double beta, double *d_y, hipStream_t s);
+
+/* spmv_apply_f32 -- the same product on the FP32 copy of the values (handle
+ * created with CK_KEEP_FP32), FP32 vectors and FP32 accumulation. */
+ck_status spmv_apply_f32(ck_handle h, const ck_config *cfg, float alpha, const float *d_x,
+                         float beta, float *d_y, hipStream_t s);
+
+/* cg_solve -- conjugate gradient (Hestenes-Stiefel) for SPD A, x0 in d_x
+ * (Introduction names CG as one of the two target solvers).  Stops when the
+ * recurred residual reaches opts->tol, then confirms on the true residual
+ * b - A x, restarting from the current x (at most 3 times) if needed.
+ * p.Ap <= 0 gives CK_E_BREAKDOWN.  opts->async = 1 runs the asynchronous
+ * executor (Section III-C-2).  MIXED precision: FP64 refinement around FP32
+ * CG segments.  Blocks until the result is final; d_x then holds x. */
+ck_status cg_solve(ck_handle h, const double *d_b, double *d_x, const ck_solve_opts *opts,
+                   ck_solve_result *res, hipStream_t s);
+
+/* gmres_solve -- restarted GMRES(m), x0 in d_x, no preconditioner (the
+ * solver of the paper's evaluation, Section IV).  Each cycle starts from the
+ * true residual; Arnoldi uses classical Gram-Schmidt applied twice; the
+ * Givens least-squares update runs on the device.  MIXED precision: each
+ * FP64 refinement step runs one FP32 GMRES(m) cycle on r/||r||. */
+ck_status gmres_solve(ck_handle h, const double *d_b, double *d_x, const ck_solve_opts *opts,
+                      ck_solve_result *res, hipStream_t s);
+
+/* ck_export_ell -- copy the ELL arrays (after spmv_convert to ELL) into
+ * caller buffers d_col int32[K*pitch], d_val double[K*pitch]; with NULL
+ * buffers only *K and *pitch are returned. */
+ck_status ck_export_ell(ck_handle h, int32_t *d_col, double *d_val, int64_t *K,
+                        int64_t *pitch, hipStream_t s);
+
+/* ck_export_coo_rows -- copy the COO row array (after spmv_convert to COO)
+ * into d_row int32[nnz]. */
+ck_status ck_export_coo_rows(ck_handle h, int32_t *d_row, hipStream_t s);
+
+/* ck_dot -- deterministic two-stage FP64 dot product of two device vectors
+ * (the inner product kernel of the Krylov loop, Introduction); result to
+ * the device scalar d_out.  Same inputs give the same bits on every call. */
+ck_status ck_dot(int64_t n, const double *d_x, const double *d_y, double *d_out, hipStream_t s);
+
+/* ck_config_id / ck_config_from_id -- number the 11 configurations 0..10:
+ * CSR-vector lanes 1,2,4,...,64 = 0..6, CSR-scalar = 7, CSR-merge = 8,
+ * ELL = 9, COO = 10.  Invalid input gives -1 / CK_E_INVALID. */
+int32_t ck_config_id(const ck_config *cfg);
+ck_status ck_config_from_id(int32_t id, ck_config *out);
+
+/* ck_kernel_name -- the device symbol of the SpMV kernel that a configuration
+ * launches (for matching profiler output); fp32 selects the FP32 variant.
+ * Writes a NUL-terminated string of at most cap bytes. */
+ck_status ck_kernel_name(const ck_config *cfg, int32_t fp32, char *buf, size_t cap);
+
+/* ck_spmv_bytes -- algorithmic bytes of one product on this matrix:
+ * nnz*(s+4) + 4*(nrows+1) + s*ncols + s*nrows [+ s*nrows if beta != 0],
+ * s = 8 (FP64) or 4 (FP32).  Format padding is not counted. */
+int64_t ck_spmv_bytes(ck_handle h, int32_t fp32, int32_t beta_nonzero);
+
+/* ck_last_error -- message for the last non-OK status on this thread. */
+const char *ck_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CASKRYLOV_H */

@@ -1,0 +1,343 @@
+"""ctypes binding of libcaskrylov.so (see include/caskrylov.h).
+
+Argument marshalling only: torch tensors become device pointers, torch
+streams become hipStream_t, ctypes structs mirror the C structs.  Every
+computation happens in the HIP library; if it is missing, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcaskrylov.so")
+DEFAULT_MODEL = os.path.join(_HERE, "cascade_model.txt")
+
+CK_OK, CK_E_INVALID, CK_E_NOMEM, CK_E_HIP = 0, -1, -2, -3
+CK_E_NOT_CONVERGED, CK_E_BREAKDOWN, CK_E_UNSUPPORTED, CK_E_CANCELLED = -4, -5, -6, -7
+STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "NOT_CONVERGED",
+                -5: "BREAKDOWN", -6: "UNSUPPORTED", -7: "CANCELLED"}
+CK_FMT_CSR, CK_FMT_ELL, CK_FMT_COO = 0, 1, 2
+CK_ALG_SCALAR, CK_ALG_VECTOR, CK_ALG_MERGE = 0, 1, 2
+CK_PREC_FP64, CK_PREC_MIXED = 0, 1
+CK_KEEP_FP32 = 1
+NUM_CONFIGS = 11
+CONFIG_NAMES = ["csr-vector-1", "csr-vector-2", "csr-vector-4", "csr-vector-8",
+                "csr-vector-16", "csr-vector-32", "csr-vector-64", "csr-scalar", "csr-merge",
+                "ell", "coo"]
+
+
+class CkError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [("format", C.c_int32), ("algorithm", C.c_int32), ("lanes", C.c_int32),
+                ("stages_done", C.c_int32)]
+
+    def __repr__(self):
+        return (f"Config(format={self.format}, algorithm={self.algorithm}, "
+                f"lanes={self.lanes}, stages_done={self.stages_done})")
+
+
+class Features(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("nrows", "ncols", "nnz", "sum_r", "sum_r2", "max_r",
+                                         "min_r", "span_sum", "cluster_sum", "ndiag", "diag_nnz")] + \
+               [("hist", C.c_int64 * 16), ("is_symmetric", C.c_int64)] + \
+               [(n, C.c_double) for n in ("density", "mean", "sd", "cov", "maxavg", "distavg",
+                                          "clusteravg", "fill", "diagfill")]
+
+    def ints(self):
+        """The 28 integer accumulators in the C layout order."""
+        return [self.nrows, self.ncols, self.nnz, self.sum_r, self.sum_r2, self.max_r,
+                self.min_r, self.span_sum, self.cluster_sum, self.ndiag, self.diag_nnz] + \
+               list(self.hist) + [self.is_symmetric]
+
+    def derived(self):
+        return [self.density, self.mean, self.sd, self.cov, self.maxavg, self.distavg,
+                self.clusteravg, self.fill, self.diagfill]
+
+    def model_inputs(self):
+        return [float(self.nrows), float(self.ncols), float(self.nnz), self.density, self.mean,
+                self.sd, self.cov, float(self.max_r), float(self.min_r), self.maxavg,
+                self.distavg, self.clusteravg, self.fill, float(self.ndiag), self.diagfill]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32),
+                ("precision", C.c_int32), ("async_", C.c_int32), ("check_every", C.c_int32),
+                ("use_config", C.c_int32), ("config", Config)]
+
+
+class SolveResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32),
+                ("switch_iter", C.c_int32 * 3), ("outer_steps", C.c_int32),
+                ("true_relres", C.c_double), ("t_features_us", C.c_double),
+                ("t_infer_us", C.c_double), ("t_convert_us", C.c_double),
+                ("t_total_us", C.c_double), ("final_config", Config)]
+
+    def as_dict(self):
+        return dict(status=self.status, iterations=self.iterations,
+                    switch_iter=list(self.switch_iter), outer_steps=self.outer_steps,
+                    true_relres=self.true_relres, t_features_us=self.t_features_us,
+                    t_infer_us=self.t_infer_us, t_convert_us=self.t_convert_us,
+                    t_total_us=self.t_total_us, final_config=config_id(self.final_config))
+
+
+_lib = None
+_vp = C.c_void_p
+_i32, _i64, _u32, _dbl, _flt = C.c_int32, C.c_int64, C.c_uint32, C.c_double, C.c_float
+
+# name -> (restype, argtypes); the C-ABI surface of include/caskrylov.h
+SIGNATURES = {
+    "spmv_create": (_i32, [C.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _vp, _u32, _vp]),
+    "spmv_destroy": (None, [_vp]),
+    "spmv_features": (_i32, [_vp, C.POINTER(Features), _vp]),
+    "spmv_select": (_i32, [C.POINTER(Features), C.c_char_p, C.POINTER(Config)]),
+    "ck_select_stages": (_i32, [C.POINTER(Features), C.c_char_p, C.POINTER(_i32)]),
+    "ck_default_config": (_i32, [_vp, C.POINTER(Config)]),
+    "spmv_convert": (_i32, [_vp, C.POINTER(Config), _vp]),
+    "ck_set_active": (_i32, [_vp, C.POINTER(Config)]),
+    "ck_get_active": (_i32, [_vp, C.POINTER(Config)]),
+    "spmv_apply": (_i32, [_vp, C.POINTER(Config), _dbl, _vp, _dbl, _vp, _vp]),
+    "spmv_apply_f32": (_i32, [_vp, C.POINTER(Config), _flt, _vp, _flt, _vp, _vp]),
+    "cg_solve": (_i32, [_vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveResult), _vp]),
+    "gmres_solve": (_i32, [_vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveResult), _vp]),
+    "ck_export_ell": (_i32, [_vp, _vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp]),
+    "ck_export_coo_rows": (_i32, [_vp, _vp, _vp]),
+    "ck_dot": (_i32, [_i64, _vp, _vp, _vp, _vp]),
+    "ck_config_id": (_i32, [C.POINTER(Config)]),
+    "ck_config_from_id": (_i32, [_i32, C.POINTER(Config)]),
+    "ck_kernel_name": (_i32, [C.POINTER(Config), _i32, C.c_char_p, C.c_size_t]),
+    "ck_spmv_bytes": (_i64, [_vp, _i32, _i32]),
+    "ck_last_error": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load libcaskrylov.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with "
+                              "`python -m paper_2411_10143_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(st):
+    if st != CK_OK:
+        raise CkError(st, lib().ck_last_error().decode())
+    return st
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _ptr(t, dtype=None):
+    if t is None:
+        return None
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if not t.is_cuda or not t.is_contiguous():
+        raise TypeError("expected a contiguous device tensor")
+    return t.data_ptr()
+
+
+def config(format=CK_FMT_CSR, algorithm=CK_ALG_VECTOR, lanes=4):
+    return Config(format, algorithm, lanes, 0)
+
+
+def config_from_id(i):
+    c = Config()
+    _check(lib().ck_config_from_id(i, C.byref(c)))
+    return c
+
+
+def config_id(c):
+    return int(lib().ck_config_id(C.byref(c)))
+
+
+def kernel_name(c, fp32=False):
+    buf = C.create_string_buffer(128)
+    _check(lib().ck_kernel_name(C.byref(c), int(fp32), buf, 128))
+    return buf.value.decode()
+
+
+def spmv_create(rp, col, val, ncols=None, keep_fp32=False, stream=None):
+    """Copy a device CSR (int32 rowptr/col, float64 val) into a new handle."""
+    import torch
+    n = rp.numel() - 1
+    h = _vp()
+    _check(lib().spmv_create(C.byref(h), n, n if ncols is None else ncols, col.numel(),
+                             _ptr(rp, torch.int32), _ptr(col, torch.int32),
+                             _ptr(val, torch.float64), CK_KEEP_FP32 if keep_fp32 else 0,
+                             _stream(stream)))
+    return h.value
+
+
+def spmv_destroy(h):
+    lib().spmv_destroy(h)
+
+
+def spmv_features(h, stream=None):
+    f = Features()
+    _check(lib().spmv_features(h, C.byref(f), _stream(stream)))
+    return f
+
+
+def spmv_select(features, model_path=None):
+    c = Config()
+    mp = model_path.encode() if model_path else None
+    _check(lib().spmv_select(C.byref(features), mp, C.byref(c)))
+    return c
+
+
+def select_stages(features, model_path=None):
+    st = (_i32 * 3)()
+    mp = model_path.encode() if model_path else None
+    _check(lib().ck_select_stages(C.byref(features), mp, st))
+    return list(st)
+
+
+def default_config(h):
+    c = Config()
+    _check(lib().ck_default_config(h, C.byref(c)))
+    return c
+
+
+def spmv_convert(h, cfg, stream=None):
+    _check(lib().spmv_convert(h, C.byref(cfg), _stream(stream)))
+
+
+def set_active(h, cfg):
+    _check(lib().ck_set_active(h, C.byref(cfg)))
+
+
+def get_active(h):
+    c = Config()
+    _check(lib().ck_get_active(h, C.byref(c)))
+    return c
+
+
+def spmv_apply(h, x, y, alpha=1.0, beta=0.0, cfg=None, stream=None):
+    import torch
+    _check(lib().spmv_apply(h, C.byref(cfg) if cfg is not None else None, float(alpha),
+                            _ptr(x, torch.float64), float(beta), _ptr(y, torch.float64),
+                            _stream(stream)))
+
+
+def spmv_apply_f32(h, x, y, alpha=1.0, beta=0.0, cfg=None, stream=None):
+    import torch
+    _check(lib().spmv_apply_f32(h, C.byref(cfg) if cfg is not None else None, float(alpha),
+                                _ptr(x, torch.float32), float(beta), _ptr(y, torch.float32),
+                                _stream(stream)))
+
+
+def _opts(tol, max_iter, restart, precision, async_, check_every, cfg):
+    o = SolveOpts()
+    o.tol = tol
+    o.max_iter = max_iter
+    o.restart = restart
+    o.precision = precision
+    o.async_ = int(async_)
+    o.check_every = check_every
+    if cfg is not None:
+        o.use_config = 1
+        o.config = cfg
+    return o
+
+
+def _solve(fn, h, b, x, tol, max_iter, restart, precision, async_, check_every, cfg, stream,
+           raise_on_error):
+    import torch
+    o = _opts(tol, max_iter, restart, precision, async_, check_every, cfg)
+    r = SolveResult()
+    st = fn(h, _ptr(b, torch.float64), _ptr(x, torch.float64), C.byref(o), C.byref(r),
+            _stream(stream))
+    if st not in (CK_OK, CK_E_NOT_CONVERGED, CK_E_BREAKDOWN) or (raise_on_error and st != CK_OK):
+        _check(st)
+    return r.as_dict()
+
+
+def cg_solve(h, b, x, tol=1e-10, max_iter=100000, precision=CK_PREC_FP64, async_=False,
+             check_every=8, config=None, stream=None, raise_on_error=False):
+    """x holds x0 on entry and the solution on return; returns the result record."""
+    return _solve(lib().cg_solve, h, b, x, tol, max_iter, 0, precision, async_, check_every,
+                  config, stream, raise_on_error)
+
+
+def gmres_solve(h, b, x, tol=1e-10, max_iter=100000, restart=30, precision=CK_PREC_FP64,
+                async_=False, check_every=8, config=None, stream=None, raise_on_error=False):
+    return _solve(lib().gmres_solve, h, b, x, tol, max_iter, restart, precision, async_,
+                  check_every, config, stream, raise_on_error)
+
+
+def export_ell(h, stream=None):
+    import torch
+    K, pitch = _i64(), _i64()
+    _check(lib().ck_export_ell(h, None, None, C.byref(K), C.byref(pitch), _stream(stream)))
+    ec = torch.empty(K.value * pitch.value, dtype=torch.int32, device="cuda")
+    ev = torch.empty(K.value * pitch.value, dtype=torch.float64, device="cuda")
+    _check(lib().ck_export_ell(h, _ptr(ec), _ptr(ev), C.byref(K), C.byref(pitch),
+                               _stream(stream)))
+    return K.value, pitch.value, ec, ev
+
+
+def export_coo_rows(h, nnz, stream=None):
+    import torch
+    row = torch.empty(nnz, dtype=torch.int32, device="cuda")
+    _check(lib().ck_export_coo_rows(h, _ptr(row) if nnz else None, _stream(stream)))
+    return row
+
+
+def dot(x, y, out, stream=None):
+    import torch
+    _check(lib().ck_dot(x.numel(), _ptr(x, torch.float64), _ptr(y, torch.float64),
+                        _ptr(out, torch.float64), _stream(stream)))
+
+
+def spmv_bytes(h, fp32=False, beta_nonzero=False):
+    return int(lib().ck_spmv_bytes(h, int(fp32), int(beta_nonzero)))
+
+
+class Matrix:
+    """Owns a handle; a convenience wrapper over the C calls."""
+
+    def __init__(self, rp, col, val, ncols=None, keep_fp32=False, stream=None):
+        self.n = rp.numel() - 1
+        self.ncols = self.n if ncols is None else ncols
+        self.nnz = col.numel()
+        self.handle = spmv_create(rp, col, val, ncols, keep_fp32, stream)
+
+    @classmethod
+    def from_csr(cls, A, keep_fp32=False, device="cuda", stream=None):
+        import torch
+        rp = torch.from_numpy(A.rp).to(device)
+        col = torch.from_numpy(A.col).to(device)
+        val = torch.from_numpy(A.val).to(device)
+        return cls(rp, col, val, A.ncols, keep_fp32, stream)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            spmv_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

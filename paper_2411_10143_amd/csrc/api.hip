@@ -1,0 +1,405 @@
+// C-ABI entry points for the matrix store, features, prediction, conversion
+// and SpMV (declared in include/caskrylov.h).
+#include <cstdarg>
+#include <cstring>
+#include <limits>
+
+#include "matrix.hpp"
+#include "predictor.hpp"
+#include "solvers.hpp"
+
+namespace ck {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string &msg) { g_last_error = msg; }
+
+ck_status fail(ck_status st, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+// features.hip
+ck_status launch_validate(int64_t n, int64_t ncols, int64_t nnz, const int *rp, const int *col,
+                          unsigned *bad, hipStream_t s);
+int64_t features_scratch_bytes(int64_t n, int64_t ncols);
+ck_status launch_features(const ck_matrix &M, void *scratch, hipStream_t s);
+void features_from_acc(const void *acc_host, const ck_matrix &M, int64_t *out28);
+int64_t features_acc_offset(int64_t n, int64_t ncols);
+size_t features_acc_size();
+ck_status launch_row_max(int64_t n, const int *rp, unsigned long long *out, hipStream_t s);
+ck_status launch_to_ell(const ck_matrix &M, int64_t K, int64_t pitch, int *ecol, double *evl,
+                        float *evl32, hipStream_t s);
+ck_status launch_to_coo(const ck_matrix &M, int *row, hipStream_t s);
+
+template <typename T>
+static ck_status dev_alloc(T **p, int64_t count) {
+    *p = nullptr;
+    const size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(CK_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return CK_OK;
+}
+
+static void release(ck_matrix *M) {
+    if (!M)
+        return;
+    (void)hipFree(M->rp);
+    (void)hipFree(M->col);
+    (void)hipFree(M->val);
+    (void)hipFree(M->val32);
+    (void)hipFree(M->ell_col);
+    (void)hipFree(M->ell_val);
+    (void)hipFree(M->ell_val32);
+    (void)hipFree(M->coo_row);
+    delete M;
+}
+
+// Exact integer features (GPU) plus host-derived floating-point features.
+ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s) {
+    std::memset(&F, 0, sizeof F);
+    const int64_t bytes = features_scratch_bytes(M.n, M.ncols);
+    void *scratch = nullptr;
+    CK_HIP(hipMallocAsync(&scratch, (size_t)bytes, s));
+    ck_status st = launch_features(M, scratch, s);
+    char acc[512];
+    if (st == CK_OK) {
+        const hipError_t e = hipMemcpyAsync(acc, (char *)scratch + features_acc_offset(M.n, M.ncols),
+                                            features_acc_size(), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess)
+            st = fail(CK_E_HIP, "feature copy failed: %s", hipGetErrorString(e));
+    }
+    const hipError_t ef = hipFreeAsync(scratch, s);
+    const hipError_t es = hipStreamSynchronize(s);
+    CK_TRY(st);
+    if (ef != hipSuccess || es != hipSuccess)
+        return fail(CK_E_HIP, "feature pass failed: %s",
+                    hipGetErrorString(es != hipSuccess ? es : ef));
+    int64_t ints[28];
+    features_from_acc(acc, M, ints);
+    std::memcpy(&F, ints, sizeof ints);
+    derive_features(F);
+    M.max_row = F.max_r;
+    return CK_OK;
+}
+
+// Builds the ELL or COO copy a configuration needs (idempotent).
+ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
+    if (!config_valid(c))
+        return fail(CK_E_INVALID, "invalid SpMV configuration");
+    if (c.format == CK_FMT_CSR)
+        return CK_OK;
+    std::lock_guard<std::mutex> lk(M.mu);
+    if (c.format == CK_FMT_COO) {
+        if (M.has_coo.load())
+            return CK_OK;
+        CK_TRY(dev_alloc(&M.coo_row, M.nnz));
+        CK_TRY(launch_to_coo(M, M.coo_row, s));
+        M.has_coo.store(true);
+        return CK_OK;
+    }
+    if (M.has_ell.load())
+        return CK_OK;
+    if (M.max_row < 0) {
+        unsigned long long *d = nullptr;
+        unsigned long long h = 0;
+        CK_HIP(hipMallocAsync((void **)&d, sizeof h, s));
+        CK_TRY(launch_fill<int>(2, (int *)d, 0, s));
+        CK_TRY(launch_row_max(M.n, M.rp, d, s));
+        CK_HIP(hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, s));
+        CK_HIP(hipFreeAsync(d, s));
+        CK_HIP(hipStreamSynchronize(s));
+        M.max_row = (int64_t)h;
+    }
+    const int64_t K = M.max_row;
+    const int64_t pitch = ceil_div(M.n, 64) * 64;
+    if (K * pitch > 8 * M.nnz)
+        return fail(CK_E_UNSUPPORTED, "ELL refused: %lld slots for %lld stored entries",
+                    (long long)(K * pitch), (long long)M.nnz);
+    CK_TRY(dev_alloc(&M.ell_col, K * pitch));
+    CK_TRY(dev_alloc(&M.ell_val, K * pitch));
+    if (M.val32)
+        CK_TRY(dev_alloc(&M.ell_val32, K * pitch));
+    CK_TRY(launch_to_ell(M, K, pitch, M.ell_col, M.ell_val, M.ell_val32, s));
+    M.ell_K = K;
+    M.ell_pitch = pitch;
+    M.has_ell.store(true);
+    return CK_OK;
+}
+
+}  // namespace ck
+
+using namespace ck;
+
+extern "C" {
+
+const char *ck_last_error(void) { return g_last_error.c_str(); }
+
+int32_t ck_config_id(const ck_config *c) {
+    if (!c || !config_valid(*c))
+        return -1;
+    if (c->format == CK_FMT_ELL)
+        return 9;
+    if (c->format == CK_FMT_COO)
+        return 10;
+    if (c->algorithm == CK_ALG_SCALAR)
+        return 7;
+    if (c->algorithm == CK_ALG_MERGE)
+        return 8;
+    int idx = 0;
+    while ((1 << idx) < c->lanes)
+        ++idx;
+    return idx;
+}
+
+ck_status ck_config_from_id(int32_t id, ck_config *out) {
+    if (!out || id < 0 || id >= CK_NUM_CONFIGS)
+        return fail(CK_E_INVALID, "configuration id must be in [0, 10]");
+    if (id <= 6)
+        *out = ck_config{CK_FMT_CSR, CK_ALG_VECTOR, 1 << id, 0};
+    else if (id == 7)
+        *out = ck_config{CK_FMT_CSR, CK_ALG_SCALAR, 0, 0};
+    else if (id == 8)
+        *out = ck_config{CK_FMT_CSR, CK_ALG_MERGE, 0, 0};
+    else if (id == 9)
+        *out = ck_config{CK_FMT_ELL, 0, 0, 0};
+    else
+        *out = ck_config{CK_FMT_COO, 0, 0, 0};
+    return CK_OK;
+}
+
+ck_status ck_kernel_name(const ck_config *cfg, int32_t fp32, char *buf, size_t cap) {
+    if (!cfg || !buf || cap == 0 || !config_valid(*cfg))
+        return fail(CK_E_INVALID, "bad arguments");
+    snprintf(buf, cap, "%s", kernel_name(*cfg, fp32 != 0));
+    return CK_OK;
+}
+
+ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
+                      const int32_t *d_rowptr, const int32_t *d_col, const double *d_val,
+                      uint32_t flags, hipStream_t s) {
+    if (!out)
+        return fail(CK_E_INVALID, "out is NULL");
+    *out = nullptr;
+    const int64_t lim = std::numeric_limits<int32_t>::max() - 4096;
+    if (nrows < 0 || ncols < 0 || nnz < 0 || nrows > lim || ncols > lim || nnz > lim)
+        return fail(CK_E_INVALID, "sizes must be non-negative and fit int32 indexing");
+    if (!d_rowptr || (nnz > 0 && (!d_col || !d_val)))
+        return fail(CK_E_INVALID, "NULL CSR array");
+    if (flags & ~CK_KEEP_FP32)
+        return fail(CK_E_INVALID, "unknown flags");
+    ck_matrix *M = new ck_matrix();
+    M->n = nrows;
+    M->ncols = ncols;
+    M->nnz = nnz;
+    M->flags = flags;
+    (void)hipGetDevice(&M->device);
+    ck_status st = CK_OK;
+    unsigned *bad = nullptr;
+    unsigned hbad = 0;
+    do {
+        if ((st = dev_alloc(&M->rp, nrows + 1)) != CK_OK) break;
+        if ((st = dev_alloc(&M->col, nnz)) != CK_OK) break;
+        if ((st = dev_alloc(&M->val, nnz)) != CK_OK) break;
+        hipError_t e = hipMemcpyAsync(M->rp, d_rowptr, sizeof(int32_t) * (nrows + 1),
+                                      hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && nnz > 0)
+            e = hipMemcpyAsync(M->col, d_col, sizeof(int32_t) * nnz, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess && nnz > 0)
+            e = hipMemcpyAsync(M->val, d_val, sizeof(double) * nnz, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) {
+            st = fail(CK_E_HIP, "copy of the CSR arrays failed: %s", hipGetErrorString(e));
+            break;
+        }
+        if (flags & CK_KEEP_FP32) {
+            if ((st = dev_alloc(&M->val32, nnz)) != CK_OK) break;
+            if (nnz > 0 && (st = launch_copy<float, double>(nnz, M->val32, M->val, nullptr, s)) != CK_OK)
+                break;
+        }
+        if ((st = dev_alloc(&bad, 1)) != CK_OK) break;
+        if ((st = launch_fill<int>(1, (int *)bad, 0, s)) != CK_OK) break;
+        if ((st = launch_validate(nrows, ncols, nnz, M->rp, M->col, bad, s)) != CK_OK) break;
+        e = hipMemcpyAsync(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            st = fail(CK_E_HIP, "validation failed: %s", hipGetErrorString(e));
+            break;
+        }
+        if (hbad) {
+            st = fail(CK_E_INVALID, "malformed CSR (code %u): rowptr must start at 0, be "
+                      "nondecreasing and end at nnz; columns in range and strictly increasing",
+                      hbad);
+            break;
+        }
+    } while (false);
+    (void)hipFree(bad);
+    if (st != CK_OK) {
+        release(M);
+        return st;
+    }
+    M->active = default_config(nrows, nnz);
+    *out = M;
+    return CK_OK;
+}
+
+void spmv_destroy(ck_handle h) { release(h); }
+
+ck_status spmv_features(ck_handle h, ck_features *out, hipStream_t s) {
+    if (!h || !out)
+        return fail(CK_E_INVALID, "NULL argument");
+    return compute_features(*h, *out, s);
+}
+
+ck_status ck_select_stages(const ck_features *f, const char *model_path, int32_t stage[3]) {
+    if (!f || !stage)
+        return fail(CK_E_INVALID, "NULL argument");
+    std::string err;
+    const Cascade *C = load_cascade(model_path, err);
+    if (!C)
+        return fail(CK_E_INVALID, "%s", err.c_str());
+    double in[kNumModelFeatures];
+    model_inputs(*f, in);
+    stage[0] = C->tree[0].eval(in);
+    stage[1] = -1;
+    stage[2] = -1;
+    if (stage[0] == CK_FMT_CSR) {
+        stage[1] = C->tree[1].eval(in);
+        if (stage[1] == CK_ALG_VECTOR)
+            stage[2] = C->tree[2].eval(in);
+    }
+    if (stage[0] < 0 || stage[0] > 2 || stage[1] > 2 || stage[2] > 6)
+        return fail(CK_E_INVALID, "cascade model produced an unknown class");
+    return CK_OK;
+}
+
+ck_status spmv_select(const ck_features *f, const char *model_path, ck_config *out) {
+    if (!f || !out)
+        return fail(CK_E_INVALID, "NULL argument");
+    int32_t st[3];
+    CK_TRY(ck_select_stages(f, model_path, st));
+    ck_config c = default_config(f->nrows, f->nnz);
+    for (int t = 0; t < 3 && st[t] >= 0; ++t)
+        c = stage_config(t, st[t], c);
+    *out = c;
+    return CK_OK;
+}
+
+ck_status ck_default_config(ck_handle h, ck_config *out) {
+    if (!h || !out)
+        return fail(CK_E_INVALID, "NULL argument");
+    *out = default_config(h->n, h->nnz);
+    return CK_OK;
+}
+
+ck_status spmv_convert(ck_handle h, const ck_config *cfg, hipStream_t s) {
+    if (!h || !cfg)
+        return fail(CK_E_INVALID, "NULL argument");
+    return convert_format(*h, *cfg, s);
+}
+
+ck_status ck_set_active(ck_handle h, const ck_config *cfg) {
+    if (!h || !cfg || !config_valid(*cfg))
+        return fail(CK_E_INVALID, "bad configuration");
+    if ((cfg->format == CK_FMT_ELL && !h->has_ell.load()) ||
+        (cfg->format == CK_FMT_COO && !h->has_coo.load()))
+        return fail(CK_E_INVALID, "format not converted yet");
+    std::lock_guard<std::mutex> lk(h->mu);
+    h->active = *cfg;
+    return CK_OK;
+}
+
+ck_status ck_get_active(ck_handle h, ck_config *out) {
+    if (!h || !out)
+        return fail(CK_E_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(h->mu);
+    *out = h->active;
+    return CK_OK;
+}
+
+static ck_config active_of(ck_handle h) {
+    std::lock_guard<std::mutex> lk(h->mu);
+    return h->active;
+}
+
+ck_status spmv_apply(ck_handle h, const ck_config *cfg, double alpha, const double *d_x,
+                     double beta, double *d_y, hipStream_t s) {
+    if (!h || (h->n > 0 && !d_y) || (h->ncols > 0 && !d_x))
+        return fail(CK_E_INVALID, "NULL argument");
+    SpmvArgs<double> a;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.x = d_x;
+    a.y = d_y;
+    return launch_spmv<double>(*h, cfg ? *cfg : active_of(h), a, s);
+}
+
+ck_status spmv_apply_f32(ck_handle h, const ck_config *cfg, float alpha, const float *d_x,
+                         float beta, float *d_y, hipStream_t s) {
+    if (!h || (h->n > 0 && !d_y) || (h->ncols > 0 && !d_x))
+        return fail(CK_E_INVALID, "NULL argument");
+    SpmvArgs<float> a;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.x = d_x;
+    a.y = d_y;
+    return launch_spmv<float>(*h, cfg ? *cfg : active_of(h), a, s);
+}
+
+ck_status ck_export_ell(ck_handle h, int32_t *d_col, double *d_val, int64_t *K, int64_t *pitch,
+                        hipStream_t s) {
+    if (!h || !K || !pitch)
+        return fail(CK_E_INVALID, "NULL argument");
+    if (!h->has_ell.load())
+        return fail(CK_E_INVALID, "matrix has no ELL copy");
+    *K = h->ell_K;
+    *pitch = h->ell_pitch;
+    const size_t cnt = (size_t)(h->ell_K * h->ell_pitch);
+    if (d_col && cnt)
+        CK_HIP(hipMemcpyAsync(d_col, h->ell_col, cnt * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (d_val && cnt)
+        CK_HIP(hipMemcpyAsync(d_val, h->ell_val, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return CK_OK;
+}
+
+ck_status ck_export_coo_rows(ck_handle h, int32_t *d_row, hipStream_t s) {
+    if (!h || (!d_row && h->nnz > 0))
+        return fail(CK_E_INVALID, "NULL argument");
+    if (!h->has_coo.load())
+        return fail(CK_E_INVALID, "matrix has no COO copy");
+    if (h->nnz)
+        CK_HIP(hipMemcpyAsync(d_row, h->coo_row, h->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    return CK_OK;
+}
+
+ck_status ck_dot(int64_t n, const double *d_x, const double *d_y, double *d_out, hipStream_t s) {
+    if (n < 0 || !d_out || (n > 0 && (!d_x || !d_y)))
+        return fail(CK_E_INVALID, "bad arguments");
+    void *ws = nullptr;
+    CK_HIP(hipMallocAsync(&ws, 1024 * sizeof(double) + 256, s));
+    unsigned *counter = (unsigned *)((char *)ws + 1024 * sizeof(double));
+    ck_status st = launch_fill<int>(1, (int *)counter, 0, s);
+    if (st == CK_OK)
+        st = launch_dot(n, d_x, d_y, (double *)ws, counter, d_out, s);
+    CK_HIP(hipFreeAsync(ws, s));
+    return st;
+}
+
+int64_t ck_spmv_bytes(ck_handle h, int32_t fp32, int32_t beta_nonzero) {
+    if (!h)
+        return -1;
+    const int64_t sz = fp32 ? 4 : 8;
+    return h->nnz * (sz + 4) + 4 * (h->n + 1) + sz * h->ncols + sz * h->n +
+           (beta_nonzero ? sz * h->n : 0);
+}
+
+}  // extern "C"

@@ -1,0 +1,381 @@
+// GMRES(m) kernels (the solver of the paper's evaluation, Section IV).
+//
+// One Arnoldi step j after the SpMV w = A v_j (written straight into basis
+// column j+1) is classical Gram-Schmidt applied twice, in three fused passes
+// over the basis:
+//   pass 1: h1 = V_j^T w
+//   pass 2: w -= V_j h1, and in the same sweep h2 = V_j^T w
+//   pass 3: w -= V_j h2, and ||w||^2; the last block then forms column j of
+//           the Hessenberg matrix (h1 + h2, ||w||), applies the previous
+//           Givens rotations, makes rotation j, updates the residual estimate
+//           |g_{j+1}| and decides whether the cycle stops.
+//   scale : v_{j+1} = w / h_{j+1,j}
+// Each pass streams the j+1 basis columns once; the per-column dot products
+// are reduced in fixed order (wave butterfly, then block order in the last
+// block), so results are deterministic.  The least-squares solve and the
+// solution update close the cycle on the device; nothing returns to the host
+// inside a cycle.
+#include "solvers.hpp"
+
+using ck::GmDev;
+
+namespace {
+
+constexpr int kGmMaxBlocks = 1024;
+
+// partials[c*G + b] = block b's sum of acc[c]  (c < ncols)
+template <typename T, int NC>
+__device__ __forceinline__ void block_cols(const T (&acc)[NC], int ncols, T *partials, int64_t b,
+                                           int64_t G) {
+    __shared__ T lds[4][NC];
+    const int w = threadIdx.x / 64, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        if (c < ncols) {
+            const T v = ck::wave_sum(acc[c]);
+            if (lane == 0)
+                lds[w][c] = v;
+        }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < ncols) {
+        const int c = threadIdx.x;
+        partials[c * G + b] = (lds[0][c] + lds[1][c]) + (lds[2][c] + lds[3][c]);
+    }
+}
+
+// out[c] = sum_b partials[c*G + b], wave w handles columns w, w+4, ...
+template <typename T>
+__device__ __forceinline__ void reduce_cols(const T *partials, int64_t G, int ncols, T *out) {
+    const int w = threadIdx.x / 64, lane = threadIdx.x & 63;
+    for (int c = w; c < ncols; c += 4) {
+        T s = 0;
+        for (int64_t b = lane; b < G; b += 64)
+            s += __builtin_nontemporal_load(&partials[c * G + b]);
+        s = ck::wave_sum(s);
+        if (lane == 0)
+            out[c] = s;
+    }
+}
+
+}  // namespace
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void gm_pass1(int64_t n, int64_t G, int ncols,
+                                                const T *__restrict__ V, int64_t ldv,
+                                                const T *__restrict__ w,
+                                                T *__restrict__ partials, GmDev<T> *st) {
+    if (st->halt)
+        return;
+    const int64_t b = blockIdx.x;
+    T acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        acc[c] = 0;
+    for (int64_t i = b * 256 + threadIdx.x; i < n; i += G * 256) {
+        const T wi = w[i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < ncols)
+                acc[c] += V[c * ldv + i] * wi;
+    }
+    block_cols<T, NC>(acc, ncols, partials, b, G);
+    if (ck::arrive_last(&st->counter[0], (unsigned)G))
+        reduce_cols(partials, G, ncols, st->h1);
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void gm_pass2(int64_t n, int64_t G, int ncols,
+                                                const T *__restrict__ V, int64_t ldv,
+                                                T *__restrict__ w, T *__restrict__ partials,
+                                                GmDev<T> *st) {
+    if (st->halt)
+        return;
+    const int64_t b = blockIdx.x;
+    T h[NC], acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        h[c] = c < ncols ? st->h1[c] : T(0);
+        acc[c] = 0;
+    }
+    for (int64_t i = b * 256 + threadIdx.x; i < n; i += G * 256) {
+        T vv[NC];
+        T wi = w[i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < ncols) {
+                vv[c] = V[c * ldv + i];
+                wi -= h[c] * vv[c];
+            }
+        w[i] = wi;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < ncols)
+                acc[c] += vv[c] * wi;
+    }
+    block_cols<T, NC>(acc, ncols, partials, b, G);
+    if (ck::arrive_last(&st->counter[1], (unsigned)G))
+        reduce_cols(partials, G, ncols, st->h2);
+}
+
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void gm_pass3(int64_t n, int64_t G, int ncols,
+                                                const T *__restrict__ V, int64_t ldv,
+                                                T *__restrict__ w, T *__restrict__ partials,
+                                                GmDev<T> *st) {
+    __shared__ T lds[4];
+    if (st->halt)
+        return;
+    const int64_t b = blockIdx.x;
+    T h[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        h[c] = c < ncols ? st->h2[c] : T(0);
+    T s = 0;
+    for (int64_t i = b * 256 + threadIdx.x; i < n; i += G * 256) {
+        T wi = w[i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            if (c < ncols)
+                wi -= h[c] * V[c * ldv + i];
+        w[i] = wi;
+        s += wi * wi;
+    }
+    s = ck::block_sum(s, lds);
+    if (threadIdx.x == 0)
+        partials[b] = s;
+    if (!ck::arrive_last(&st->counter[2], (unsigned)G))
+        return;
+    const T nrm2 = ck::sum_partials(partials, G, lds);
+    if (threadIdx.x != 0)
+        return;
+    // Hessenberg column j, previous rotations, new rotation, residual estimate
+    const int m = st->m;
+    const int j = st->j;
+    T *Hj = st->H + (int64_t)j * (m + 1);
+    const T hn = sqrt(nrm2);
+    for (int c = 0; c <= j; ++c)
+        Hj[c] = st->h1[c] + st->h2[c];
+    Hj[j + 1] = hn;
+    for (int i = 0; i < j; ++i) {
+        const T a = Hj[i], c2 = Hj[i + 1];
+        Hj[i] = st->cs[i] * a + st->sn[i] * c2;
+        Hj[i + 1] = -st->sn[i] * a + st->cs[i] * c2;
+    }
+    const T a = Hj[j], c2 = Hj[j + 1];
+    const T d = sqrt(a * a + c2 * c2);
+    if (d == T(0)) {
+        st->final_state = ck::BREAKDOWN;
+        st->cycle_stop = ck::BREAKDOWN;
+        st->halt = 1;
+        return;
+    }
+    st->cs[j] = a / d;
+    st->sn[j] = c2 / d;
+    Hj[j] = d;
+    Hj[j + 1] = 0;
+    st->g[j + 1] = -st->sn[j] * st->g[j];
+    st->g[j] = st->cs[j] * st->g[j];
+    st->j = j + 1;
+    st->iter += 1;
+    st->relres = fabs((double)st->g[j + 1]) / st->bnorm;
+    int stop = ck::RUN;
+    if (st->relres <= st->tol)
+        stop = ck::CONVERGED;
+    else if (hn == T(0))
+        stop = ck::BREAKDOWN;
+    else if (st->iter >= st->max_iter)
+        stop = ck::BUDGET;
+    else if (j + 1 == m)
+        stop = ck::FULL;
+    st->cycle_stop = stop;
+    st->halt = stop != ck::RUN;
+    st->inv = hn > T(0) ? T(1) / hn : T(0);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gm_scale(int64_t n, T *__restrict__ w, GmDev<T> *st) {
+    if (st->halt)
+        return;
+    const T inv = st->inv;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256)
+        w[i] *= inv;
+}
+
+// Cycle start: beta = ||r|| (FP64), true-residual convergence test, g = beta e1.
+template <typename T>
+__global__ __launch_bounds__(256) void gm_start_norm(int64_t n, int64_t G,
+                                                     const double *__restrict__ r,
+                                                     double *__restrict__ partials,
+                                                     GmDev<T> *st) {
+    __shared__ double lds[4];
+    if (st->final_state != ck::RUN)
+        return;
+    const int64_t b = blockIdx.x;
+    double s = 0;
+    for (int64_t i = b * 256 + threadIdx.x; i < n; i += G * 256)
+        s += r[i] * r[i];
+    s = ck::block_sum(s, lds);
+    if (threadIdx.x == 0)
+        partials[b] = s;
+    if (!ck::arrive_last(&st->counter[3], (unsigned)G))
+        return;
+    const double tot = ck::sum_partials(partials, G, lds);
+    if (threadIdx.x != 0)
+        return;
+    const double beta = sqrt(tot);
+    st->beta = beta;
+    st->relres = beta / st->bnorm;
+    if (st->relres <= st->tol) {
+        st->final_state = ck::CONVERGED;
+        st->halt = 1;
+        return;
+    }
+    if (st->iter >= st->max_iter) {
+        st->final_state = ck::BUDGET;
+        st->halt = 1;
+        return;
+    }
+    st->inv_beta = 1.0 / beta;
+    st->j = 0;
+    st->cycle_stop = ck::RUN;
+    st->halt = 0;
+    st->cycles += 1;
+    st->g[0] = (T)beta;
+    for (int t = 1; t <= st->m; ++t)
+        st->g[t] = 0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void gm_start_v0(int64_t n, T *__restrict__ v0,
+                                                   const double *__restrict__ r,
+                                                   const GmDev<T> *st) {
+    if (st->halt)
+        return;
+    const double inv = st->inv_beta;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256)
+        v0[i] = (T)(r[i] * inv);
+}
+
+// Cycle end: back substitution R y = g over the k = j columns formed.
+template <typename T>
+__global__ void gm_solve_y(GmDev<T> *st) {
+    if (st->final_state != ck::RUN || threadIdx.x != 0)
+        return;
+    const int m = st->m, k = st->j;
+    for (int i = k - 1; i >= 0; --i) {
+        T s = st->g[i];
+        for (int t = i + 1; t < k; ++t)
+            s -= st->H[(int64_t)t * (m + 1) + i] * st->y[t];
+        st->y[i] = s / st->H[(int64_t)i * (m + 1) + i];
+    }
+}
+
+// x += V_k y, accumulated in FP64 (the basis may be FP32).
+template <typename T>
+__global__ __launch_bounds__(256) void gm_update_x(int64_t n, double *__restrict__ x,
+                                                   const T *__restrict__ V, int64_t ldv,
+                                                   const GmDev<T> *st) {
+    __shared__ double ys[ck::kMaxRestart];
+    if (st->final_state != ck::RUN)
+        return;
+    const int k = st->j;
+    for (int c = threadIdx.x; c < k; c += 256)
+        ys[c] = (double)st->y[c];
+    __syncthreads();
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
+        double acc = 0;
+        for (int c = 0; c < k; ++c)
+            acc += ys[c] * (double)V[c * ldv + i];
+        x[i] += acc;
+    }
+}
+
+namespace ck {
+
+int64_t gm_blocks(int64_t n) {
+    int64_t g = ceil_div(n, 2048);
+    if (g < 1)
+        g = 1;
+    return g < kGmMaxBlocks ? g : kGmMaxBlocks;
+}
+
+static int64_t gm_stream_grid(int64_t n) {
+    int64_t g = ceil_div(n, 1024);
+    if (g < 1)
+        g = 1;
+    return g < 8192 ? g : 8192;
+}
+
+template <typename T>
+ck_status launch_gm_cycle_start(int64_t n, const double *r64, T *v0, double *partials64,
+                                GmDev<T> *st, hipStream_t s) {
+    const int64_t G = gm_blocks(n);
+    hipLaunchKernelGGL((gm_start_norm<T>), dim3(G), dim3(256), 0, s, n, G, r64, partials64, st);
+    hipLaunchKernelGGL((gm_start_v0<T>), dim3(gm_stream_grid(n)), dim3(256), 0, s, n, v0, r64, st);
+    CK_HIP(hipGetLastError());
+    return CK_OK;
+}
+
+template <typename T, int NC>
+static void arnoldi_nc(int64_t n, int64_t G, int ncols, T *V, int64_t ldv, T *w, T *partials,
+                       GmDev<T> *st, hipStream_t s) {
+    hipLaunchKernelGGL((gm_pass1<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w,
+                       partials, st);
+    hipLaunchKernelGGL((gm_pass2<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w,
+                       partials, st);
+    hipLaunchKernelGGL((gm_pass3<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w,
+                       partials, st);
+}
+
+// Orthogonalisation and normalisation of w = V[:, j+1] (the SpMV output)
+// against columns 0..j.
+template <typename T>
+ck_status launch_gm_arnoldi(int64_t n, int j, T *V, int64_t ldv, T *partials, GmDev<T> *st,
+                            hipStream_t s) {
+    const int64_t G = gm_blocks(n);
+    const int ncols = j + 1;
+    T *w = V + (int64_t)(j + 1) * ldv;
+    if (ncols <= 8)
+        arnoldi_nc<T, 8>(n, G, ncols, V, ldv, w, partials, st, s);
+    else if (ncols <= 16)
+        arnoldi_nc<T, 16>(n, G, ncols, V, ldv, w, partials, st, s);
+    else if (ncols <= 24)
+        arnoldi_nc<T, 24>(n, G, ncols, V, ldv, w, partials, st, s);
+    else if (ncols <= 32)
+        arnoldi_nc<T, 32>(n, G, ncols, V, ldv, w, partials, st, s);
+    else if (ncols <= 48)
+        arnoldi_nc<T, 48>(n, G, ncols, V, ldv, w, partials, st, s);
+    else if (ncols <= 64)
+        arnoldi_nc<T, 64>(n, G, ncols, V, ldv, w, partials, st, s);
+    else
+        return fail(CK_E_INVALID, "restart length above %d", kMaxRestart);
+    hipLaunchKernelGGL((gm_scale<T>), dim3(gm_stream_grid(n)), dim3(256), 0, s, n, w, st);
+    CK_HIP(hipGetLastError());
+    return CK_OK;
+}
+
+template <typename T>
+ck_status launch_gm_cycle_end(int64_t n, double *x, const T *V, int64_t ldv, GmDev<T> *st,
+                              hipStream_t s) {
+    hipLaunchKernelGGL((gm_solve_y<T>), dim3(1), dim3(64), 0, s, st);
+    hipLaunchKernelGGL((gm_update_x<T>), dim3(gm_stream_grid(n)), dim3(256), 0, s, n, x, V, ldv,
+                       st);
+    CK_HIP(hipGetLastError());
+    return CK_OK;
+}
+
+#define CK_GM_INST(T)                                                                          \
+    template ck_status launch_gm_cycle_start<T>(int64_t, const double *, T *, double *,        \
+                                                GmDev<T> *, hipStream_t);                      \
+    template ck_status launch_gm_arnoldi<T>(int64_t, int, T *, int64_t, T *, GmDev<T> *,       \
+                                            hipStream_t);                                      \
+    template ck_status launch_gm_cycle_end<T>(int64_t, double *, const T *, int64_t,           \
+                                              GmDev<T> *, hipStream_t);
+CK_GM_INST(double)
+CK_GM_INST(float)
+
+}  // namespace ck

@@ -1,0 +1,91 @@
+// Device-resident solver state and the reduction helpers the fused Krylov
+// kernels share.  All scalar algebra of CG and GMRES stays on the GPU; the
+// host only enqueues work and polls a small status record.
+#pragma once
+
+#include "common.hpp"
+
+namespace ck {
+
+constexpr int kMaxRestart = 64;    // largest GMRES restart length m
+constexpr int kMaxPartials = 4096; // blocks that feed one last-block reduction
+
+// Run states shared by the solvers
+enum : int { RUN = 0, CONVERGED = 1, BREAKDOWN = 2, BUDGET = 3 };
+
+// CG (Hestenes-Stiefel) scalars.  `state` != RUN makes every iteration
+// kernel a no-op, so the host may enqueue ahead of convergence.
+template <typename T>
+struct CgDev {
+    T rho;            // r.r of the current residual
+    T sigma;          // p.Ap
+    T alpha, beta;
+    double bnorm;     // ||rhs|| of this (inner) solve
+    double tol;       // stop when sqrt(rho)/bnorm <= tol
+    double relres;    // last sqrt(rho)/bnorm
+    int state;
+    int iter;         // iterations completed
+    int max_iter;
+    int pad;
+    unsigned counter[4];   // arrival counters (always back to 0 after a launch)
+};
+
+// GMRES(m) cycle scalars (Givens form of the Hessenberg least squares).
+// cycle_stop ends the current cycle's Arnoldi steps; final_state ends the
+// whole solve.  H is column-major (m+1) x m.
+template <typename T>
+struct GmDev {
+    T H[(kMaxRestart + 1) * kMaxRestart];
+    T cs[kMaxRestart], sn[kMaxRestart];
+    T g[kMaxRestart + 1];
+    T y[kMaxRestart];
+    T h1[kMaxRestart + 1];      // first Gram-Schmidt pass
+    T h2[kMaxRestart + 1];      // second pass
+    T inv;                      // 1 / h_{j+1,j}
+    double beta;                // ||r|| at the cycle start (FP64 true residual)
+    double inv_beta;            // 1 / beta
+    double bnorm, tol, relres;  // relres: last estimate or true value
+    int m;
+    int j;                      // Arnoldi steps done in this cycle
+    int iter;                   // total Arnoldi steps
+    int max_iter;
+    int cycle_stop;             // RUN, CONVERGED (estimate), BREAKDOWN (happy), BUDGET
+    int final_state;            // RUN, CONVERGED, BREAKDOWN (singular), BUDGET
+    int cycles;
+    int halt;                   // 1 when cycle_stop or final_state is not RUN
+    unsigned counter[4];
+};
+
+constexpr int FULL = 4;         // cycle_stop value: m steps done
+
+// ---- last-block reductions --------------------------------------------------
+// Each block stores its partial(s), then the block that arrives last (an
+// integer counter; no floating-point atomics) sums all partials in block
+// order and finishes the scalar algebra.  The counter is reset by that block.
+__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned nblocks) {
+    __shared__ bool last;
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned prev = atomicAdd(counter, 1u);
+        last = (prev == nblocks - 1);
+        if (last)
+            atomicExch(counter, 0u);
+    }
+    __syncthreads();
+    if (last)
+        __threadfence();
+    return last;
+}
+
+// Fixed-order sum of n partials by the 256 threads of one block (valid in
+// thread 0 only).
+template <typename T>
+__device__ __forceinline__ T sum_partials(const T *p, int64_t n, T *lds4) {
+    T s = 0;
+    for (int64_t i = threadIdx.x; i < n; i += 256)
+        s += __builtin_nontemporal_load(&p[i]);
+    return block_sum(s, lds4);
+}
+
+}  // namespace ck

@@ -1,0 +1,75 @@
+// Device-resident matrix store and the internal launch interface of the SpMV
+// kernel family.
+#pragma once
+
+#include <atomic>
+#include <mutex>
+
+#include "krylov.hpp"
+
+struct ck_matrix {
+    int64_t n = 0, ncols = 0, nnz = 0;
+    int device = 0;
+    uint32_t flags = 0;
+    // CSR (always present)
+    int32_t *rp = nullptr;
+    int32_t *col = nullptr;
+    double *val = nullptr;
+    float *val32 = nullptr;           // CK_KEEP_FP32
+    // ELL (after conversion): column-major, slot s of row i at s*pitch + i
+    int32_t *ell_col = nullptr;
+    double *ell_val = nullptr;
+    float *ell_val32 = nullptr;
+    int64_t ell_K = 0, ell_pitch = 0;
+    std::atomic<bool> has_ell{false};
+    // COO (after conversion): row index per stored entry; col/val shared with CSR
+    int32_t *coo_row = nullptr;
+    std::atomic<bool> has_coo{false};
+    int64_t max_row = -1;             // longest row, once known
+    ck_config active{};
+    std::mutex mu;                    // guards conversions and `active`
+};
+
+namespace ck {
+
+// Arguments of one product y = alpha*A*x + beta*y.
+//  skip   : if non-null and *skip != 0 when the launch starts, it does nothing
+//           (lets a solver enqueue iterations ahead of its convergence test).
+//  cg     : fused CG step (only where spmv_fuses_dot() holds): the launch also
+//           forms sigma = y.x (x = p, y = q = A p) and its last block sets
+//           alpha = rho/sigma, or state = BREAKDOWN when sigma <= 0.
+//           dot_partials needs spmv_dot_blocks() entries.
+//  carry  : workspace of spmv_carry_bytes() for merge-path and COO; when null
+//           the launch allocates it stream-ordered.
+template <typename T>
+struct SpmvArgs {
+    T alpha = 1, beta = 0;
+    const T *x = nullptr;
+    T *y = nullptr;
+    const int *skip = nullptr;
+    CgDev<T> *cg = nullptr;
+    T *dot_partials = nullptr;
+    void *carry = nullptr;
+};
+
+bool config_valid(const ck_config &c);
+bool spmv_fuses_dot(const ck_config &c);
+// Number of dot partials a fused launch writes (0 if not fused; <= kMaxPartials).
+int64_t spmv_dot_blocks(const ck_matrix &M, const ck_config &c);
+// Bytes of carry workspace a launch needs (0 if none).
+int64_t spmv_carry_bytes(const ck_matrix &M, const ck_config &c, bool fp32);
+
+template <typename T>
+ck_status launch_spmv(const ck_matrix &M, const ck_config &c, const SpmvArgs<T> &a,
+                      hipStream_t s);
+
+// Deterministic two-stage reductions (vecops.hip)
+template <typename T>
+int64_t dot_blocks(int64_t n);
+template <typename T>
+ck_status launch_dot_partials(int64_t n, const T *x, const T *y, T *partials, hipStream_t s);
+
+const char *kernel_name(const ck_config &c, bool fp32);
+ck_config default_config(int64_t n, int64_t nnz);
+
+}  // namespace ck

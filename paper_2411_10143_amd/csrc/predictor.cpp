@@ -1,0 +1,201 @@
+// Cascaded SpMV-configuration predictor (Section III-C-1, cascaded-prediction
+// figure): three decision trees evaluated in sequence.
+//   stage 1 "format"    : CSR / ELL / COO
+//   stage 2 "algorithm" : (CSR only) scalar / vector / merge-path
+//   stage 3 "lanes"     : (CSR-vector only) log2 of lanes per row, 0..6
+// The paper compiles its trained models to C with m2cgen so inference costs
+// microseconds instead of milliseconds (inference-time table); here each tree
+// is a flat node table walked by a few lines of C++.
+//
+// Model file (text): comment lines start with '#'; each tree is
+//   tree <name> <node count>
+// followed by one line per node:
+//   <feature index or -1 for a leaf> <threshold, C99 hex float> <left> <right> <class>
+// An internal node sends a feature vector left iff (double)(float)f[feature]
+// <= threshold (the tree was fitted on single-precision inputs).
+#include <dlfcn.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "predictor.hpp"
+
+namespace ck {
+
+namespace {
+
+std::mutex g_models_mu;
+std::map<std::string, Cascade> g_models;
+
+bool parse_model(const std::string &path, Cascade &out, std::string &err) {
+    FILE *f = fopen(path.c_str(), "r");
+    if (!f) {
+        err = "cannot open cascade model '" + path + "'";
+        return false;
+    }
+    char line[512];
+    Tree *cur = nullptr;
+    int expect = 0;
+    bool ok = true;
+    while (ok && fgets(line, sizeof line, f)) {
+        if (line[0] == '#' || line[0] == '\n')
+            continue;
+        if (strncmp(line, "tree ", 5) == 0) {
+            char name[64];
+            int count = 0;
+            if (sscanf(line + 5, "%63s %d", name, &count) != 2 || count <= 0) {
+                ok = false;
+                break;
+            }
+            if (!strcmp(name, "format"))
+                cur = &out.tree[0];
+            else if (!strcmp(name, "algorithm"))
+                cur = &out.tree[1];
+            else if (!strcmp(name, "lanes"))
+                cur = &out.tree[2];
+            else {
+                ok = false;
+                break;
+            }
+            cur->feature.clear();
+            cur->threshold.clear();
+            cur->left.clear();
+            cur->right.clear();
+            cur->cls.clear();
+            expect = count;
+            continue;
+        }
+        if (!cur || expect <= 0) {
+            ok = false;
+            break;
+        }
+        int fe, le, ri, cl;
+        char thr[128];
+        if (sscanf(line, "%d %127s %d %d %d", &fe, thr, &le, &ri, &cl) != 5) {
+            ok = false;
+            break;
+        }
+        cur->feature.push_back(fe);
+        cur->threshold.push_back(strtod(thr, nullptr));
+        cur->left.push_back(le);
+        cur->right.push_back(ri);
+        cur->cls.push_back(cl);
+        --expect;
+    }
+    fclose(f);
+    if (ok) {
+        for (int t = 0; t < 3 && ok; ++t) {
+            const Tree &T = out.tree[t];
+            const int nn = (int)T.feature.size();
+            if (nn == 0)
+                ok = false;
+            for (int i = 0; i < nn && ok; ++i)
+                if (T.feature[i] >= 0 &&
+                    (T.feature[i] >= kNumModelFeatures || T.left[i] <= i || T.right[i] <= i ||
+                     T.left[i] >= nn || T.right[i] >= nn))
+                    ok = false;   // children come after parents: the walk ends
+        }
+    }
+    if (!ok)
+        err = "malformed cascade model '" + path + "'";
+    return ok;
+}
+
+std::string default_model_path() {
+    Dl_info info;
+    if (dladdr((void *)&default_model_path, &info) && info.dli_fname) {
+        std::string p(info.dli_fname);
+        const size_t slash = p.rfind('/');
+        return (slash == std::string::npos ? std::string(".") : p.substr(0, slash)) +
+               "/cascade_model.txt";
+    }
+    return "cascade_model.txt";
+}
+
+}  // namespace
+
+const Cascade *load_cascade(const char *path, std::string &err) {
+    const std::string key = path ? std::string(path) : default_model_path();
+    std::lock_guard<std::mutex> lk(g_models_mu);
+    auto it = g_models.find(key);
+    if (it != g_models.end())
+        return &it->second;
+    Cascade c;
+    if (!parse_model(key, c, err))
+        return nullptr;
+    return &g_models.emplace(key, std::move(c)).first->second;
+}
+
+int Tree::eval(const double *f) const {
+    int t = 0;
+    while (feature[t] >= 0) {
+        const double v = (double)(float)f[feature[t]];
+        t = v <= threshold[t] ? left[t] : right[t];
+    }
+    return cls[t];
+}
+
+// The 15 model inputs in feature-table order.
+#pragma clang fp contract(off)
+void derive_features(ck_features &F) {
+    const double n = (double)F.nrows;
+    F.density = F.mean = F.sd = F.cov = F.maxavg = F.distavg = F.clusteravg = F.fill =
+        F.diagfill = 0.0;
+    if (F.nrows <= 0)
+        return;
+    F.density = F.ncols > 0 ? (double)F.nnz / (n * (double)F.ncols) : 0.0;
+    F.mean = (double)F.nnz / n;
+    const __int128 var = (__int128)F.nrows * (__int128)F.sum_r2 - (__int128)F.sum_r * (__int128)F.sum_r;
+    F.sd = std::sqrt((double)var) / n;
+    F.cov = F.mean > 0.0 ? F.sd / F.mean : 0.0;
+    F.maxavg = (double)F.max_r - F.mean;
+    F.distavg = (double)F.span_sum / n;
+    F.clusteravg = (double)F.cluster_sum / n;
+    F.fill = F.nnz > 0 ? (n * (double)F.max_r) / (double)F.nnz : 0.0;
+    F.diagfill = F.nnz > 0 ? (n * (double)F.ndiag) / (double)F.nnz : 0.0;
+}
+
+void model_inputs(const ck_features &F, double *f) {
+    f[0] = (double)F.nrows;
+    f[1] = (double)F.ncols;
+    f[2] = (double)F.nnz;
+    f[3] = F.density;
+    f[4] = F.mean;
+    f[5] = F.sd;
+    f[6] = F.cov;
+    f[7] = (double)F.max_r;
+    f[8] = (double)F.min_r;
+    f[9] = F.maxavg;
+    f[10] = F.distavg;
+    f[11] = F.clusteravg;
+    f[12] = F.fill;
+    f[13] = (double)F.ndiag;
+    f[14] = F.diagfill;
+}
+
+ck_config stage_config(int stage, int cls, const ck_config &prev) {
+    ck_config c = prev;
+    if (stage == 0) {
+        c.format = cls;
+        if (cls != CK_FMT_CSR) {
+            c.algorithm = 0;
+            c.lanes = 0;
+        }
+    } else if (stage == 1) {
+        c.algorithm = cls;
+        if (cls != CK_ALG_VECTOR)
+            c.lanes = 0;
+    } else {
+        c.lanes = 1 << cls;
+    }
+    c.stages_done = stage + 1;
+    return c;
+}
+
+}  // namespace ck

@@ -1,0 +1,632 @@
+// Host drivers of CG and GMRES(m), plain FP64 and mixed FP32/FP64, and the
+// asynchronous executor that predicts and swaps the SpMV configuration while
+// the solve runs (Section III-C-2, asynchronous execution).
+//
+// The drivers only enqueue: every scalar of the iteration (alpha, beta, the
+// Hessenberg/Givens update, convergence tests) lives on the device, and every
+// iteration kernel turns into a no-op once the device state leaves RUN.  The
+// host polls that state through pinned memory every few iterations, one poll
+// behind, so the GPU never waits for the host inside a solve.
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <thread>
+
+#include "matrix.hpp"
+#include "predictor.hpp"
+#include "solvers.hpp"
+
+namespace ck {
+
+ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s);
+ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s);
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+double us_since(Clock::time_point t0) {
+    return std::chrono::duration<double, std::micro>(Clock::now() - t0).count();
+}
+
+// ---------------------------------------------------------------------------
+// Device workspace owned by one solve (freed in stream order at the end).
+struct Workspace {
+    hipStream_t s;
+    std::vector<void *> blocks;
+    explicit Workspace(hipStream_t st) : s(st) {}
+    template <typename T>
+    ck_status get(T **p, int64_t count) {
+        void *q = nullptr;
+        const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
+        hipError_t e = hipMallocAsync(&q, bytes, s);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return fail(CK_E_NOMEM, "workspace allocation of %zu bytes failed", bytes);
+        }
+        blocks.push_back(q);
+        *p = (T *)q;
+        return CK_OK;
+    }
+    ~Workspace() {
+        for (void *q : blocks)
+            (void)hipFreeAsync(q, s);
+    }
+};
+
+// Pinned host staging for status polls (one buffer per host thread).
+struct Pinned {
+    char *buf = nullptr;
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    ck_status init() {
+        if (!buf) {
+            CK_HIP(hipHostMalloc((void **)&buf, 4096, hipHostMallocDefault));
+            CK_HIP(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+            CK_HIP(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+        }
+        return CK_OK;
+    }
+};
+thread_local Pinned tl_pinned;
+
+// ---------------------------------------------------------------------------
+// Asynchronous executor: a worker thread runs features (GPU, side stream),
+// the three-stage cascade (host) and the format conversion (GPU, side
+// stream) and publishes each stage's configuration as soon as it is known.
+// The solver calls poll() at every iteration boundary and adopts a published
+// configuration once its conversion (if any) has completed.
+class AsyncExec {
+  public:
+    AsyncExec(ck_matrix &M, const ck_config &start) : M_(M), current_(start) {
+        for (int t = 0; t < 3; ++t) {
+            published_[t].store(-1);
+            applied_[t] = false;
+        }
+    }
+    ~AsyncExec() { finish(); }
+
+    ck_status start() {
+        CK_HIP(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
+        CK_HIP(hipEventCreateWithFlags(&conv_done_, hipEventDisableTiming));
+        worker_ = std::thread([this] { run(); });
+        return CK_OK;
+    }
+
+    // Called by the solver between iterations; `iter` = iterations issued so far.
+    void poll(int iter, ck_config &cfg, int32_t switch_iter[3]) {
+        for (int t = 0; t < 3; ++t) {
+            if (applied_[t])
+                continue;
+            const int code = published_[t].load(std::memory_order_acquire);
+            if (code < 0)
+                return;                      // later stages come after this one
+            if (code == kNoStage) {          // stage not run (cascade ended earlier)
+                applied_[t] = true;
+                continue;
+            }
+            if (t == 0 && conv_needed_.load(std::memory_order_acquire)) {
+                const hipError_t e = hipEventQuery(conv_done_);
+                if (e == hipErrorNotReady)
+                    return;
+                (void)hipGetLastError();
+            }
+            ck_config next = decoded_[t];
+            cfg = next;
+            switch_iter[t] = iter;
+            applied_[t] = true;
+        }
+    }
+
+    void finish() {
+        cancel_.store(true);
+        if (worker_.joinable())
+            worker_.join();
+        if (side_) {
+            (void)hipStreamSynchronize(side_);
+            (void)hipStreamDestroy(side_);
+            side_ = nullptr;
+        }
+        if (conv_done_) {
+            (void)hipEventDestroy(conv_done_);
+            conv_done_ = nullptr;
+        }
+    }
+
+    double t_features = 0, t_infer = 0, t_convert = 0;
+    int conversion_failed = 0;
+
+  private:
+    static constexpr int kNoStage = 1000;
+
+    void publish(int t, const ck_config &c) {
+        decoded_[t] = c;
+        published_[t].store(ck_config_id(&c) >= 0 ? ck_config_id(&c) : 0,
+                            std::memory_order_release);
+    }
+    void skip_rest(int from) {
+        for (int t = from; t < 3; ++t)
+            published_[t].store(kNoStage, std::memory_order_release);
+    }
+
+    void run() {
+        (void)hipSetDevice(M_.device);
+        auto t0 = Clock::now();
+        ck_features F;
+        if (compute_features(M_, F, side_) != CK_OK || cancel_.load()) {
+            skip_rest(0);
+            return;
+        }
+        t_features = us_since(t0);
+        std::string err;
+        const Cascade *C = load_cascade(nullptr, err);
+        if (!C) {
+            skip_rest(0);
+            return;
+        }
+        double in[kNumModelFeatures];
+        model_inputs(F, in);
+        auto t1 = Clock::now();
+        const int fmt = C->tree[0].eval(in);
+        t_infer += us_since(t1);
+        ck_config c = stage_config(0, fmt, current_);
+        if (fmt != CK_FMT_CSR) {
+            if (cancel_.load()) {
+                skip_rest(0);
+                return;
+            }
+            auto t2 = Clock::now();
+            if (convert_format(M_, c, side_) != CK_OK) {
+                // conversion refused or out of memory: keep the current kernel
+                conversion_failed = 1;
+                skip_rest(0);
+                return;
+            }
+            (void)hipEventRecord(conv_done_, side_);
+            conv_needed_.store(true, std::memory_order_release);
+            publish(0, c);
+            skip_rest(1);
+            (void)hipEventSynchronize(conv_done_);
+            t_convert = us_since(t2);
+            return;
+        }
+        publish(0, c);
+        if (cancel_.load()) {
+            skip_rest(1);
+            return;
+        }
+        t1 = Clock::now();
+        const int alg = C->tree[1].eval(in);
+        t_infer += us_since(t1);
+        c = stage_config(1, alg, c);
+        publish(1, c);
+        if (alg != CK_ALG_VECTOR) {
+            skip_rest(2);
+            return;
+        }
+        t1 = Clock::now();
+        const int lg = C->tree[2].eval(in);
+        t_infer += us_since(t1);
+        c = stage_config(2, lg, c);
+        publish(2, c);
+    }
+
+    ck_matrix &M_;
+    ck_config current_;
+    hipStream_t side_ = nullptr;
+    hipEvent_t conv_done_ = nullptr;
+    std::thread worker_;
+    std::atomic<bool> cancel_{false};
+    std::atomic<bool> conv_needed_{false};
+    std::atomic<int> published_[3];
+    ck_config decoded_[3];
+    bool applied_[3];
+};
+
+// ---------------------------------------------------------------------------
+struct SolveCtx {
+    ck_matrix &M;
+    const ck_solve_opts &o;
+    ck_solve_result &res;
+    hipStream_t s;
+    ck_config cfg;
+    AsyncExec *exec = nullptr;
+    void *carry = nullptr;       // merge-path / COO workspace
+    void poll(int iter) {
+        if (exec)
+            exec->poll(iter, cfg, res.switch_iter);
+    }
+};
+
+template <typename T>
+ck_status spmv(SolveCtx &c, T alpha, const T *x, T beta, T *y, const int *skip,
+               CgDev<T> *cg = nullptr, T *partials = nullptr) {
+    SpmvArgs<T> a;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.x = x;
+    a.y = y;
+    a.skip = skip;
+    a.cg = cg;
+    a.dot_partials = partials;
+    a.carry = c.carry;
+    return launch_spmv<T>(c.M, c.cfg, a, c.s);
+}
+
+// ||v|| in FP64, blocking (used once per solve / refinement step)
+ck_status norm_host(SolveCtx &c, const double *v, double *partials, unsigned *counter,
+                    double *dout, double &out) {
+    CK_TRY(launch_dot(c.M.n, v, v, partials, counter, dout, c.s));
+    double h = 0;
+    CK_HIP(hipMemcpyAsync(&h, dout, sizeof h, hipMemcpyDeviceToHost, c.s));
+    CK_HIP(hipStreamSynchronize(c.s));
+    out = std::sqrt(h);
+    return CK_OK;
+}
+
+struct Fp64Scratch {
+    double *partials = nullptr, *dout = nullptr;
+    unsigned *counter = nullptr;
+    ck_status init(Workspace &ws, hipStream_t s) {
+        CK_TRY(ws.get(&partials, 1024));
+        CK_TRY(ws.get(&dout, 4));
+        CK_TRY(ws.get(&counter, 64));
+        return launch_fill<int>(64, (int *)counter, 0, s);
+    }
+};
+
+// true ||b - A x|| / bnorm with the FP64 values
+ck_status true_relres(SolveCtx &c, const double *b, const double *x, double *r, Fp64Scratch &f,
+                      double bnorm, double &out) {
+    CK_TRY(launch_copy<double, double>(c.M.n, r, b, nullptr, c.s));
+    CK_TRY(spmv<double>(c, -1.0, x, 1.0, r, nullptr));
+    double nr = 0;
+    CK_TRY(norm_host(c, r, f.partials, f.counter, f.dout, nr));
+    out = bnorm > 0 ? nr / bnorm : nr;
+    return CK_OK;
+}
+
+// ---------------------------------------------------------------------------
+// One CG run in precision T on A (FP64 or FP32 values) from the residual
+// already in r (x is updated in place).  Returns the final device state.
+template <typename T>
+ck_status cg_core(SolveCtx &c, T *x, T *r, T *p, T *q, T *partials, CgDev<T> *dev,
+                  double bnorm, double tol, int &iter_total, int max_iter, int &state_out) {
+    Pinned &pin = tl_pinned;
+    CK_TRY(pin.init());
+    CgDev<T> h{};
+    h.bnorm = bnorm;
+    h.tol = tol;
+    h.state = RUN;
+    h.iter = iter_total;
+    h.max_iter = max_iter;
+    std::memcpy(pin.buf + 2048, &h, sizeof h);
+    CK_HIP(hipMemcpyAsync(dev, pin.buf + 2048, sizeof h, hipMemcpyHostToDevice, c.s));
+    CK_TRY(launch_cg_start<T>(c.M.n, r, p, partials, dev, c.s));
+    const int every = std::max(1, c.o.check_every > 0 ? c.o.check_every : 8);
+    const int *state_ptr = &dev->state;
+    int slot = 0, polls = 0;
+    int issued = 0;
+    const int budget = max_iter - iter_total;
+    while (true) {
+        c.poll(iter_total + issued);
+        const bool fused = spmv_fuses_dot(c.cfg);
+        if (fused) {
+            CK_TRY(spmv<T>(c, T(1), p, T(0), q, state_ptr, dev, partials));
+        } else {
+            CK_TRY(spmv<T>(c, T(1), p, T(0), q, state_ptr));
+            CK_TRY(launch_cg_sigma<T>(c.M.n, p, q, partials, dev, c.s));
+        }
+        CK_TRY(launch_cg_update<T>(c.M.n, x, r, p, q, partials, dev, c.s));
+        ++issued;
+        if (issued % every == 0 || issued >= budget) {
+            // stage this poll, then read the previous one
+            CK_HIP(hipMemcpyAsync(pin.buf + 64 * slot, &dev->state, 2 * sizeof(int),
+                                  hipMemcpyDeviceToHost, c.s));
+            CK_HIP(hipEventRecord(pin.ev[slot], c.s));
+            ++polls;
+            if (polls >= 2 || issued >= budget) {
+                const int prev = (issued >= budget) ? slot : slot ^ 1;
+                CK_HIP(hipEventSynchronize(pin.ev[prev]));
+                int st;
+                std::memcpy(&st, pin.buf + 64 * prev, sizeof st);
+                if (st != RUN)
+                    break;
+            }
+            slot ^= 1;
+            if (issued >= budget + 2 * every)
+                break;   // device budget check has certainly fired
+        }
+    }
+    CK_HIP(hipMemcpyAsync(pin.buf + 2048, dev, sizeof h, hipMemcpyDeviceToHost, c.s));
+    CK_HIP(hipStreamSynchronize(c.s));
+    std::memcpy(&h, pin.buf + 2048, sizeof h);
+    iter_total = h.iter;
+    state_out = h.state;
+    return CK_OK;
+}
+
+ck_status cg_fp64(SolveCtx &c, const double *b, double *x) {
+    ck_matrix &M = c.M;
+    Workspace ws(c.s);
+    double *r, *p, *q, *partials;
+    CgDev<double> *dev;
+    Fp64Scratch f;
+    CK_TRY(ws.get(&r, M.n));
+    CK_TRY(ws.get(&p, M.n));
+    CK_TRY(ws.get(&q, M.n));
+    CK_TRY(ws.get(&partials, kMaxPartials));
+    CK_TRY(ws.get(&dev, 1));
+    CK_TRY(f.init(ws, c.s));
+    double bnorm = 0;
+    CK_TRY(norm_host(c, b, f.partials, f.counter, f.dout, bnorm));
+    if (bnorm == 0.0) {
+        CK_TRY(launch_fill<double>(M.n, x, 0.0, c.s));
+        c.res.true_relres = 0;
+        return CK_OK;
+    }
+    const int max_iter = c.o.max_iter > 0 ? c.o.max_iter : 100000;
+    int iters = 0, state = RUN;
+    ck_status out = CK_E_NOT_CONVERGED;
+    for (int restart = 0; restart <= 3; ++restart) {
+        CK_TRY(launch_copy<double, double>(M.n, r, b, nullptr, c.s));     // r = b - A x
+        CK_TRY(spmv<double>(c, -1.0, x, 1.0, r, nullptr));
+        CK_TRY(cg_core<double>(c, x, r, p, q, partials, dev, bnorm, c.o.tol, iters, max_iter,
+                               state));
+        c.res.outer_steps = restart + 1;
+        if (state == BREAKDOWN) {
+            out = CK_E_BREAKDOWN;
+            break;
+        }
+        double tr = 0;
+        CK_TRY(true_relres(c, b, x, r, f, bnorm, tr));
+        c.res.true_relres = tr;
+        if (tr <= c.o.tol) {
+            out = CK_OK;
+            break;
+        }
+        if (state == BUDGET)
+            break;
+    }
+    c.res.iterations = iters;
+    return out;
+}
+
+// Mixed precision CG: FP64 refinement steps r = b - A64 x, d = CG32(A32, r/||r||),
+// x += ||r|| d.  The inner solve stops at relative residual max(tol*||b||/||r||, 1e-5)
+// or after max(50, 4 sqrt(n)) iterations.
+ck_status cg_mixed(SolveCtx &c, const double *b, double *x) {
+    ck_matrix &M = c.M;
+    Workspace ws(c.s);
+    double *r64, *scal;
+    float *r, *p, *q, *d, *partials;
+    CgDev<float> *dev;
+    Fp64Scratch f;
+    CK_TRY(ws.get(&r64, M.n));
+    CK_TRY(ws.get(&scal, 4));
+    CK_TRY(ws.get(&r, M.n));
+    CK_TRY(ws.get(&p, M.n));
+    CK_TRY(ws.get(&q, M.n));
+    CK_TRY(ws.get(&d, M.n));
+    CK_TRY(ws.get(&partials, kMaxPartials));
+    CK_TRY(ws.get(&dev, 1));
+    CK_TRY(f.init(ws, c.s));
+    double bnorm = 0;
+    CK_TRY(norm_host(c, b, f.partials, f.counter, f.dout, bnorm));
+    if (bnorm == 0.0) {
+        CK_TRY(launch_fill<double>(M.n, x, 0.0, c.s));
+        c.res.true_relres = 0;
+        return CK_OK;
+    }
+    const int max_iter = c.o.max_iter > 0 ? c.o.max_iter : 100000;
+    const int inner_cap = std::max(50, (int)(4.0 * std::sqrt((double)M.n)));
+    int iters = 0;
+    ck_status out = CK_E_NOT_CONVERGED;
+    Pinned &pin = tl_pinned;
+    CK_TRY(pin.init());
+    for (int step = 0; step < 60; ++step) {
+        double tr = 0;
+        CK_TRY(true_relres(c, b, x, r64, f, bnorm, tr));          // r64 = b - A x
+        c.res.true_relres = tr;
+        c.res.outer_steps = step;
+        if (tr <= c.o.tol) {
+            out = CK_OK;
+            break;
+        }
+        if (iters >= max_iter)
+            break;
+        const double beta = tr * bnorm;
+        double hs[2] = {1.0 / beta, beta};
+        std::memcpy(pin.buf + 3072, hs, sizeof hs);
+        CK_HIP(hipMemcpyAsync(scal, pin.buf + 3072, sizeof hs, hipMemcpyHostToDevice, c.s));
+        CK_TRY(launch_scale_cast<float>(M.n, r, r64, scal, nullptr, c.s));   // r32 = r/beta
+        CK_TRY(launch_fill<float>(M.n, d, 0.0f, c.s));
+        const double inner_tol = std::max(c.o.tol * bnorm / beta, 1e-5);
+        int inner_iters = 0, state = RUN;
+        const int cap = std::min(inner_cap, max_iter - iters);
+        CK_TRY(cg_core<float>(c, d, r, p, q, partials, dev, 1.0, inner_tol, inner_iters, cap,
+                              state));
+        iters += inner_iters;
+        if (state == BREAKDOWN && inner_iters == 0) {
+            out = CK_E_BREAKDOWN;
+            break;
+        }
+        CK_TRY(launch_axpy_promote<float>(M.n, x, d, scal + 1, nullptr, c.s));   // x += beta d
+    }
+    c.res.iterations = iters;
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// GMRES(m) in precision T (T = float: mixed precision; each cycle is one
+// refinement step, since it starts from the FP64 true residual and adds its
+// correction to the FP64 x).
+template <typename T>
+ck_status gmres_run(SolveCtx &c, const double *b, double *x) {
+    ck_matrix &M = c.M;
+    const int m = c.o.restart > 0 ? c.o.restart : 30;
+    if (m > kMaxRestart)
+        return fail(CK_E_INVALID, "restart length %d above %d", m, kMaxRestart);
+    Workspace ws(c.s);
+    const int64_t ldv = ceil_div(std::max<int64_t>(M.n, 1), 64) * 64;
+    T *V, *partials;
+    double *r64;
+    GmDev<T> *st;
+    Fp64Scratch f;
+    CK_TRY(ws.get(&V, ldv * (m + 1)));
+    CK_TRY(ws.get(&partials, (int64_t)(kMaxRestart + 1) * 1024));
+    CK_TRY(ws.get(&r64, M.n));
+    CK_TRY(ws.get(&st, 1));
+    CK_TRY(f.init(ws, c.s));
+    double bnorm = 0;
+    CK_TRY(norm_host(c, b, f.partials, f.counter, f.dout, bnorm));
+    if (bnorm == 0.0) {
+        CK_TRY(launch_fill<double>(M.n, x, 0.0, c.s));
+        c.res.true_relres = 0;
+        return CK_OK;
+    }
+    Pinned &pin = tl_pinned;
+    CK_TRY(pin.init());
+    GmDev<T> *h = (GmDev<T> *)std::malloc(sizeof(GmDev<T>));
+    std::memset(h, 0, sizeof(GmDev<T>));
+    h->m = m;
+    h->bnorm = bnorm;
+    h->tol = c.o.tol;
+    h->max_iter = c.o.max_iter > 0 ? c.o.max_iter : 100000;
+    h->final_state = RUN;
+    h->halt = 1;
+    CK_HIP(hipMemcpyAsync(st, h, sizeof(GmDev<T>), hipMemcpyHostToDevice, c.s));
+    CK_HIP(hipStreamSynchronize(c.s));
+    const int *final_ptr = &st->final_state;
+    const int *halt_ptr = &st->halt;
+    const int status_off = (int)offsetof(GmDev<T>, j);   // j, iter, max_iter, cycle_stop, final_state
+    int issued = 0, slot = 0, cycles = 0;
+    ck_status out = CK_OK;
+    while (true) {
+        // true residual r = b - A x in FP64, then beta, test, v0 = r / beta
+        CK_TRY(launch_copy<double, double>(M.n, r64, b, final_ptr, c.s));
+        CK_TRY(spmv<double>(c, -1.0, x, 1.0, r64, final_ptr));
+        CK_TRY(launch_gm_cycle_start<T>(M.n, r64, V, f.partials, st, c.s));
+        for (int j = 0; j < m; ++j) {
+            c.poll(issued);
+            CK_TRY(spmv<T>(c, T(1), V + (int64_t)j * ldv, T(0), V + (int64_t)(j + 1) * ldv,
+                           halt_ptr));
+            CK_TRY(launch_gm_arnoldi<T>(M.n, j, V, ldv, partials, st, c.s));
+            ++issued;
+        }
+        CK_TRY(launch_gm_cycle_end<T>(M.n, x, V, ldv, st, c.s));
+        ++cycles;
+        CK_HIP(hipMemcpyAsync(pin.buf + 64 * slot, (char *)st + status_off, 5 * sizeof(int),
+                              hipMemcpyDeviceToHost, c.s));
+        CK_HIP(hipEventRecord(pin.ev[slot], c.s));
+        if (cycles >= 2) {
+            const int prev = slot ^ 1;
+            CK_HIP(hipEventSynchronize(pin.ev[prev]));
+            int fs;
+            std::memcpy(&fs, pin.buf + 64 * prev + 4 * sizeof(int), sizeof fs);
+            if (fs != RUN)
+                break;
+        }
+        slot ^= 1;
+        // a cycle that ends on the budget is followed by at most one more start
+        if (issued > h->max_iter + 2 * m)
+            break;
+    }
+    CK_HIP(hipMemcpyAsync(h, st, sizeof(GmDev<T>), hipMemcpyDeviceToHost, c.s));
+    CK_HIP(hipStreamSynchronize(c.s));
+    c.res.iterations = h->iter;
+    c.res.outer_steps = h->cycles;
+    if (h->final_state == CONVERGED)
+        out = CK_OK;
+    else if (h->final_state == BREAKDOWN)
+        out = CK_E_BREAKDOWN;
+    else
+        out = CK_E_NOT_CONVERGED;
+    std::free(h);
+    double tr = 0;
+    CK_TRY(true_relres(c, b, x, r64, f, bnorm, tr));
+    c.res.true_relres = tr;
+    return out;
+}
+
+enum class Solver { CG, GMRES };
+
+ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *opts,
+                ck_solve_result *res, hipStream_t s, Solver which) {
+    if (!hnd || !opts || !res || (hnd->n > 0 && (!b || !x)))
+        return fail(CK_E_INVALID, "NULL argument");
+    ck_matrix &M = *hnd;
+    if (M.n != M.ncols)
+        return fail(CK_E_INVALID, "the matrix must be square");
+    if (!(opts->tol >= 0.0))
+        return fail(CK_E_INVALID, "tol must be >= 0");
+    if (opts->precision == CK_PREC_MIXED && !M.val32)
+        return fail(CK_E_INVALID, "mixed precision needs a handle created with CK_KEEP_FP32");
+    std::memset(res, 0, sizeof *res);
+    res->switch_iter[0] = res->switch_iter[1] = res->switch_iter[2] = -1;
+    const auto t0 = Clock::now();
+    SolveCtx c{M, *opts, *res, s, default_config(M.n, M.nnz)};
+    if (opts->use_config) {
+        if (!config_valid(opts->config))
+            return fail(CK_E_INVALID, "invalid configuration in opts");
+        CK_TRY(convert_format(M, opts->config, s));
+        c.cfg = opts->config;
+    }
+    if (M.n == 0) {
+        res->status = CK_OK;
+        res->final_config = c.cfg;
+        return CK_OK;
+    }
+    Workspace ws(s);
+    int64_t carry = std::max(spmv_carry_bytes(M, ck_config{CK_FMT_CSR, CK_ALG_MERGE, 0, 0}, false),
+                             spmv_carry_bytes(M, ck_config{CK_FMT_COO, 0, 0, 0}, false));
+    char *cbuf = nullptr;
+    CK_TRY(ws.get(&cbuf, carry));
+    c.carry = cbuf;
+    AsyncExec *exec = nullptr;
+    if (opts->async && !opts->use_config) {
+        exec = new AsyncExec(M, c.cfg);
+        ck_status e = exec->start();
+        if (e != CK_OK) {
+            delete exec;
+            return e;
+        }
+        c.exec = exec;
+    }
+    ck_status st;
+    if (which == Solver::CG)
+        st = opts->precision == CK_PREC_MIXED ? cg_mixed(c, b, x) : cg_fp64(c, b, x);
+    else
+        st = opts->precision == CK_PREC_MIXED ? gmres_run<float>(c, b, x)
+                                              : gmres_run<double>(c, b, x);
+    if (exec) {
+        exec->finish();
+        res->t_features_us = exec->t_features;
+        res->t_infer_us = exec->t_infer;
+        res->t_convert_us = exec->t_convert;
+        delete exec;
+    }
+    (void)hipStreamSynchronize(s);
+    res->final_config = c.cfg;
+    res->status = st;
+    res->t_total_us = us_since(t0);
+    return st;
+}
+
+}  // namespace
+}  // namespace ck
+
+extern "C" {
+
+ck_status cg_solve(ck_handle h, const double *d_b, double *d_x, const ck_solve_opts *opts,
+                   ck_solve_result *res, hipStream_t s) {
+    return ck::solve(h, d_b, d_x, opts, res, s, ck::Solver::CG);
+}
+
+ck_status gmres_solve(ck_handle h, const double *d_b, double *d_x, const ck_solve_opts *opts,
+                      ck_solve_result *res, hipStream_t s) {
+    return ck::solve(h, d_b, d_x, opts, res, s, ck::Solver::GMRES);
+}
+
+}  // extern "C"

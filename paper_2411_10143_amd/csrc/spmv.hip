@@ -1,0 +1,613 @@
+// SpMV kernel family for gfx950: y = alpha*A*x + beta*y.
+//
+// The configuration space follows the paper's (Section III-B-2): several
+// storage formats, several algorithms for CSR, and a thread-count parameter
+// for CSR-vector.  On MI355X the kernels are written for wave64:
+//
+//   spmv_csr_vector<L>  L lanes (1..64) share one row, strided over its
+//                       entries; a butterfly over the L lanes sums them
+//                       (Bell & Garland's CSR-vector; the paper's TpV).
+//   spmv_csr_scalar     one lane per row; the workgroup first forms the
+//                       products of its 256-row block in LDS with coalesced
+//                       loads, then each lane sums its row from LDS.
+//   spmv_merge          merge-path load balancing (Merrill & Garland): every
+//                       thread takes an equal share of the merged sequence
+//                       (row ends + entries); rows cut by a thread or block
+//                       boundary are completed by a deterministic carry pass.
+//   spmv_ell            column-major ELLPACK, one lane per row.
+//   spmv_coo            row-sorted triples, equal entry shares per thread,
+//                       the same carry scheme as merge-path.
+//
+// Matrix arrays are streamed with non-temporal loads so the cache keeps the
+// gathered vector; row blocks are mapped so that each XCD works on one
+// contiguous slice of rows (its L2 then holds the x entries that slice uses).
+// Every reduction has a fixed order, so a configuration always returns the
+// same bits for the same input.
+#include "matrix.hpp"
+
+using ck::ld_stream;
+
+constexpr int kMergeIPT = 8;   // merged items per thread  (2048 per workgroup)
+constexpr int kCooIPT = 8;     // entries per thread       (2048 per workgroup)
+constexpr int kScalarCap = 4096;  // products staged per LDS chunk (CSR-scalar)
+
+// ---------------------------------------------------------------------------
+// Row-blocked kernels process row groups g = b, b+G, b+2G, ... (G logical
+// blocks).  Without a fused dot G equals the number of groups; with the fused
+// CG dot G is capped at kMaxPartials so that the last block can finish the
+// reduction quickly.
+//
+// Fused CG step: every block adds q_i * p_i over its rows (x = p, y = q), the
+// last block to arrive sums the partials in block order and sets
+// alpha = rho / sigma (or flags a breakdown when sigma <= 0).
+template <typename T, bool DOT>
+__device__ __forceinline__ void cg_sigma_epilogue(T mine, ck::CgDev<T> *cg, T *partials,
+                                                  int64_t b, int64_t G) {
+    if constexpr (DOT) {
+        __shared__ T lds[4];
+        const T d = ck::block_sum(mine, lds);
+        if (threadIdx.x == 0)
+            partials[b] = d;
+        if (ck::arrive_last(&cg->counter[0], (unsigned)G)) {
+            const T sigma = ck::sum_partials(partials, G, lds);
+            if (threadIdx.x == 0) {
+                cg->sigma = sigma;
+                if (!(sigma > T(0)))
+                    cg->state = ck::BREAKDOWN;
+                else
+                    cg->alpha = cg->rho / sigma;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ bool skipped(const int *skip) { return skip != nullptr && *skip != 0; }
+
+template <int L, typename T, bool BETA, bool DOT>
+__global__ __launch_bounds__(256) void spmv_csr_vector(int n, int64_t G,
+                                                       const int *__restrict__ rp,
+                                                       const int *__restrict__ col,
+                                                       const T *__restrict__ val, T alpha,
+                                                       const T *__restrict__ x, T beta,
+                                                       T *__restrict__ y,
+                                                       const int *__restrict__ skip,
+                                                       ck::CgDev<T> *cg,
+                                                       T *__restrict__ partials) {
+    if (skipped(skip))
+        return;
+    const int64_t b = ck::xcd_block(G);
+    if (b < 0)
+        return;
+    constexpr int R = 256 / L;
+    const int lane = threadIdx.x & (L - 1);
+    const int64_t groups = ((int64_t)n + R - 1) / R;
+    T mine = 0;
+    for (int64_t g = b; g < groups; g += G) {
+        const int64_t row = g * R + threadIdx.x / L;
+        T sum = 0;
+        if (row < n) {
+            const int k0 = rp[row], k1 = rp[row + 1];
+            T s0 = 0, s1 = 0;
+            int k = k0 + lane;
+            for (; k + L < k1; k += 2 * L) {
+                s0 += ld_stream(&val[k]) * x[ld_stream(&col[k])];
+                s1 += ld_stream(&val[k + L]) * x[ld_stream(&col[k + L])];
+            }
+            if (k < k1)
+                s0 += ld_stream(&val[k]) * x[ld_stream(&col[k])];
+            sum = s0 + s1;
+        }
+        sum = ck::group_sum<L>(sum);
+        if (lane == 0 && row < n) {
+            T out = alpha * sum;
+            if (BETA)
+                out += beta * y[row];
+            y[row] = out;
+            if (DOT)
+                mine += out * x[row];
+        }
+    }
+    cg_sigma_epilogue<T, DOT>(mine, cg, partials, b, G);
+}
+
+template <typename T, bool BETA, bool DOT>
+__global__ __launch_bounds__(256) void spmv_csr_scalar(int n, int64_t G,
+                                                       const int *__restrict__ rp,
+                                                       const int *__restrict__ col,
+                                                       const T *__restrict__ val, T alpha,
+                                                       const T *__restrict__ x, T beta,
+                                                       T *__restrict__ y,
+                                                       const int *__restrict__ skip,
+                                                       ck::CgDev<T> *cg,
+                                                       T *__restrict__ partials) {
+    __shared__ T prod[kScalarCap];
+    __shared__ int srp[257];
+    if (skipped(skip))
+        return;
+    const int64_t b = ck::xcd_block(G);
+    if (b < 0)
+        return;
+    const int tid = threadIdx.x;
+    const int64_t groups = ((int64_t)n + 255) / 256;
+    T mine = 0;
+    for (int64_t g = b; g < groups; g += G) {
+        const int64_t r0 = g * 256;
+        const int rows = (int)min<int64_t>(256, n - r0);
+        __syncthreads();   // srp/prod of the previous group are no longer read
+        for (int t = tid; t <= rows; t += 256)
+            srp[t] = rp[r0 + t];
+        __syncthreads();
+        const int k0 = srp[0], k1 = srp[rows];
+        const int my_lo = tid < rows ? srp[tid] : 0;
+        const int my_hi = tid < rows ? srp[tid + 1] : 0;
+        T acc = 0;
+        for (int base = k0; base < k1; base += kScalarCap) {
+            const int cnt = min(kScalarCap, k1 - base);
+            for (int t = tid; t < cnt; t += 256)
+                prod[t] = ld_stream(&val[base + t]) * x[ld_stream(&col[base + t])];
+            __syncthreads();
+            const int lo = max(my_lo, base), hi = min(my_hi, base + cnt);
+            for (int k = lo; k < hi; ++k)
+                acc += prod[k - base];
+            __syncthreads();
+        }
+        if (tid < rows) {
+            const int64_t row = r0 + tid;
+            T out = alpha * acc;
+            if (BETA)
+                out += beta * y[row];
+            y[row] = out;
+            if (DOT)
+                mine += out * x[row];
+        }
+    }
+    cg_sigma_epilogue<T, DOT>(mine, cg, partials, b, G);
+}
+
+template <typename T, bool BETA, bool DOT>
+__global__ __launch_bounds__(256) void spmv_ell(int n, int64_t G, int K, int64_t pitch,
+                                                const int *__restrict__ ecol,
+                                                const T *__restrict__ evl, T alpha,
+                                                const T *__restrict__ x, T beta,
+                                                T *__restrict__ y, const int *__restrict__ skip,
+                                                ck::CgDev<T> *cg, T *__restrict__ partials) {
+    if (skipped(skip))
+        return;
+    const int64_t b = ck::xcd_block(G);
+    if (b < 0)
+        return;
+    const int64_t groups = ((int64_t)n + 255) / 256;
+    T mine = 0;
+    for (int64_t g = b; g < groups; g += G) {
+        const int64_t row = g * 256 + threadIdx.x;
+        if (row < n) {
+            T sum = 0;
+            for (int s = 0; s < K; ++s) {
+                const int c = ld_stream(&ecol[s * pitch + row]);
+                if (c < 0)
+                    break;
+                sum += ld_stream(&evl[s * pitch + row]) * x[c];
+            }
+            T out = alpha * sum;
+            if (BETA)
+                out += beta * y[row];
+            y[row] = out;
+            if (DOT)
+                mine += out * x[row];
+        }
+    }
+    cg_sigma_epilogue<T, DOT>(mine, cg, partials, b, G);
+}
+
+// ---- carry completion shared by merge-path and COO -------------------------
+// Every active thread left in LDS: the row it ended inside (crow, -1 if
+// none) with its partial (cval), and the first row it completed (frow, -1 if
+// none) with its own part of that row (fval).  The first completed row of a
+// thread started in earlier threads: add their carries (ascending order).
+// Thread 0 then records the block's own carry-out for carry_fixup.
+template <typename T, bool BETA>
+__device__ __forceinline__ void finish_carries(int *s_crow, T *s_cval, int frow, T fval,
+                                               int last_active, int64_t b, T alpha, T beta,
+                                               T *__restrict__ y, int *__restrict__ crow_g,
+                                               T *__restrict__ cval_g) {
+    const int tid = threadIdx.x;
+    if (frow >= 0) {
+        int s = tid - 1;
+        while (s >= 0 && s_crow[s] == frow)
+            --s;
+        T tot = 0;
+        for (int u = s + 1; u < tid; ++u)
+            tot += s_cval[u];
+        tot += fval;
+        T out = alpha * tot;
+        if (BETA)
+            out += beta * y[frow];
+        y[frow] = out;
+    }
+    if (tid == 0) {
+        const int R = last_active >= 0 ? s_crow[last_active] : -1;
+        T tot = 0;
+        if (R >= 0) {
+            int s = last_active;
+            while (s >= 0 && s_crow[s] == R)
+                --s;
+            for (int u = s + 1; u <= last_active; ++u)
+                tot += s_cval[u];
+        }
+        crow_g[b] = R;
+        cval_g[b] = tot;
+    }
+}
+
+template <typename T, bool BETA>
+__global__ __launch_bounds__(256) void spmv_merge(int n, int nnz, int64_t G,
+                                                  const int *__restrict__ rp,
+                                                  const int *__restrict__ col,
+                                                  const T *__restrict__ val, T alpha,
+                                                  const T *__restrict__ x, T beta,
+                                                  T *__restrict__ y, int *__restrict__ crow_g,
+                                                  T *__restrict__ cval_g,
+                                                  const int *__restrict__ skip) {
+    __shared__ int s_crow[256];
+    __shared__ T s_cval[256];
+    if (skipped(skip))
+        return;
+    const int64_t b = ck::xcd_block(G);
+    if (b < 0)
+        return;
+    const int tid = threadIdx.x;
+    const int64_t P = (int64_t)n + nnz;
+    const int64_t d0 = (b * 256 + tid) * kMergeIPT;
+    int crow = -1, frow = -1;
+    T cval = 0, fval = 0;
+    if (d0 < P) {
+        const int64_t d1 = min(d0 + kMergeIPT, P);
+        // merge-path search: i = row ends among the first d0 merged items
+        int lo = (int)max<int64_t>(0, d0 - nnz), hi = (int)min<int64_t>(d0, n);
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if ((int64_t)rp[mid + 1] <= d0 - mid - 1)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        int i = lo;
+        int j = (int)(d0 - lo);
+        int rend = i < n ? rp[i + 1] : nnz;
+        T acc = 0;
+        bool first = true;
+        for (int64_t d = d0; d < d1; ++d) {
+            if (j < rend) {
+                acc += ld_stream(&val[j]) * x[ld_stream(&col[j])];
+                ++j;
+            } else {
+                if (first) {
+                    frow = i;
+                    fval = acc;
+                    first = false;
+                } else {
+                    T out = alpha * acc;
+                    if (BETA)
+                        out += beta * y[i];
+                    y[i] = out;
+                }
+                acc = 0;
+                ++i;
+                rend = i < n ? rp[i + 1] : nnz;
+            }
+        }
+        crow = i < n ? i : -1;
+        cval = acc;
+    }
+    s_crow[tid] = crow;
+    s_cval[tid] = cval;
+    __syncthreads();
+    const int64_t first_d = b * 256 * kMergeIPT;
+    const int last_active =
+        (int)min<int64_t>(255, (P - first_d + kMergeIPT - 1) / kMergeIPT - 1);
+    finish_carries<T, BETA>(s_crow, s_cval, frow, fval, last_active, b, alpha, beta, y, crow_g,
+                            cval_g);
+}
+
+template <typename T, bool BETA>
+__global__ __launch_bounds__(256) void spmv_coo(int n, int nnz, int64_t G,
+                                                const int *__restrict__ row,
+                                                const int *__restrict__ col,
+                                                const T *__restrict__ val, T alpha,
+                                                const T *__restrict__ x, T beta,
+                                                T *__restrict__ y, int *__restrict__ crow_g,
+                                                T *__restrict__ cval_g,
+                                                const int *__restrict__ skip) {
+    __shared__ int s_crow[256];
+    __shared__ T s_cval[256];
+    if (skipped(skip))
+        return;
+    const int64_t b = ck::xcd_block(G);
+    if (b < 0)
+        return;
+    const int tid = threadIdx.x;
+    const int64_t k0 = (b * 256 + tid) * kCooIPT;
+    int crow = -1, frow = -1;
+    T cval = 0, fval = 0;
+    if (k0 < nnz) {
+        const int k1 = (int)min<int64_t>(k0 + kCooIPT, nnz);
+        if (k0 == 0) {   // rows before the first stored entry are empty
+            const int r_first = row[0];
+            for (int r = 0; r < r_first; ++r)
+                y[r] = BETA ? beta * y[r] : T(0);
+        }
+        int cur = row[k0];
+        T acc = 0;
+        bool first = true;
+        for (int k = (int)k0; k < k1; ++k) {
+            acc += ld_stream(&val[k]) * x[ld_stream(&col[k])];
+            const int nxt = (k + 1 < nnz) ? row[k + 1] : n;
+            if (nxt != cur) {
+                if (first) {
+                    frow = cur;
+                    fval = acc;
+                    first = false;
+                } else {
+                    T out = alpha * acc;
+                    if (BETA)
+                        out += beta * y[cur];
+                    y[cur] = out;
+                }
+                for (int r = cur + 1; r < nxt; ++r)   // empty rows in the gap
+                    y[r] = BETA ? beta * y[r] : T(0);
+                acc = 0;
+                cur = nxt;
+            }
+        }
+        const int nxt = (k1 < nnz) ? row[k1] : n;
+        if (nxt == row[k1 - 1]) {
+            crow = row[k1 - 1];
+            cval = acc;
+        }
+    }
+    s_crow[tid] = crow;
+    s_cval[tid] = cval;
+    __syncthreads();
+    const int64_t first_k = b * 256 * kCooIPT;
+    const int last_active = (int)min<int64_t>(255, (nnz - first_k + kCooIPT - 1) / kCooIPT - 1);
+    finish_carries<T, BETA>(s_crow, s_cval, frow, fval, last_active, b, alpha, beta, y, crow_g,
+                            cval_g);
+}
+
+// Rows cut by a workgroup boundary: each run of equal carry rows is summed in
+// block order by the run's first entry and added once.
+template <typename T>
+__global__ __launch_bounds__(256) void carry_fixup(int64_t G, const int *__restrict__ crow,
+                                                   const T *__restrict__ cval, T alpha,
+                                                   T *__restrict__ y,
+                                                   const int *__restrict__ skip) {
+    if (skipped(skip))
+        return;
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (b >= G)
+        return;
+    const int R = crow[b];
+    if (R < 0 || (b > 0 && crow[b - 1] == R))
+        return;
+    T tot = 0;
+    for (int64_t e = b; e < G && crow[e] == R; ++e)
+        tot += cval[e];
+    y[R] += alpha * tot;
+}
+
+template <typename T, bool BETA>
+__global__ __launch_bounds__(256) void scale_rows(int64_t n, T beta, T *__restrict__ y,
+                                                  const int *__restrict__ skip) {
+    if (skipped(skip))
+        return;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        y[i] = BETA ? beta * y[i] : T(0);
+}
+
+// ---------------------------------------------------------------------------
+namespace ck {
+
+bool config_valid(const ck_config &c) {
+    if (c.format == CK_FMT_ELL || c.format == CK_FMT_COO)
+        return true;
+    if (c.format != CK_FMT_CSR)
+        return false;
+    if (c.algorithm == CK_ALG_SCALAR || c.algorithm == CK_ALG_MERGE)
+        return true;
+    if (c.algorithm != CK_ALG_VECTOR)
+        return false;
+    return c.lanes >= 1 && c.lanes <= 64 && (c.lanes & (c.lanes - 1)) == 0;
+}
+
+bool spmv_fuses_dot(const ck_config &c) {
+    return c.format == CK_FMT_ELL ||
+           (c.format == CK_FMT_CSR && (c.algorithm == CK_ALG_VECTOR || c.algorithm == CK_ALG_SCALAR));
+}
+
+static int64_t row_groups(const ck_matrix &M, const ck_config &c) {
+    if (c.format == CK_FMT_CSR && c.algorithm == CK_ALG_VECTOR)
+        return ceil_div(M.n, 256 / c.lanes);
+    return ceil_div(M.n, 256);
+}
+
+int64_t spmv_dot_blocks(const ck_matrix &M, const ck_config &c) {
+    if (!spmv_fuses_dot(c))
+        return 0;
+    const int64_t g = row_groups(M, c);
+    return g < kMaxPartials ? (g > 0 ? g : 1) : kMaxPartials;
+}
+
+static int64_t carry_blocks(const ck_matrix &M, const ck_config &c) {
+    if (c.format == CK_FMT_COO)
+        return ceil_div(M.nnz, 256 * kCooIPT);
+    if (c.format == CK_FMT_CSR && c.algorithm == CK_ALG_MERGE)
+        return ceil_div(M.n + M.nnz, 256 * kMergeIPT);
+    return 0;
+}
+
+int64_t spmv_carry_bytes(const ck_matrix &M, const ck_config &c, bool fp32) {
+    const int64_t G = carry_blocks(M, c);
+    return ((G * (int64_t)sizeof(int) + 255) / 256) * 256 + G * (fp32 ? 4 : 8) + 256;
+}
+
+ck_config default_config(int64_t n, int64_t nnz) {
+    const int64_t mean = n > 0 ? nnz / n : 0;   // floor(nnz/n) has the same floor(log2)
+    int L = 1;
+    while ((int64_t)L * 2 <= mean && L < 64)
+        L *= 2;
+    if (L < 2)
+        L = 2;
+    return ck_config{CK_FMT_CSR, CK_ALG_VECTOR, L, 0};
+}
+
+const char *kernel_name(const ck_config &c, bool fp32) {
+    static const char *vec64[7] = {
+        "spmv_csr_vector<1, double, false, false>", "spmv_csr_vector<2, double, false, false>",
+        "spmv_csr_vector<4, double, false, false>", "spmv_csr_vector<8, double, false, false>",
+        "spmv_csr_vector<16, double, false, false>", "spmv_csr_vector<32, double, false, false>",
+        "spmv_csr_vector<64, double, false, false>"};
+    static const char *vec32[7] = {
+        "spmv_csr_vector<1, float, false, false>", "spmv_csr_vector<2, float, false, false>",
+        "spmv_csr_vector<4, float, false, false>", "spmv_csr_vector<8, float, false, false>",
+        "spmv_csr_vector<16, float, false, false>", "spmv_csr_vector<32, float, false, false>",
+        "spmv_csr_vector<64, float, false, false>"};
+    if (c.format == CK_FMT_ELL)
+        return fp32 ? "spmv_ell<float, false, false>" : "spmv_ell<double, false, false>";
+    if (c.format == CK_FMT_COO)
+        return fp32 ? "spmv_coo<float, false>" : "spmv_coo<double, false>";
+    if (c.algorithm == CK_ALG_SCALAR)
+        return fp32 ? "spmv_csr_scalar<float, false, false>" : "spmv_csr_scalar<double, false, false>";
+    if (c.algorithm == CK_ALG_MERGE)
+        return fp32 ? "spmv_merge<float, false>" : "spmv_merge<double, false>";
+    int idx = 0;
+    while ((1 << idx) < c.lanes)
+        ++idx;
+    return fp32 ? vec32[idx] : vec64[idx];
+}
+
+template <typename T>
+static const T *values(const ck_matrix &M) {
+    if constexpr (sizeof(T) == 4)
+        return M.val32;
+    else
+        return M.val;
+}
+
+template <typename T>
+static const T *ell_values(const ck_matrix &M) {
+    if constexpr (sizeof(T) == 4)
+        return M.ell_val32;
+    else
+        return M.ell_val;
+}
+
+template <int L, typename T, bool BETA, bool DOT>
+static void go_vector(const ck_matrix &M, int64_t G, const SpmvArgs<T> &a, hipStream_t s) {
+    hipLaunchKernelGGL((spmv_csr_vector<L, T, BETA, DOT>), dim3(xcd_grid(G)), dim3(256), 0, s,
+                       (int)M.n, G, M.rp, M.col, values<T>(M), a.alpha, a.x, a.beta, a.y, a.skip,
+                       a.cg, a.dot_partials);
+}
+
+template <typename T, bool BETA, bool DOT>
+static ck_status dispatch_rows(const ck_matrix &M, const ck_config &c, const SpmvArgs<T> &a,
+                               hipStream_t s) {
+    const int64_t G = DOT ? spmv_dot_blocks(M, c) : row_groups(M, c);
+    if (c.format == CK_FMT_ELL) {
+        hipLaunchKernelGGL((spmv_ell<T, BETA, DOT>), dim3(xcd_grid(G)), dim3(256), 0, s,
+                           (int)M.n, G, (int)M.ell_K, M.ell_pitch, M.ell_col, ell_values<T>(M),
+                           a.alpha, a.x, a.beta, a.y, a.skip, a.cg, a.dot_partials);
+        return CK_OK;
+    }
+    if (c.algorithm == CK_ALG_SCALAR) {
+        hipLaunchKernelGGL((spmv_csr_scalar<T, BETA, DOT>), dim3(xcd_grid(G)), dim3(256), 0, s,
+                           (int)M.n, G, M.rp, M.col, values<T>(M), a.alpha, a.x, a.beta, a.y,
+                           a.skip, a.cg, a.dot_partials);
+        return CK_OK;
+    }
+    switch (c.lanes) {
+    case 1: go_vector<1, T, BETA, DOT>(M, G, a, s); break;
+    case 2: go_vector<2, T, BETA, DOT>(M, G, a, s); break;
+    case 4: go_vector<4, T, BETA, DOT>(M, G, a, s); break;
+    case 8: go_vector<8, T, BETA, DOT>(M, G, a, s); break;
+    case 16: go_vector<16, T, BETA, DOT>(M, G, a, s); break;
+    case 32: go_vector<32, T, BETA, DOT>(M, G, a, s); break;
+    case 64: go_vector<64, T, BETA, DOT>(M, G, a, s); break;
+    default: return fail(CK_E_INVALID, "lanes must be a power of two in [1, 64]");
+    }
+    return CK_OK;
+}
+
+template <typename T, bool BETA>
+static ck_status dispatch_carry(const ck_matrix &M, const ck_config &c, const SpmvArgs<T> &a,
+                                hipStream_t s) {
+    const int64_t G = carry_blocks(M, c);
+    void *ws = a.carry;
+    bool own = false;
+    if (ws == nullptr) {
+        CK_HIP(hipMallocAsync(&ws, (size_t)spmv_carry_bytes(M, c, sizeof(T) == 4), s));
+        own = true;
+    }
+    int *crow = (int *)ws;
+    T *cval = (T *)((char *)ws + ((G * (int64_t)sizeof(int) + 255) / 256) * 256);
+    if (c.format == CK_FMT_COO)
+        hipLaunchKernelGGL((spmv_coo<T, BETA>), dim3(xcd_grid(G)), dim3(256), 0, s, (int)M.n,
+                           (int)M.nnz, G, M.coo_row, M.col, values<T>(M), a.alpha, a.x, a.beta,
+                           a.y, crow, cval, a.skip);
+    else
+        hipLaunchKernelGGL((spmv_merge<T, BETA>), dim3(xcd_grid(G)), dim3(256), 0, s, (int)M.n,
+                           (int)M.nnz, G, M.rp, M.col, values<T>(M), a.alpha, a.x, a.beta, a.y,
+                           crow, cval, a.skip);
+    hipLaunchKernelGGL((carry_fixup<T>), dim3(ceil_div(G, 256)), dim3(256), 0, s, G, crow, cval,
+                       a.alpha, a.y, a.skip);
+    if (own)
+        CK_HIP(hipFreeAsync(ws, s));
+    return CK_OK;
+}
+
+template <typename T>
+ck_status launch_spmv(const ck_matrix &M, const ck_config &c, const SpmvArgs<T> &a,
+                      hipStream_t s) {
+    if (!config_valid(c))
+        return fail(CK_E_INVALID, "invalid SpMV configuration");
+    if constexpr (sizeof(T) == 4) {
+        if (!M.val32)
+            return fail(CK_E_INVALID, "FP32 product needs a handle created with CK_KEEP_FP32");
+    }
+    if (c.format == CK_FMT_ELL && !M.has_ell.load())
+        return fail(CK_E_INVALID, "ELL requested but the matrix has not been converted");
+    if (c.format == CK_FMT_COO && !M.has_coo.load())
+        return fail(CK_E_INVALID, "COO requested but the matrix has not been converted");
+    const bool beta = a.beta != T(0);
+    const bool dot = a.cg != nullptr;
+    if (dot && (!spmv_fuses_dot(c) || a.dot_partials == nullptr))
+        return fail(CK_E_INVALID, "this configuration does not fuse the CG dot product");
+    if (M.n == 0)
+        return CK_OK;
+    ck_status st;
+    if (M.nnz == 0 && !dot) {
+        if (beta)
+            hipLaunchKernelGGL((scale_rows<T, true>), dim3(ceil_div(M.n, 256)), dim3(256), 0, s,
+                               M.n, a.beta, a.y, a.skip);
+        else
+            hipLaunchKernelGGL((scale_rows<T, false>), dim3(ceil_div(M.n, 256)), dim3(256), 0, s,
+                               M.n, a.beta, a.y, a.skip);
+        st = CK_OK;
+    } else if (c.format == CK_FMT_COO || (c.format == CK_FMT_CSR && c.algorithm == CK_ALG_MERGE)) {
+        st = beta ? dispatch_carry<T, true>(M, c, a, s) : dispatch_carry<T, false>(M, c, a, s);
+    } else if (beta) {
+        st = dot ? dispatch_rows<T, true, true>(M, c, a, s) : dispatch_rows<T, true, false>(M, c, a, s);
+    } else {
+        st = dot ? dispatch_rows<T, false, true>(M, c, a, s) : dispatch_rows<T, false, false>(M, c, a, s);
+    }
+    CK_TRY(st);
+    CK_HIP(hipGetLastError());
+    return CK_OK;
+}
+
+template ck_status launch_spmv<double>(const ck_matrix &, const ck_config &,
+                                       const SpmvArgs<double> &, hipStream_t);
+template ck_status launch_spmv<float>(const ck_matrix &, const ck_config &,
+                                      const SpmvArgs<float> &, hipStream_t);
+
+}  // namespace ck

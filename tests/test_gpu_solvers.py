@@ -1,0 +1,191 @@
+"""GPU CG / GMRES(m) through the C ABI: every result is checked by the oracle's
+true FP64 residual, and iteration counts are compared with the oracle's."""
+import numpy as np
+import pytest
+
+from helpers import say
+from synth import matrices as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ck():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2411_10143_amd as ck
+    ck.lib()
+    return ck
+
+
+def problem(orc, A, seed):
+    xs = M.vector(A.n, seed)
+    return xs, orc.spmv(A, xs)
+
+
+def run(ck, solver, Mx, b, x0=None, **kw):
+    import torch
+    db = torch.from_numpy(b).cuda()
+    dx = torch.zeros_like(db) if x0 is None else torch.from_numpy(x0).cuda()
+    res = solver(Mx.handle, db, dx, **kw)
+    return dx.cpu().numpy(), res
+
+
+def test_cg_lap2d_64_default_config(ck, orc):
+    A = M.laplacian_2d(64)
+    xs, b = problem(orc, A, 1)
+    say("cg lap2d_64 default")
+    Mx = ck.Matrix.from_csr(A)
+    x, r = run(ck, ck.cg_solve, Mx, b, tol=1e-10)
+    ref = orc.cg(A, b, tol=1e-10)
+    assert r["status"] == ck.CK_OK
+    assert orc.relres(A, b, x) <= 1e-10
+    assert abs(r["true_relres"] - orc.relres(A, b, x)) <= 1e-12
+    assert abs(r["iterations"] - ref["iters"]) <= 3, (r["iterations"], ref["iters"])
+    assert np.linalg.norm(x - ref["x"]) / np.linalg.norm(ref["x"]) < 1e-6
+    Mx.close()
+
+
+@pytest.mark.parametrize("cid", range(11))
+def test_cg_every_config(ck, orc, cid):
+    A = M.laplacian_2d(40)
+    xs, b = problem(orc, A, 2)
+    say(f"cg lap2d_40 config {cid}")
+    Mx = ck.Matrix.from_csr(A)
+    x, r = run(ck, ck.cg_solve, Mx, b, tol=1e-10, config=ck.config_from_id(cid))
+    assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10
+    assert r["final_config"] == cid
+    Mx.close()
+
+
+def test_cg_mixed_precision(ck, orc):
+    A = M.laplacian_2d(64)
+    xs, b = problem(orc, A, 1)
+    say("cg mixed lap2d_64")
+    Mx = ck.Matrix.from_csr(A, keep_fp32=True)
+    x, r = run(ck, ck.cg_solve, Mx, b, tol=1e-10, precision=ck.CK_PREC_MIXED)
+    assert r["status"] == ck.CK_OK, r
+    assert orc.relres(A, b, x) <= 1e-10
+    assert r["outer_steps"] >= 2
+    Mx.close()
+
+
+def test_cg_async_executor(ck, orc):
+    A = M.laplacian_3d(48)
+    xs, b = problem(orc, A, 3)
+    say("cg async lap3d_48")
+    Mx = ck.Matrix.from_csr(A)
+    x, r = run(ck, ck.cg_solve, Mx, b, tol=1e-10, async_=True)
+    assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10
+    # stage 1 must have landed on this ~150-iteration solve, then the
+    # cascade's decisions stay consistent with the final configuration
+    assert r["switch_iter"][0] >= 0, r
+    assert r["t_features_us"] > 0
+    Mx.close()
+
+
+def test_cg_breakdown_budget_zero_rhs(ck, orc):
+    import torch
+    say("cg breakdown")
+    Mx = ck.Matrix.from_csr(M.from_dense(-np.eye(50)))
+    x, r = run(ck, ck.cg_solve, Mx, np.ones(50))
+    assert r["status"] == ck.CK_E_BREAKDOWN
+    Mx.close()
+    A = M.laplacian_2d(32)
+    Mx = ck.Matrix.from_csr(A)
+    say("cg budget")
+    x, r = run(ck, ck.cg_solve, Mx, M.vector(A.n, 1), tol=1e-12, max_iter=10)
+    assert r["status"] == ck.CK_E_NOT_CONVERGED and r["iterations"] == 10
+    ref = orc.cg(A, M.vector(A.n, 1), tol=1e-12, maxit=10)
+    assert np.allclose(x, ref["x"], rtol=1e-9, atol=1e-12)
+    say("cg zero rhs")
+    x, r = run(ck, ck.cg_solve, Mx, np.zeros(A.n), x0=np.ones(A.n))
+    assert r["status"] == ck.CK_OK and not x.any()
+    Mx.close()
+
+
+def test_gmres_convdiff_fp64(ck, orc):
+    A = M.convection_diffusion_2d(48, 10.0)
+    xs, b = problem(orc, A, 4001)
+    say("gmres convdiff48 fp64")
+    Mx = ck.Matrix.from_csr(A)
+    x, r = run(ck, ck.gmres_solve, Mx, b, tol=1e-10, restart=30)
+    ref = orc.gmres(A, b, m=30, tol=1e-10)
+    assert r["status"] == ck.CK_OK, r
+    assert orc.relres(A, b, x) <= 1e-10
+    assert abs(r["iterations"] - ref["iters"]) <= max(5, 0.05 * ref["iters"]), \
+        (r["iterations"], ref["iters"])
+    Mx.close()
+
+
+@pytest.mark.parametrize("cid", range(11))
+def test_gmres_every_config(ck, orc, cid):
+    A = M.convection_diffusion_2d(24, 10.0)
+    xs, b = problem(orc, A, 5)
+    say(f"gmres convdiff24 config {cid}")
+    Mx = ck.Matrix.from_csr(A)
+    x, r = run(ck, ck.gmres_solve, Mx, b, tol=1e-10, config=ck.config_from_id(cid))
+    assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10
+    Mx.close()
+
+
+def test_gmres_mixed_precision(ck, orc):
+    A = M.convection_diffusion_2d(48, 10.0)
+    xs, b = problem(orc, A, 4001)
+    say("gmres convdiff48 mixed")
+    Mx = ck.Matrix.from_csr(A, keep_fp32=True)
+    x, r = run(ck, ck.gmres_solve, Mx, b, tol=1e-10, precision=ck.CK_PREC_MIXED)
+    assert r["status"] == ck.CK_OK, r
+    assert orc.relres(A, b, x) <= 1e-10
+    Mx.close()
+
+
+@pytest.mark.parametrize("m", [1, 5, 30, 64])
+def test_gmres_restart_lengths(ck, orc, m):
+    A = M.diagonally_dominant(M.uniform_random(3000, 9, 4, 16))
+    xs, b = problem(orc, A, 6)
+    say(f"gmres dd m={m}")
+    Mx = ck.Matrix.from_csr(A)
+    x, r = run(ck, ck.gmres_solve, Mx, b, tol=1e-10, restart=m)
+    ref = orc.gmres(A, b, m=m, tol=1e-10)
+    assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10
+    assert abs(r["iterations"] - ref["iters"]) <= max(3, 0.1 * ref["iters"])
+    Mx.close()
+
+
+def test_gmres_happy_breakdown_and_identity(ck, orc):
+    say("gmres invariant subspace")
+    Dg = M.from_dense(np.diag(np.arange(1.0, 41.0)))
+    b = np.zeros(40)
+    b[[1, 4, 7]] = [1.0, -2.0, 3.0]
+    Mx = ck.Matrix.from_csr(Dg)
+    x, r = run(ck, ck.gmres_solve, Mx, b, tol=1e-13, restart=8)
+    assert r["status"] == ck.CK_OK and r["iterations"] == 3
+    Mx.close()
+    Mx = ck.Matrix.from_csr(M.from_dense(np.eye(10)))
+    x, r = run(ck, ck.gmres_solve, Mx, M.vector(10, 1), restart=5)
+    assert r["status"] == ck.CK_OK and r["iterations"] == 1
+    Mx.close()
+
+
+def test_gmres_budget_and_zero_rhs(ck, orc):
+    A = M.convection_diffusion_2d(32, 10.0)
+    Mx = ck.Matrix.from_csr(A)
+    say("gmres budget")
+    x, r = run(ck, ck.gmres_solve, Mx, M.vector(A.n, 1), tol=1e-12, max_iter=40)
+    assert r["status"] == ck.CK_E_NOT_CONVERGED and r["iterations"] == 40
+    say("gmres zero rhs")
+    x, r = run(ck, ck.gmres_solve, Mx, np.zeros(A.n))
+    assert r["status"] == ck.CK_OK and not x.any()
+    Mx.close()
+
+
+def test_gmres_async(ck, orc):
+    A = M.convection_diffusion_2d(128, 10.0)
+    xs, b = problem(orc, A, 7)
+    say("gmres async convdiff128")
+    Mx = ck.Matrix.from_csr(A)
+    x, r = run(ck, ck.gmres_solve, Mx, b, tol=1e-10, async_=True)
+    assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10
+    assert r["switch_iter"][0] >= 0
+    Mx.close()

@@ -1,0 +1,259 @@
+"""GPU parity of the SpMV family, features, conversions and the cascade,
+through the C ABI, against the CPU oracle on the same seeded inputs."""
+import numpy as np
+import pytest
+
+from helpers import MODEL, parse_model, say, sk_tree, spmv_bound, upload, write_model
+from synth import matrices as M
+
+pytestmark = pytest.mark.gpu
+
+U64 = 2.0 ** -53
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def ck():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2411_10143_amd as ck
+    ck.lib()
+    return ck
+
+
+CASES = {
+    "int_ragged": lambda: M.random_integer(3001, 2800, 1, density=0.004, empty_rows=0.2,
+                                           long_rows=3, long_len=2500),
+    "int_wide": lambda: M.random_integer(700, 9000, 2, density=0.01, empty_rows=0.0),
+    "powerlaw": lambda: M.power_law_rows(20011, 1.6, 3),
+    "banded27": lambda: M.banded_stencil(30011, 27, 4),
+    "blockdiag": lambda: M.block_diagonal(10007, 5),
+    "uniform": lambda: M.uniform_random(50003, 6),
+    "lap2d_64": lambda: M.laplacian_2d(64),
+    "convdiff": lambda: M.convection_diffusion_2d(100, 10.0),
+    "empty": lambda: M.from_dense(np.zeros((5, 7))),
+    "one_by_one": lambda: M.from_dense(np.array([[3.0]])),
+    "single_row": lambda: M.from_dense(np.arange(1.0, 200.0)[None, :]),
+    "single_col": lambda: M.from_dense(np.arange(1.0, 300.0)[:, None]),
+}
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        _cache[name] = CASES[name]()
+    return _cache[name]
+
+
+def is_int(A):
+    return np.all(A.val == np.round(A.val))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_spmv_all_configs_fp64(ck, orc, name):
+    import torch
+    A = case(name)
+    rng = np.random.default_rng(7)
+    integer = is_int(A)
+    x = rng.integers(-8, 9, A.ncols).astype(float) if integer else rng.uniform(-1, 1, A.ncols)
+    y0 = rng.integers(-8, 9, A.n).astype(float) if integer else rng.uniform(-1, 1, A.n)
+    Mx = ck.Matrix.from_csr(A)
+    dx = torch.from_numpy(x).cuda()
+    st_ell = orc.ell_shape(A)[0]
+    for cid in range(ck.NUM_CONFIGS):
+        cfg = ck.config_from_id(cid)
+        say(f"spmv {name} n={A.n} nnz={A.nnz} config={ck.CONFIG_NAMES[cid]}")
+        if cid == 9 and st_ell != orc.OK:
+            with pytest.raises(ck.CkError) as e:
+                ck.spmv_convert(Mx.handle, cfg)
+            assert e.value.status == ck.CK_E_UNSUPPORTED
+            continue
+        ck.spmv_convert(Mx.handle, cfg)
+        for alpha, beta in [(1.0, 0.0), (-0.5, 2.0)]:
+            dy = torch.from_numpy(y0).cuda() if beta else torch.full((A.n,), float("nan"),
+                                                                      dtype=torch.float64,
+                                                                      device="cuda")
+            ck.spmv_apply(Mx.handle, dx, dy, alpha, beta, cfg)
+            got = dy.cpu().numpy()
+            ref = orc.spmv(A, x, alpha, beta, y0)
+            if integer:
+                assert np.array_equal(got, ref), (name, cid, alpha, beta)
+            else:
+                bound = spmv_bound(orc, A, x, alpha, beta, y0, U64)
+                assert np.all(np.abs(got - ref) <= bound), (name, cid, alpha, beta)
+                normA = np.max(orc.spmv(M.CSR(A.n, A.ncols, A.rp, A.col, np.abs(A.val)),
+                                        np.ones(A.ncols)), initial=0.0)
+                err = np.max(np.abs(got - ref), initial=0.0)
+                assert err <= 1e-13 * (abs(alpha) * normA * np.max(np.abs(x), initial=0.0)
+                                       + abs(beta) * np.max(np.abs(y0), initial=0.0)) + 1e-300
+        # determinism: same inputs, same bits
+        d1 = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        d2 = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        ck.spmv_apply(Mx.handle, dx, d1, 1.0, 0.0, cfg)
+        ck.spmv_apply(Mx.handle, dx, d2, 1.0, 0.0, cfg)
+        assert torch.equal(d1, d2)
+    Mx.close()
+
+
+@pytest.mark.parametrize("name", ["int_ragged", "powerlaw", "banded27", "uniform", "empty",
+                                  "single_row"])
+def test_spmv_all_configs_fp32(ck, orc, name):
+    import torch
+    A = case(name)
+    rng = np.random.default_rng(8)
+    integer = is_int(A)
+    x = rng.integers(-8, 9, A.ncols).astype(float) if integer else rng.uniform(-1, 1, A.ncols)
+    y0 = rng.integers(-8, 9, A.n).astype(float) if integer else rng.uniform(-1, 1, A.n)
+    x32, y32 = x.astype(np.float32), y0.astype(np.float32)
+    A32 = M.CSR(A.n, A.ncols, A.rp, A.col, A.val.astype(np.float32).astype(np.float64))
+    Mx = ck.Matrix.from_csr(A, keep_fp32=True)
+    dx = torch.from_numpy(x32).cuda()
+    for cid in range(ck.NUM_CONFIGS):
+        cfg = ck.config_from_id(cid)
+        say(f"spmv32 {name} config={ck.CONFIG_NAMES[cid]}")
+        try:
+            ck.spmv_convert(Mx.handle, cfg)
+        except ck.CkError as e:
+            assert cid == 9 and e.status == ck.CK_E_UNSUPPORTED
+            continue
+        dy = torch.from_numpy(y32).cuda()
+        ck.spmv_apply_f32(Mx.handle, dx, dy, -0.5, 2.0, cfg)
+        got = dy.cpu().numpy().astype(np.float64)
+        ref = orc.spmv(A32, x32.astype(np.float64), -0.5, 2.0, y32.astype(np.float64))
+        if integer:
+            assert np.array_equal(got, ref)
+        else:
+            bound = spmv_bound(orc, A32, x32.astype(np.float64), -0.5, 2.0,
+                               y32.astype(np.float64), U32, k_extra=3)
+            assert np.all(np.abs(got - ref) <= bound), (name, cid)
+    Mx.close()
+
+
+@pytest.mark.parametrize("name", ["int_ragged", "int_wide", "powerlaw", "banded27", "blockdiag",
+                                  "uniform", "lap2d_64", "convdiff", "empty", "one_by_one",
+                                  "single_row", "single_col"])
+def test_features_bit_exact(ck, orc, name):
+    A = case(name)
+    say(f"features {name}")
+    Mx = ck.Matrix.from_csr(A)
+    F = ck.spmv_features(Mx.handle)
+    ints, der, f15 = orc.features(A)
+    assert F.ints() == [int(v) for v in ints], name
+    got = np.array(F.derived())
+    assert np.array_equal(got.view(np.int64), der.view(np.int64)), (name, got, der)
+    assert np.array_equal(np.array(F.model_inputs()), f15)
+    Mx.close()
+
+
+def test_symmetric_flag(ck, orc):
+    for A in [M.laplacian_2d(30), M.graph_laplacian_chung_lu(5000, 11, wmax=500),
+              M.convection_diffusion_2d(30), M.diagonally_dominant(M.uniform_random(3000, 2))]:
+        say(f"symmetry {A.name}")
+        Mx = ck.Matrix.from_csr(A)
+        assert ck.spmv_features(Mx.handle).is_symmetric == orc.features(A)[0][27]
+        Mx.close()
+
+
+@pytest.mark.parametrize("name", ["int_ragged", "banded27", "blockdiag", "lap2d_64", "convdiff",
+                                  "single_col", "one_by_one"])
+def test_ell_conversion_bit_exact(ck, orc, name):
+    A = case(name)
+    say(f"ell {name}")
+    st, K, pitch, ec, ev = orc.to_ell(A)
+    Mx = ck.Matrix.from_csr(A)
+    if st != orc.OK:
+        with pytest.raises(ck.CkError):
+            ck.spmv_convert(Mx.handle, ck.config_from_id(9))
+        return
+    ck.spmv_convert(Mx.handle, ck.config_from_id(9))
+    gK, gp, gc, gv = ck.export_ell(Mx.handle)
+    assert (gK, gp) == (K, pitch)
+    assert np.array_equal(gc.cpu().numpy(), ec)
+    assert np.array_equal(gv.cpu().numpy().view(np.int64), ev.view(np.int64))   # +0.0 padding
+    Mx.close()
+
+
+def test_ell_refused_like_oracle(ck, orc):
+    A = case("powerlaw")
+    assert orc.ell_shape(A)[0] == orc.UNSUPPORTED
+    Mx = ck.Matrix.from_csr(A)
+    with pytest.raises(ck.CkError) as e:
+        ck.spmv_convert(Mx.handle, ck.config_from_id(9))
+    assert e.value.status == ck.CK_E_UNSUPPORTED
+    Mx.close()
+
+
+@pytest.mark.parametrize("name", ["int_ragged", "powerlaw", "uniform", "empty", "single_col"])
+def test_coo_conversion_bit_exact(ck, orc, name):
+    A = case(name)
+    say(f"coo {name}")
+    Mx = ck.Matrix.from_csr(A)
+    ck.spmv_convert(Mx.handle, ck.config_from_id(10))
+    got = ck.export_coo_rows(Mx.handle, A.nnz).cpu().numpy()
+    assert np.array_equal(got, orc.to_coo_rows(A))
+    Mx.close()
+
+
+def test_cascade_decisions_match_oracle(ck, orc, tmp_path):
+    """Same features + same model -> same decisions (shipped model and a
+    freshly fitted sklearn model)."""
+    from sklearn.tree import DecisionTreeClassifier
+    mats = [case(n) for n in ["int_ragged", "powerlaw", "banded27", "blockdiag", "uniform",
+                              "lap2d_64", "convdiff"]]
+    feats = []
+    for A in mats:
+        Mx = ck.Matrix.from_csr(A)
+        feats.append(ck.spmv_features(Mx.handle))
+        Mx.close()
+    trees = parse_model(MODEL)
+    for F, A in zip(feats, mats):
+        _, _, f15 = orc.features(A)
+        assert ck.select_stages(F) == orc.cascade(trees, f15)
+    # a model fitted here on oracle features with arbitrary labels
+    X = np.array([orc.features(A)[2] for A in mats] * 3)
+    X = X * np.repeat([1.0, 0.5, 2.0], len(mats))[:, None]
+    y1 = np.arange(len(X)) % 3
+    y2 = (np.arange(len(X)) // 2) % 3
+    y3 = np.arange(len(X)) % 7
+    fitted = [sk_tree(DecisionTreeClassifier(random_state=0).fit(X, y)) for y in (y1, y2, y3)]
+    path = str(tmp_path / "m.txt")
+    write_model(path, fitted)
+    for F, A in zip(feats, mats):
+        _, _, f15 = orc.features(A)
+        assert ck.select_stages(F, path) == orc.cascade(fitted, f15)
+
+
+def test_dot_deterministic_and_accurate(ck):
+    import torch
+    for n in [0, 1, 1000, 1 << 20, 3_000_001]:
+        say(f"dot n={n}")
+        rng = np.random.default_rng(n)
+        x, y = rng.standard_normal(n), rng.standard_normal(n)
+        dx, dy = torch.from_numpy(x).cuda(), torch.from_numpy(y).cuda()
+        o1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        o2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ck.dot(dx, dy, o1)
+        ck.dot(dx, dy, o2)
+        assert torch.equal(o1, o2)
+        ref = float(np.dot(x, y))
+        assert abs(o1.item() - ref) <= 1e-14 * max(1.0, float(np.dot(np.abs(x), np.abs(y))))
+
+
+def test_invalid_csr_rejected(ck):
+    import torch
+    A = M.laplacian_1d(10)
+    rp, col, val = upload(A)
+    bad = col.clone()
+    bad[3], bad[4] = col[4], col[3]
+    with pytest.raises(ck.CkError) as e:
+        ck.spmv_create(rp, bad, val)
+    assert e.value.status == ck.CK_E_INVALID
+    bad = col.clone()
+    bad[0] = 10
+    with pytest.raises(ck.CkError):
+        ck.spmv_create(rp, bad, val)
+    badrp = rp.clone()
+    badrp[5] = rp[7]                      # row pointers not monotone
+    with pytest.raises(ck.CkError):
+        ck.spmv_create(badrp, col, val)

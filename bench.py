@@ -1,0 +1,547 @@
+#!/usr/bin/env python3
+"""Benchmark of the SpMV + Krylov hot path on one MI355X.
+
+Default workload ("spmv_set"): the 48 held-out synthetic FP64 matrices (four
+families x twelve sizes, n = 1e4 .. 2e6).  One step runs the method's whole
+SpMV path on every matrix: ingest (copy + validate), GPU features, cascaded
+prediction, format conversion when the prediction asks for it, then 200
+products with the predicted kernel (the paper times configurations as the
+mean of 200 runs).  value = algorithmic bytes of all those products / step
+time, in GB/s.
+
+Untimed, the same run measures every configuration on every matrix (warm,
+200 products each) to report predicted vs exhaustive-best vs default CSR-vector,
+times the predicted / best / default kernels cold (cache flushed) on the
+matrices whose product moves >= 512 MB, and times the CPU oracle on one
+product per matrix.
+
+Other workloads (--workload): cg_lap2d (CG, 64x64 Laplacian), cg_async (async
+CG on 3D Poisson 128^3 and a 2^20-row power-law graph Laplacian),
+gmres_mixed (mixed vs FP64 GMRES(30), convection-diffusion 1024^2), serve
+(request loop).  Each prints one JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SpMV HBM GB/s (predicted vs best vs CSR); CG/GMRES solves/s + p99 @1e-10"
+HBM_PEAK_GBS = 8000.0
+LARGE_BYTES = 512 * 2 ** 20
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class KernelLedger:
+    """Event-timed batches of SpMV launches, per device kernel symbol, over the
+    whole process (so the per-launch average matches a profiler's)."""
+
+    def __init__(self):
+        self.k = {}
+
+    def add(self, name, launches, us_per_launch, bytes_per_launch):
+        e = self.k.setdefault(name, [0, 0.0, 0.0])
+        e[0] += launches
+        e[1] += launches * us_per_launch
+        e[2] += launches * bytes_per_launch
+
+    def summary(self, name):
+        n, us, by = self.k[name]
+        return dict(launches=n, avg_us=us / n, achieved_GBs=by / (us * 1e3))
+
+
+def flush_cache(buf):
+    buf.fill_(1.0)   # 1 GiB streaming write evicts the 256 MB last-level cache
+
+
+def geomean(v):
+    v = [x for x in v if x > 0 and math.isfinite(x)]
+    return math.exp(sum(math.log(x) for x in v) / len(v)) if v else float("nan")
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, if
+    it was taken for this kernel (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        return d.get(kernel)
+    except Exception:
+        return None
+
+
+# ---------------------------------------------------------------------------
+def bench_spmv_set(args):
+    import torch
+
+    import paper_2411_10143_amd as ck
+    from synth import workloads as W
+
+    torch.cuda.set_device(0)
+    specs = W.spmv_set_specs(max_n=args.max_n)
+    mats, dev = [], []
+    t0 = time.time()
+    for i, spec in enumerate(specs):
+        A = W.spmv_set_matrix(spec)
+        mats.append(A)
+        dev.append(dict(rp=torch.from_numpy(A.rp).cuda(), col=torch.from_numpy(A.col).cuda(),
+                        val=torch.from_numpy(A.val).cuda(),
+                        x=torch.from_numpy(np.random.default_rng(spec[4]).uniform(-1, 1, A.ncols)).cuda(),
+                        y=torch.zeros(A.n, dtype=torch.float64, device="cuda")))
+        log(f"[gen {i + 1}/{len(specs)}] {A.name} n={A.n} nnz={A.nnz} ({time.time() - t0:.0f}s)")
+    nbytes = [A.nnz * 12 + 4 * (A.n + 1) + 8 * A.ncols + 8 * A.n for A in mats]
+    ledger = KernelLedger()
+    R = args.reps
+
+    # ---- exhaustive table (warm, every configuration) -----------------------
+    T = np.full((len(mats), ck.NUM_CONFIGS), np.inf)
+    default_id = []
+    for m, (A, d) in enumerate(zip(mats, dev)):
+        Mx = ck.Matrix(d["rp"], d["col"], d["val"], A.ncols)
+        default_id.append(ck.config_id(ck.default_config(Mx.handle)))
+        for cid in range(ck.NUM_CONFIGS):
+            cfg = ck.config_from_id(cid)
+            try:
+                ck.spmv_convert(Mx.handle, cfg)
+            except ck.CkError as e:
+                if e.status != ck.CK_E_UNSUPPORTED:
+                    raise
+                continue
+            us = ck.time_spmv(Mx.handle, cfg, d["x"], d["y"], warmup=10, reps=R)
+            T[m, cid] = us
+            ledger.add(ck.kernel_name(cfg), R, us, nbytes[m])
+        Mx.close()
+        log(f"[table {m + 1}/{len(mats)}] {A.name} best={ck.CONFIG_NAMES[int(np.argmin(T[m]))]}"
+            f" {T[m].min():.2f}us default={T[m, default_id[-1]]:.2f}us")
+
+    # ---- timed steps: ingest -> features -> select -> convert -> R products ---
+    def one_step(record):
+        picks, spmv_us = [], 0.0
+        for m, (A, d) in enumerate(zip(mats, dev)):
+            Mx = ck.Matrix(d["rp"], d["col"], d["val"], A.ncols)
+            F = ck.spmv_features(Mx.handle)
+            cfg = ck.spmv_select(F)
+            try:
+                ck.spmv_convert(Mx.handle, cfg)
+            except ck.CkError as e:
+                if e.status != ck.CK_E_UNSUPPORTED:
+                    raise
+                cfg = ck.default_config(Mx.handle)   # refused conversion: keep the default
+            us = ck.time_spmv(Mx.handle, cfg, d["x"], d["y"], warmup=0, reps=R)
+            spmv_us += us * R
+            if record:
+                ledger.add(ck.kernel_name(cfg), R, us, nbytes[m])
+            picks.append(ck.config_id(cfg))
+            Mx.close()
+        return picks, spmv_us
+
+    for _ in range(args.warmup):
+        one_step(False)
+    torch.cuda.synchronize()
+    step_times, spmv_totals, picks = [], [], None
+    for s in range(args.steps):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        picks, spmv_us = one_step(True)
+        torch.cuda.synchronize()
+        step_times.append(time.perf_counter() - ts)
+        spmv_totals.append(spmv_us)
+        log(f"[step {s + 1}/{args.steps}] {step_times[-1] * 1e3:.1f} ms")
+    bytes_step = R * sum(nbytes)
+    value = bytes_step * len(step_times) / sum(step_times) / 1e9
+
+    # ---- predicted vs best vs default from the exhaustive table -------------
+    best = T.min(axis=1)
+    t_pred = np.array([T[m, p] for m, p in enumerate(picks)])
+    t_def = np.array([T[m, default_id[m]] for m in range(len(mats))])
+    ratio = t_pred / best
+    agg = lambda t: float(sum(nbytes) / (np.sum(t) * 1e3))   # GB/s over the set
+    # per-kernel totals inside the timed steps decide the dominant kernel
+    timed = {}
+    for m, p in enumerate(picks):
+        name = ck.kernel_name(ck.config_from_id(p))
+        timed[name] = timed.get(name, 0.0) + T[m, p]
+    dominant = max(timed, key=timed.get)
+    ks = ledger.summary(dominant)
+
+    # ---- cold products on the large matrices ---------------------------------
+    cold = []
+    flushbuf = torch.empty(2 ** 27, dtype=torch.float64, device="cuda")
+    for m, (A, d) in enumerate(zip(mats, dev)):
+        if nbytes[m] < LARGE_BYTES:
+            continue
+        Mx = ck.Matrix(d["rp"], d["col"], d["val"], A.ncols)
+        row = dict(matrix=A.name, MB=round(nbytes[m] / 1e6, 1))
+        for label, cid in (("predicted", picks[m]), ("best", int(np.argmin(T[m]))),
+                           ("default", default_id[m])):
+            cfg = ck.config_from_id(cid)
+            ck.spmv_convert(Mx.handle, cfg)
+            ts = []
+            for _ in range(5):
+                flush_cache(flushbuf)
+                ts.append(ck.time_spmv(Mx.handle, cfg, d["x"], d["y"], warmup=0, reps=1))
+            us = float(np.median(ts))
+            row[label] = dict(config=ck.CONFIG_NAMES[cid], us=round(us, 2),
+                              GBs=round(nbytes[m] / (us * 1e3), 1),
+                              frac=round(nbytes[m] / (us * 1e3) / HBM_PEAK_GBS, 3))
+        cold.append(row)
+        Mx.close()
+    del flushbuf
+
+    # ---- achievable copy bandwidth (same box) ---------------------------------
+    a = torch.empty(2 ** 28, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    e1.synchronize()
+    copy_gbs = 10 * 2 * a.numel() * 8 / (e0.elapsed_time(e1) * 1e6)
+    del a, b
+
+    # ---- CPU oracle baseline ---------------------------------------------------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        xs = [d["x"].cpu().numpy() for d in dev]
+        tc = time.perf_counter()
+        for A, x in zip(mats, xs):
+            oracle.spmv(A, x)
+        dt = time.perf_counter() - tc
+        cpu = dict(value=round(sum(nbytes) / dt / 1e9, 3), unit="GB/s", cores=1, kind="oracle",
+                   sample=f"one FP64 product per matrix of the {len(mats)}-matrix set "
+                          f"({sum(nbytes) / 1e9:.2f} GB algorithmic), single-threaded plain C, "
+                          f"{dt:.1f} s; host has {os.cpu_count()} logical CPUs")
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * sum(step_times) / len(step_times), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"spmv_set_{len(mats)}: banded/power-law/block-diagonal/"
+                               f"uniform-random FP64, n 1e4-2e6, int32 CSR; per matrix ingest + "
+                               f"GPU features + cascade + conversion + {R} products",
+                   "matrices": len(mats), "products_per_matrix": R,
+                   "algorithmic_GB_per_step": round(bytes_step / 1e9, 3)},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(ks["achieved_GBs"], 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ks["achieved_GBs"] / HBM_PEAK_GBS, 4),
+                     "avg_us": round(ks["avg_us"], 3), "launches": ks["launches"],
+                     "traffic": traffic_for(dominant)},
+        "cpu_baseline": cpu,
+        "spmv": {
+            "predicted_GBs": round(agg(t_pred), 1), "best_GBs": round(agg(best), 1),
+            "default_csr_vector_GBs": round(agg(t_def), 1),
+            "geomean_t_pred_over_t_best": round(geomean(ratio), 4),
+            "geomean_t_default_over_t_best": round(geomean(t_def / best), 4),
+            "picked_best": int(np.sum(ratio <= 1.0)), "within_10pct": int(np.sum(ratio <= 1.10)),
+            "of": len(mats),
+            "kernel_GBs_in_steps": round(bytes_step / (np.mean(spmv_totals) * 1e3), 1),
+            "copy_GBs": round(copy_gbs, 1), "cold_large": cold,
+        },
+    }
+    if args.table:
+        rows = []
+        for m, A in enumerate(mats):
+            rows.append(dict(matrix=A.name, n=A.n, nnz=A.nnz, MB=round(nbytes[m] / 1e6, 2),
+                             times_us=[None if not math.isfinite(v) else round(v, 3) for v in T[m]],
+                             predicted=ck.CONFIG_NAMES[picks[m]],
+                             best=ck.CONFIG_NAMES[int(np.argmin(T[m]))],
+                             default=ck.CONFIG_NAMES[default_id[m]]))
+        with open(args.table, "w") as f:
+            json.dump(rows, f, indent=1)
+    print(json.dumps(out), flush=True)
+
+
+# ---------------------------------------------------------------------------
+# Solver workloads.  The solve is timed from the call to the result on the
+# host, with the matrix resident; `roofline` reports the effective bandwidth
+# of the iteration (algorithmic bytes of all iterations / solve time).
+
+def _solve_json(args, value, unit, ms_per_step, workload, extra, roof, cpu, dtype="f64"):
+    out = {"metric": METRIC, "value": round(value, 3), "unit": unit, "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
+           "data": "synthetic", "config": dict(workload=workload, **extra.pop("config", {})),
+           "roofline": roof, "cpu_baseline": cpu}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def _cg_iter_bytes(A, s=8):
+    # fused CG iteration: SpMV (+p.Ap) then x,r update (+r.r) then p update
+    return A.nnz * (s + 4) + 4 * (A.n + 1) + 2 * s * A.n + 6 * s * A.n + 3 * s * A.n
+
+
+def _gmres_iter_bytes(A, m=30, s=8):
+    # SpMV, three Gram-Schmidt passes over j+1 basis columns (average m/2 + 1),
+    # normalisation; per-cycle residual and update terms amortised over m
+    spmv = A.nnz * (s + 4) + 4 * (A.n + 1) + 2 * s * A.n
+    cols = m / 2.0 + 1.0
+    return spmv + s * A.n * (3 * cols + 2 + 2 + 1 + 2 + 2) + (8 * A.n * (4 + m)) / m
+
+
+def _upload(A):
+    import torch
+    return (torch.from_numpy(A.rp).cuda(), torch.from_numpy(A.col).cuda(),
+            torch.from_numpy(A.val).cuda())
+
+
+def _rhs(ck, Mx, xs):
+    import torch
+    dx = torch.from_numpy(xs).cuda()
+    b = torch.zeros_like(dx)
+    ck.spmv_apply(Mx.handle, dx, b)
+    return b
+
+
+def bench_cg_lap2d(args):
+    import torch
+
+    import paper_2411_10143_amd as ck
+    from synth import workloads as W
+    A, xs = W.lap2d_64()
+    Mx = ck.Matrix.from_csr(A)
+    b = _rhs(ck, Mx, xs)
+    per_step = 20
+    lat, iters = [], []
+    for s in range(args.warmup + args.steps):
+        for _ in range(per_step):
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = ck.cg_solve(Mx.handle, b, x, tol=1e-10)
+            dt = time.perf_counter() - t
+            assert r["status"] == ck.CK_OK and r["true_relres"] <= 1e-10, r
+            if s >= args.warmup:
+                lat.append(dt)
+                iters.append(r["iterations"])
+    total = sum(lat)
+    eff = float(np.mean(iters)) * _cg_iter_bytes(A) / (total / len(lat)) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        bh = b.cpu().numpy()
+        tc = time.perf_counter()
+        n = 0
+        while time.perf_counter() - tc < 2.0:
+            oracle.cg(A, bh, tol=1e-10)
+            n += 1
+        dt = time.perf_counter() - tc
+        cpu = dict(value=round(n / dt, 2), unit="solves/s", cores=1, kind="oracle",
+                   sample=f"{n} complete oracle CG solves of the same system")
+    _solve_json(args, len(lat) / total, "solves/s", 1e3 * total / args.steps,
+                "cg_lap2d_64: FP64 CG, 2D 5-point Laplacian 64x64 (n=4096), default "
+                "CSR-vector, tol 1e-10",
+                {"latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
+                                "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
+                 "iterations": int(np.median(iters)), "solves": len(lat)},
+                {"bound": "hbm", "kernel": "cg_iteration (fused SpMV + 2 vector kernels)",
+                 "achieved": round(eff, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(eff / HBM_PEAK_GBS, 5), "traffic": None,
+                 "note": "n=4096: the whole system sits in cache; launch-latency bound"}, cpu)
+
+
+def _best_fixed_config(ck, Mx, A):
+    import torch
+    x = torch.ones(A.ncols, dtype=torch.float64, device="cuda")
+    y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    best, tb = None, math.inf
+    for cid in range(ck.NUM_CONFIGS):
+        cfg = ck.config_from_id(cid)
+        try:
+            ck.spmv_convert(Mx.handle, cfg)
+        except ck.CkError:
+            continue
+        t = ck.time_spmv(Mx.handle, cfg, x, y, warmup=5, reps=50)
+        if t < tb:
+            best, tb = cid, t
+    return best, tb
+
+
+def bench_cg_async(args):
+    import torch
+
+    import oracle
+    import paper_2411_10143_amd as ck
+    from synth import workloads as W
+    problems = [("poisson3d_128", *W.poisson3d_128()),
+                ("graph_laplacian_2^20", *W.graph_laplacian_1m())]
+    rows, tot_time, tot_solves, tot_bytes = [], 0.0, 0, 0.0
+    for name, A, xs in problems:
+        log(f"[cg_async] {name} n={A.n} nnz={A.nnz}")
+        rp, col, val = _upload(A)
+        probe = ck.Matrix(rp, col, val)
+        b = _rhs(ck, probe, xs)
+        best_id, _ = _best_fixed_config(ck, probe, A)
+        probe.close()
+        res = {"async": [], "default": [], "best_fixed": []}
+        for s in range(args.warmup + args.steps):
+            for mode in res:
+                Mx = ck.Matrix(rp, col, val)        # fresh handle: nothing cached
+                kw = {}
+                if mode == "async":
+                    kw["async_"] = True
+                elif mode == "best_fixed":
+                    kw["config"] = ck.config_from_id(best_id)
+                    ck.spmv_convert(Mx.handle, kw["config"])
+                x = torch.zeros_like(b)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                r = ck.cg_solve(Mx.handle, b, x, tol=1e-10, **kw)
+                dt = time.perf_counter() - t
+                assert r["status"] == ck.CK_OK, (name, mode, r)
+                if s >= args.warmup:
+                    r["wall_s"] = dt
+                    if mode == "async":
+                        r["oracle_relres"] = oracle.relres(A, b.cpu().numpy(), x.cpu().numpy())
+                        r["forward_error"] = float(np.linalg.norm(x.cpu().numpy() - xs) /
+                                                   np.linalg.norm(xs))
+                    res[mode].append(r)
+                Mx.close()
+        a = res["async"]
+        t_async = sum(r["wall_s"] for r in a)
+        tot_time += t_async
+        tot_solves += len(a)
+        tot_bytes += sum(r["iterations"] for r in a) * _cg_iter_bytes(A)
+        rows.append({"problem": name, "n": A.n, "nnz": A.nnz,
+                     "async_solves_per_s": round(len(a) / t_async, 3),
+                     "default_solves_per_s": round(len(res["default"]) / sum(r["wall_s"] for r in res["default"]), 3),
+                     "best_fixed_solves_per_s": round(len(res["best_fixed"]) / sum(r["wall_s"] for r in res["best_fixed"]), 3),
+                     "best_fixed_config": ck.CONFIG_NAMES[best_id],
+                     "iterations": a[-1]["iterations"], "switch_iter": a[-1]["switch_iter"],
+                     "final_config": ck.CONFIG_NAMES[a[-1]["final_config"]],
+                     "t_features_us": round(a[-1]["t_features_us"], 1),
+                     "t_infer_us": round(a[-1]["t_infer_us"], 2),
+                     "t_convert_us": round(a[-1]["t_convert_us"], 1),
+                     "true_relres": a[-1]["true_relres"], "oracle_relres": a[-1]["oracle_relres"],
+                     "forward_error": a[-1]["forward_error"],
+                     "latency_ms": {"p50": round(1e3 * float(np.percentile([r["wall_s"] for r in a], 50)), 3),
+                                    "p99": round(1e3 * float(np.percentile([r["wall_s"] for r in a], 99)), 3)}})
+        del rp, col, val, b
+    eff = tot_bytes / tot_time / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        A, xs = problems[0][1], problems[0][2]
+        bh = oracle.spmv(A, xs)
+        k = 20
+        tc = time.perf_counter()
+        oracle.cg(A, bh, tol=1e-30, maxit=k)
+        dt = (time.perf_counter() - tc) / k
+        it = rows[0]["iterations"]
+        cpu = dict(value=round(1.0 / (dt * it), 5), unit="solves/s", cores=1, kind="oracle",
+                   sample=f"{k} oracle CG iterations on poisson3d_128 ({dt * 1e3:.1f} ms each), "
+                          f"scaled to the {it} iterations of a full solve")
+    _solve_json(args, tot_solves / tot_time, "solves/s", 1e3 * tot_time / args.steps,
+                "cg_async: async FP64 CG, tol 1e-10, on 3D Poisson 128^3 (n=2,097,152) and a "
+                "Chung-Lu power-law graph Laplacian + 1e-2 I (n=2^20, mean degree 16)",
+                {"problems": rows},
+                {"bound": "hbm", "kernel": "cg_iteration (fused SpMV + 2 vector kernels)",
+                 "achieved": round(eff, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(eff / HBM_PEAK_GBS, 4), "traffic": None}, cpu)
+
+
+def bench_gmres_mixed(args):
+    import torch
+
+    import oracle
+    import paper_2411_10143_amd as ck
+    from synth import workloads as W
+    A, xs = W.convdiff_1024(args.grid)
+    log(f"[gmres_mixed] n={A.n} nnz={A.nnz}")
+    Mx = ck.Matrix.from_csr(A, keep_fp32=True)
+    b = _rhs(ck, Mx, xs)
+    res = {"mixed": [], "fp64": []}
+    for s in range(args.warmup + args.steps):
+        for mode in res:
+            x = torch.zeros_like(b)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            r = ck.gmres_solve(Mx.handle, b, x, tol=1e-10, restart=30, max_iter=200000,
+                               precision=ck.CK_PREC_MIXED if mode == "mixed" else ck.CK_PREC_FP64)
+            dt = time.perf_counter() - t
+            assert r["status"] == ck.CK_OK, (mode, r)
+            log(f"[gmres_mixed] {mode} {dt:.3f}s it={r['iterations']} relres={r['true_relres']:.2e}")
+            if s >= args.warmup:
+                xh = x.cpu().numpy()
+                r["wall_s"] = dt
+                r["oracle_relres"] = oracle.relres(A, b.cpu().numpy(), xh)
+                r["forward_error"] = float(np.linalg.norm(xh - xs) / np.linalg.norm(xs))
+                res[mode].append(r)
+    tm = sum(r["wall_s"] for r in res["mixed"])
+    t64 = sum(r["wall_s"] for r in res["fp64"])
+    mixed_sps, fp64_sps = len(res["mixed"]) / tm, len(res["fp64"]) / t64
+    rm, r64 = res["mixed"][-1], res["fp64"][-1]
+    eff = rm["iterations"] * _gmres_iter_bytes(A, 30, 4) / (tm / len(res["mixed"])) / 1e9
+    cpu = None
+    if not args.no_cpu_baseline:
+        bh = b.cpu().numpy()
+        k = 60
+        tc = time.perf_counter()
+        oracle.gmres(A, bh, m=30, tol=1e-30, maxit=k)
+        dt = (time.perf_counter() - tc) / k
+        cpu = dict(value=round(1.0 / (dt * r64["iterations"]), 6), unit="solves/s", cores=1,
+                   kind="oracle",
+                   sample=f"{k} oracle FP64 GMRES(30) iterations ({dt * 1e3:.1f} ms each), scaled "
+                          f"to the {r64['iterations']} iterations of the GPU FP64 solve")
+    keep = ("iterations", "outer_steps", "true_relres", "oracle_relres", "forward_error")
+    _solve_json(args, mixed_sps, "solves/s", 1e3 * (tm + t64) / args.steps,
+                f"gmres_mixed: GMRES(30), 2D convection-diffusion {args.grid}^2 upwind, "
+                "Peclet 10, tol 1e-10; mixed FP32 inner / FP64 refinement vs plain FP64",
+                {"mixed": {**{k: rm[k] for k in keep}, "solves_per_s": round(mixed_sps, 4)},
+                 "fp64": {**{k: r64[k] for k in keep}, "solves_per_s": round(fp64_sps, 4)},
+                 "mixed_speedup": round(mixed_sps / fp64_sps, 3)},
+                {"bound": "hbm", "kernel": "mixed gmres_iteration (SpMV + CGS2 passes)",
+                 "achieved": round(eff, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                 "frac": round(eff / HBM_PEAK_GBS, 4), "traffic": None}, cpu, dtype="f32+f64")
+
+
+def bench_serve(args):
+    raise SystemExit("serve workload: see paper_2411_10143_amd.serving")
+
+
+# ---------------------------------------------------------------------------
+def main():
+    p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=5)
+    p.add_argument("--warmup", type=int, default=1)
+    p.add_argument("--workload", default="spmv_set",
+                   choices=["spmv_set", "cg_lap2d", "cg_async", "gmres_mixed", "serve"])
+    p.add_argument("--reps", type=int, default=200)
+    p.add_argument("--max-n", type=int, default=None, help="drop set members above this n")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--table", default=None, help="write the per-matrix timing table (JSON)")
+    p.add_argument("--grid", type=int, default=1024, help="gmres_mixed grid side")
+    args = p.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build runs on a single MI355X (the serving and "
+              "solver paths shard by request, not across GPUs); use --gpus 1.", file=sys.stderr)
+        return 2
+    {"spmv_set": bench_spmv_set, "cg_lap2d": bench_cg_lap2d, "cg_async": bench_cg_async,
+     "gmres_mixed": bench_gmres_mixed, "serve": bench_serve}[args.workload](args)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -237,6 +237,80 @@ ck_status ck_kernel_name(const ck_config *cfg, int32_t fp32, char *buf, size_t c
  * s = 8 (FP64) or 4 (FP32).  Format padding is not counted. */
 int64_t ck_spmv_bytes(ck_handle h, int32_t fp32, int32_t beta_nonzero);
 
+/* ck_time_spmv -- the offline timing protocol (Section III-B-2: the time of
+ * a configuration is the mean over repeated products): enqueue `warmup`
+ * products, then `reps` products y = A x (alpha = 1, beta = 0) back to back
+ * with configuration cfg on stream s, bracketed by HIP events recorded on s.
+ * fp32 = 1 uses the FP32 values and float vectors.  Blocks; *us_per_call is
+ * the mean microseconds per product over the reps.  The format must have
+ * been converted (spmv_convert). */
+ck_status ck_time_spmv(ck_handle h, const ck_config *cfg, int32_t fp32, const void *d_x,
+                       void *d_y, int32_t warmup, int32_t reps, hipStream_t s,
+                       double *us_per_call);
+
+/* ---- Request loop (serving) ----------------------------------------------
+ * Solve requests on a pool of registered matrices, processed by a scheduler
+ * thread inside the library.  This is the iterative-solver use of the
+ * method with many right-hand sides and matrices arriving over time: every
+ * matrix gets its features and cascaded prediction once (then cached), stays
+ * resident in device memory while the budget allows (least-recently-used
+ * idle matrices are evicted), and its requests run either in a slot of a
+ * batched kernel (n <= small_n: one workgroup per system, chunk_iters
+ * iterations per launch, new requests joining between launches) or as a
+ * full cg_solve / gmres_solve on a worker stream.  Symmetric matrices are
+ * solved with CG, the others with GMRES(restart).  x0 = 0. */
+typedef struct ck_server *ck_server_t;
+
+typedef struct {
+    int64_t budget_bytes;    /* device memory for resident matrices + workspaces   */
+    int32_t max_slots;       /* batched slots (<= 4096)                             */
+    int32_t chunk_iters;     /* iterations per slot per batched launch              */
+    int32_t small_n;         /* systems with n <= small_n use the batched path      */
+    int32_t large_workers;   /* concurrent large solves (1..16), one stream each    */
+    int32_t precision;       /* CK_PREC_MIXED (FP32 inner, FP64 refinement) or FP64 */
+    int32_t restart;         /* GMRES m (the batched path caps it at 32)            */
+    int32_t max_iter;        /* per request; <= 0 means 100000                      */
+    double tol;              /* ||b - A x|| / ||b|| target                          */
+} ck_server_opts;
+
+typedef struct {
+    int64_t tag;             /* the caller's tag from ck_server_submit              */
+    int32_t matrix_id, status, iterations;
+    int32_t path;            /* 0 batched slot, 1 worker-stream solve               */
+    int32_t config_id;       /* cached configuration of the matrix (ck_config_id)   */
+    int32_t pad;
+    double true_relres;      /* FP64 relative residual at exit                      */
+    double t_submit_us, t_admit_us, t_done_us;   /* ck_server_clock_us() times     */
+} ck_completion;
+
+typedef struct {
+    int64_t submitted, completed, queued, in_flight, resident_matrices, evictions,
+        bytes_in_use, batched_launches, prediction_cache_hits, prediction_cache_misses;
+} ck_server_stats;
+
+/* ck_server_create -- start a request loop on the current device. */
+ck_status ck_server_create(const ck_server_opts *opts, ck_server_t *out);
+/* ck_server_add_matrix -- register a square CSR matrix under `id`.  The
+ * device arrays stay owned by the caller and must outlive the server (an
+ * evicted matrix is re-ingested from them). */
+ck_status ck_server_add_matrix(ck_server_t s, int32_t id, int64_t n, int64_t nnz,
+                               const int32_t *d_rowptr, const int32_t *d_col,
+                               const double *d_val);
+/* ck_server_submit -- enqueue a solve of A_id x = b; returns at once.  d_b and
+ * d_x (n doubles each) must stay valid until the completion is polled. */
+ck_status ck_server_submit(ck_server_t s, int32_t matrix_id, const double *d_b, double *d_x,
+                           int64_t tag);
+/* ck_server_poll -- move up to cap completions into out; returns the count. */
+int32_t ck_server_poll(ck_server_t s, ck_completion *out, int32_t cap);
+/* ck_server_drain -- wait until every submitted request has completed. */
+ck_status ck_server_drain(ck_server_t s, double timeout_s);
+ck_status ck_server_get_stats(ck_server_t s, ck_server_stats *out);
+/* ck_server_clock_us -- microseconds since the server was created. */
+double ck_server_clock_us(ck_server_t s);
+/* ck_server_destroy -- stop the loop, free everything (pending requests are
+ * dropped). */
+void ck_server_destroy(ck_server_t s);
+
 /* ck_last_error -- message for the last non-OK status on this thread. */
 const char *ck_last_error(void);
 

@@ -41,8 +41,12 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build(force=False)
-        _lib = C.CDLL(_LIB)
+        alt = os.environ.get("ORACLE_LIB")   # a separately built variant (mutation tests)
+        if alt:
+            _lib = C.CDLL(alt)
+        else:
+            build(force=False)
+            _lib = C.CDLL(_LIB)
         _declare(_lib)
     return _lib
 

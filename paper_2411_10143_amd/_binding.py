@@ -86,6 +86,33 @@ class SolveResult(C.Structure):
                     t_total_us=self.t_total_us, final_config=config_id(self.final_config))
 
 
+class ServerOpts(C.Structure):
+    _fields_ = [("budget_bytes", C.c_int64), ("max_slots", C.c_int32),
+                ("chunk_iters", C.c_int32), ("small_n", C.c_int32),
+                ("large_workers", C.c_int32), ("precision", C.c_int32),
+                ("restart", C.c_int32), ("max_iter", C.c_int32), ("tol", C.c_double)]
+
+
+class Completion(C.Structure):
+    _fields_ = [("tag", C.c_int64), ("matrix_id", C.c_int32), ("status", C.c_int32),
+                ("iterations", C.c_int32), ("path", C.c_int32), ("config_id", C.c_int32),
+                ("pad", C.c_int32), ("true_relres", C.c_double), ("t_submit_us", C.c_double),
+                ("t_admit_us", C.c_double), ("t_done_us", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
+class ServerStats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in ("submitted", "completed", "queued", "in_flight",
+                                         "resident_matrices", "evictions", "bytes_in_use",
+                                         "batched_launches", "prediction_cache_hits",
+                                         "prediction_cache_misses")]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 _vp = C.c_void_p
 _i32, _i64, _u32, _dbl, _flt = C.c_int32, C.c_int64, C.c_uint32, C.c_double, C.c_float
@@ -112,6 +139,16 @@ SIGNATURES = {
     "ck_config_from_id": (_i32, [_i32, C.POINTER(Config)]),
     "ck_kernel_name": (_i32, [C.POINTER(Config), _i32, C.c_char_p, C.c_size_t]),
     "ck_spmv_bytes": (_i64, [_vp, _i32, _i32]),
+    "ck_time_spmv": (_i32, [_vp, C.POINTER(Config), _i32, _vp, _vp, _i32, _i32, _vp,
+                            C.POINTER(_dbl)]),
+    "ck_server_create": (_i32, [C.POINTER(ServerOpts), C.POINTER(_vp)]),
+    "ck_server_add_matrix": (_i32, [_vp, _i32, _i64, _i64, _vp, _vp, _vp]),
+    "ck_server_submit": (_i32, [_vp, _i32, _vp, _vp, _i64]),
+    "ck_server_poll": (_i32, [_vp, C.POINTER(Completion), _i32]),
+    "ck_server_drain": (_i32, [_vp, _dbl]),
+    "ck_server_get_stats": (_i32, [_vp, C.POINTER(ServerStats)]),
+    "ck_server_clock_us": (_dbl, [_vp]),
+    "ck_server_destroy": (None, [_vp]),
     "ck_last_error": (C.c_char_p, []),
 }
 
@@ -310,8 +347,64 @@ def dot(x, y, out, stream=None):
                         _ptr(out, torch.float64), _stream(stream)))
 
 
+def time_spmv(h, cfg, x, y, warmup=10, reps=200, fp32=False, stream=None):
+    """Mean microseconds per product over `reps` back-to-back launches (HIP
+    events on the launch stream)."""
+    us = _dbl()
+    _check(lib().ck_time_spmv(h, C.byref(cfg), int(fp32), _ptr(x), _ptr(y), int(warmup),
+                              int(reps), _stream(stream), C.byref(us)))
+    return us.value
+
+
 def spmv_bytes(h, fp32=False, beta_nonzero=False):
     return int(lib().ck_spmv_bytes(h, int(fp32), int(beta_nonzero)))
+
+
+def server_create(budget_bytes=64 << 30, max_slots=256, chunk_iters=32, small_n=32768,
+                  large_workers=4, precision=CK_PREC_MIXED, restart=30, max_iter=100000,
+                  tol=1e-8):
+    o = ServerOpts(int(budget_bytes), max_slots, chunk_iters, small_n, large_workers,
+                   precision, restart, max_iter, float(tol))
+    h = _vp()
+    _check(lib().ck_server_create(C.byref(o), C.byref(h)))
+    return h.value
+
+
+def server_add_matrix(srv, mid, rp, col, val):
+    import torch
+    _check(lib().ck_server_add_matrix(srv, int(mid), rp.numel() - 1, col.numel(),
+                                      _ptr(rp, torch.int32), _ptr(col, torch.int32),
+                                      _ptr(val, torch.float64)))
+
+
+def server_submit(srv, mid, b, x, tag):
+    import torch
+    _check(lib().ck_server_submit(srv, int(mid), _ptr(b, torch.float64), _ptr(x, torch.float64),
+                                  int(tag)))
+
+
+def server_poll(srv, cap=1024):
+    buf = (Completion * cap)()
+    k = lib().ck_server_poll(srv, buf, cap)
+    return [buf[i].as_dict() for i in range(k)]
+
+
+def server_drain(srv, timeout_s=600.0):
+    _check(lib().ck_server_drain(srv, float(timeout_s)))
+
+
+def server_stats(srv):
+    s = ServerStats()
+    _check(lib().ck_server_get_stats(srv, C.byref(s)))
+    return s.as_dict()
+
+
+def server_clock_us(srv):
+    return float(lib().ck_server_clock_us(srv))
+
+
+def server_destroy(srv):
+    lib().ck_server_destroy(srv)
 
 
 class Matrix:

@@ -1,5 +1,6 @@
 // C-ABI entry points for the matrix store, features, prediction, conversion
 // and SpMV (declared in include/caskrylov.h).
+#include <algorithm>
 #include <cstdarg>
 #include <cstring>
 #include <limits>
@@ -61,6 +62,8 @@ static void release(ck_matrix *M) {
     (void)hipFree(M->ell_val);
     (void)hipFree(M->ell_val32);
     (void)hipFree(M->coo_row);
+    for (auto &kv : M->carry)
+        (void)hipFree(kv.second);
     delete M;
 }
 
@@ -331,6 +334,27 @@ static ck_config active_of(ck_handle h) {
     return h->active;
 }
 
+// Carry workspace for merge-path / COO products on stream s, sized for both.
+static ck_status carry_for(ck_handle h, const ck_config &c, hipStream_t s, void **out) {
+    *out = nullptr;
+    if (!(c.format == CK_FMT_COO || (c.format == CK_FMT_CSR && c.algorithm == CK_ALG_MERGE)))
+        return CK_OK;
+    std::lock_guard<std::mutex> lk(h->mu);
+    auto it = h->carry.find(s);
+    if (it != h->carry.end()) {
+        *out = it->second;
+        return CK_OK;
+    }
+    const int64_t bytes =
+        std::max(spmv_carry_bytes(*h, ck_config{CK_FMT_CSR, CK_ALG_MERGE, 0, 0}, false),
+                 spmv_carry_bytes(*h, ck_config{CK_FMT_COO, 0, 0, 0}, false));
+    char *p = nullptr;
+    CK_TRY(dev_alloc(&p, bytes));
+    h->carry[s] = p;
+    *out = p;
+    return CK_OK;
+}
+
 ck_status spmv_apply(ck_handle h, const ck_config *cfg, double alpha, const double *d_x,
                      double beta, double *d_y, hipStream_t s) {
     if (!h || (h->n > 0 && !d_y) || (h->ncols > 0 && !d_x))
@@ -340,7 +364,9 @@ ck_status spmv_apply(ck_handle h, const ck_config *cfg, double alpha, const doub
     a.beta = beta;
     a.x = d_x;
     a.y = d_y;
-    return launch_spmv<double>(*h, cfg ? *cfg : active_of(h), a, s);
+    const ck_config c = cfg ? *cfg : active_of(h);
+    CK_TRY(carry_for(h, c, s, &a.carry));
+    return launch_spmv<double>(*h, c, a, s);
 }
 
 ck_status spmv_apply_f32(ck_handle h, const ck_config *cfg, float alpha, const float *d_x,
@@ -352,7 +378,9 @@ ck_status spmv_apply_f32(ck_handle h, const ck_config *cfg, float alpha, const f
     a.beta = beta;
     a.x = d_x;
     a.y = d_y;
-    return launch_spmv<float>(*h, cfg ? *cfg : active_of(h), a, s);
+    const ck_config c = cfg ? *cfg : active_of(h);
+    CK_TRY(carry_for(h, c, s, &a.carry));
+    return launch_spmv<float>(*h, c, a, s);
 }
 
 ck_status ck_export_ell(ck_handle h, int32_t *d_col, double *d_val, int64_t *K, int64_t *pitch,
@@ -392,6 +420,46 @@ ck_status ck_dot(int64_t n, const double *d_x, const double *d_y, double *d_out,
         st = launch_dot(n, d_x, d_y, (double *)ws, counter, d_out, s);
     CK_HIP(hipFreeAsync(ws, s));
     return st;
+}
+
+ck_status ck_time_spmv(ck_handle h, const ck_config *cfg, int32_t fp32, const void *d_x,
+                       void *d_y, int32_t warmup, int32_t reps, hipStream_t s,
+                       double *us_per_call) {
+    if (!h || !cfg || !us_per_call || reps <= 0 || warmup < 0 ||
+        (h->n > 0 && !d_y) || (h->ncols > 0 && !d_x))
+        return fail(CK_E_INVALID, "bad arguments");
+    void *carry = nullptr;
+    CK_TRY(carry_for(h, *cfg, s, &carry));
+    SpmvArgs<double> a64;
+    SpmvArgs<float> a32;
+    a64.x = (const double *)d_x;
+    a64.y = (double *)d_y;
+    a64.carry = carry;
+    a32.x = (const float *)d_x;
+    a32.y = (float *)d_y;
+    a32.carry = carry;
+    auto one = [&]() -> ck_status {
+        return fp32 ? launch_spmv<float>(*h, *cfg, a32, s) : launch_spmv<double>(*h, *cfg, a64, s);
+    };
+    for (int i = 0; i < warmup; ++i)
+        CK_TRY(one());
+    hipEvent_t e0, e1;
+    CK_HIP(hipEventCreate(&e0));
+    CK_HIP(hipEventCreate(&e1));
+    ck_status st = CK_OK;
+    if (hipEventRecord(e0, s) != hipSuccess)
+        st = fail(CK_E_HIP, "hipEventRecord failed");
+    for (int i = 0; i < reps && st == CK_OK; ++i)
+        st = one();
+    float ms = 0.f;
+    if (st == CK_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+        st = fail(CK_E_HIP, "event timing failed");
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    CK_TRY(st);
+    *us_per_call = 1000.0 * (double)ms / reps;
+    return CK_OK;
 }
 
 int64_t ck_spmv_bytes(ck_handle h, int32_t fp32, int32_t beta_nonzero) {

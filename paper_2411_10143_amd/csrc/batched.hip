@@ -1,0 +1,366 @@
+// Batched small-system solver for the request loop: one workgroup per system
+// ("slot"), a bounded number of iterations per launch.  Between launches the
+// host retires finished slots and admits new requests, so requests that
+// arrive while others run join the next launch (continuous batching).
+//
+// Each slot runs FP64 iterative refinement around an FP32 inner solve:
+//   outer : r = b - A x (FP64 values, FP64 arithmetic), beta = ||r||, test
+//           beta/||b|| <= tol; otherwise the inner system A d = r/beta
+//   inner : CG (symmetric) until ||r_in|| <= max(tol ||b||/beta, 1e-5), or
+//           one GMRES(m) cycle (classical Gram-Schmidt twice, Givens), on
+//           the FP32 values with FP32 vectors and FP32 accumulation
+//   update: x += beta * d  (FP64)
+// (precision = FP64 runs the same loop with FP64 inner vectors.)
+// Every reduction stays inside the workgroup in a fixed order, so a slot's
+// bits do not depend on which other slots share the launch.
+#include <algorithm>
+
+#include "batched.hpp"
+
+namespace {
+
+constexpr int kB = 256;
+
+// sum over the workgroup, returned to every thread (fixed order)
+template <typename T>
+__device__ __forceinline__ T wg_sum(T v, T *lds) {
+    v = ck::wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0)
+        lds[w] = v;
+    __syncthreads();
+    const T r = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+    __syncthreads();
+    return r;
+}
+
+// y[i] = s1 * (A x)[i] + s0 * z[i] with L lanes per row (runtime power of two)
+template <typename TV, typename TX, typename TA>
+__device__ void wg_spmv(int n, int L, const int *__restrict__ rp, const int *__restrict__ col,
+                        const TV *__restrict__ val, const TX *__restrict__ x, TA s1, TA s0,
+                        const TA *__restrict__ z, TA *__restrict__ y) {
+    const int lane = threadIdx.x & (L - 1);
+    const int rpp = kB / L;
+    for (int r0 = 0; r0 < n; r0 += rpp) {
+        const int row = r0 + threadIdx.x / L;
+        TA acc = 0;
+        if (row < n) {
+            const int k1 = rp[row + 1];
+            for (int k = rp[row] + lane; k < k1; k += L)
+                acc += (TA)val[k] * (TA)x[col[k]];
+        }
+        for (int off = L >> 1; off > 0; off >>= 1)
+            acc += __shfl_xor(acc, off, 64);
+        if (lane == 0 && row < n)
+            y[row] = z ? s1 * acc + s0 * z[row] : s1 * acc;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T *wsp(ck::BSlot *s, int which) {
+    return (T *)s->work + (int64_t)which * s->ld;
+}
+
+}  // namespace
+
+// One launch: every listed slot advances by up to `budget` steps.
+template <typename T>
+__global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat *stat,
+                                                     const int *active, int budget) {
+    __shared__ T lds[4];
+    __shared__ double lds64[4];
+    __shared__ T hcol[ck::kBMaxM + 1];
+    __shared__ T hacc[ck::kBMaxM + 1];
+    __shared__ T wred[4][ck::kBMaxM + 1];
+    ck::BSlot *s = slots + active[blockIdx.x];
+    const int tid = threadIdx.x;
+    const int n = s->n, L = s->lanes;
+    int phase = s->phase;
+    if (phase == ck::B_DONE)
+        return;
+    if (s->bnorm < 0) {   // first launch of this request: ||b||, x0 = 0
+        double q = 0;
+        for (int i = tid; i < n; i += kB) {
+            q += s->b[i] * s->b[i];
+            s->x[i] = 0.0;
+        }
+        const double bn = sqrt(wg_sum(q, lds64));
+        if (tid == 0)
+            s->bnorm = bn;
+        __syncthreads();
+        if (bn == 0.0) {
+            phase = ck::B_DONE;
+            if (tid == 0) {
+                s->status = ck::CONVERGED;
+                s->relres = 0.0;
+            }
+        }
+    }
+    int steps = 0;
+    while (steps < budget && phase != ck::B_DONE) {
+        ++steps;
+        if (phase == ck::B_OUTER) {
+            // r = b - A x in FP64; beta = ||r||
+            wg_spmv<double, double, double>(n, L, s->rp, s->col, s->val64, s->x, -1.0, 1.0, s->b,
+                                            s->r64);
+            __syncthreads();
+            double q = 0;
+            for (int i = tid; i < n; i += kB)
+                q += s->r64[i] * s->r64[i];
+            const double beta = sqrt(wg_sum(q, lds64));
+            const double rel = beta / s->bnorm;
+            if (tid == 0) {
+                s->relres = rel;
+                s->beta = beta;
+            }
+            if (rel <= s->tol) {
+                phase = ck::B_DONE;
+                if (tid == 0)
+                    s->status = ck::CONVERGED;
+                break;
+            }
+            if (s->iter >= s->max_iter) {
+                phase = ck::B_DONE;
+                if (tid == 0)
+                    s->status = ck::BUDGET;
+                break;
+            }
+            const double inv = 1.0 / beta;
+            if (s->kind == ck::B_CG) {
+                T *r = wsp<T>(s, 0), *p = wsp<T>(s, 1), *d = wsp<T>(s, 3);
+                T rr = 0;
+                for (int i = tid; i < n; i += kB) {
+                    const T ri = (T)(s->r64[i] * inv);
+                    r[i] = ri;
+                    p[i] = ri;
+                    d[i] = 0;
+                    rr += ri * ri;
+                }
+                rr = wg_sum(rr, lds);
+                if (tid == 0) {
+                    s->rho = (double)rr;
+                    s->inner_tol = fmax(s->tol * s->bnorm / beta, 1e-5);
+                    s->inner_iter = 0;
+                }
+            } else {
+                T *v0 = wsp<T>(s, 0);
+                for (int i = tid; i < n; i += kB)
+                    v0[i] = (T)(s->r64[i] * inv);
+                if (tid == 0) {
+                    s->j = 0;
+                    s->g[0] = 1;
+                    for (int t = 1; t <= s->m; ++t)
+                        s->g[t] = 0;
+                }
+            }
+            if (tid == 0)
+                s->outer += 1;
+            phase = ck::B_INNER;
+            __syncthreads();
+            continue;
+        }
+        if (phase == ck::B_INNER && s->kind == ck::B_CG) {
+            T *r = wsp<T>(s, 0), *p = wsp<T>(s, 1), *q = wsp<T>(s, 2), *d = wsp<T>(s, 3);
+            const T *val = sizeof(T) == 4 ? (const T *)s->val32 : (const T *)s->val64;
+            wg_spmv<T, T, T>(n, L, s->rp, s->col, val, p, T(1), T(0), (const T *)nullptr, q);
+            __syncthreads();
+            T pq = 0;
+            for (int i = tid; i < n; i += kB)
+                pq += p[i] * q[i];
+            const T sigma = wg_sum(pq, lds);
+            if (!(sigma > T(0))) {
+                phase = s->inner_iter == 0 ? ck::B_DONE : ck::B_UPDATE;
+                if (phase == ck::B_DONE && tid == 0)
+                    s->status = ck::BREAKDOWN;
+                __syncthreads();
+                continue;
+            }
+            const T rho = (T)s->rho;
+            const T alpha = rho / sigma;
+            T rr = 0;
+            for (int i = tid; i < n; i += kB) {
+                d[i] += alpha * p[i];
+                const T ri = r[i] - alpha * q[i];
+                r[i] = ri;
+                rr += ri * ri;
+            }
+            const T rho_new = wg_sum(rr, lds);
+            const int it = s->inner_iter + 1;
+            const bool stop = sqrt((double)rho_new) <= s->inner_tol || it >= s->inner_cap ||
+                              s->iter + 1 >= s->max_iter;
+            const T bcg = rho_new / rho;
+            if (!stop)
+                for (int i = tid; i < n; i += kB)
+                    p[i] = r[i] + bcg * p[i];
+            __syncthreads();
+            if (tid == 0) {
+                s->rho = (double)rho_new;
+                s->inner_iter = it;
+                s->iter += 1;
+            }
+            if (stop)
+                phase = ck::B_UPDATE;
+            __syncthreads();
+            continue;
+        }
+        if (phase == ck::B_INNER) {   // GMRES: one Arnoldi step (CGS2) + Givens
+            const int j = s->j, m = s->m;
+            T *V = wsp<T>(s, 0);
+            T *w = V + (int64_t)(j + 1) * s->ld;
+            const T *val = sizeof(T) == 4 ? (const T *)s->val32 : (const T *)s->val64;
+            wg_spmv<T, T, T>(n, L, s->rp, s->col, val, V + (int64_t)j * s->ld, T(1), T(0),
+                             (const T *)nullptr, w);
+            __syncthreads();
+            for (int pass = 0; pass < 2; ++pass) {
+                T acc[ck::kBMaxM + 1];
+#pragma unroll
+                for (int c = 0; c <= ck::kBMaxM; ++c)
+                    acc[c] = 0;
+                for (int i = tid; i < n; i += kB) {
+                    const T wi = w[i];
+#pragma unroll
+                    for (int c = 0; c <= ck::kBMaxM; ++c)
+                        if (c <= j)
+                            acc[c] += V[(int64_t)c * s->ld + i] * wi;
+                }
+#pragma unroll
+                for (int c = 0; c <= ck::kBMaxM; ++c)
+                    if (c <= j) {
+                        const T v = ck::wave_sum(acc[c]);
+                        if ((tid & 63) == 0)
+                            wred[tid >> 6][c] = v;
+                    }
+                __syncthreads();
+                if (tid <= j) {
+                    const T h = (wred[0][tid] + wred[1][tid]) + (wred[2][tid] + wred[3][tid]);
+                    hcol[tid] = h;
+                    hacc[tid] = pass == 0 ? h : hacc[tid] + h;
+                }
+                __syncthreads();
+                for (int i = tid; i < n; i += kB) {
+                    T wi = w[i];
+                    for (int c = 0; c <= j; ++c)
+                        wi -= hcol[c] * V[(int64_t)c * s->ld + i];
+                    w[i] = wi;
+                }
+                __syncthreads();
+            }
+            T nn = 0;
+            for (int i = tid; i < n; i += kB)
+                nn += w[i] * w[i];
+            const T hn = sqrt(wg_sum(nn, lds));
+            __shared__ int stop_sh;
+            __shared__ T inv_sh;
+            if (tid == 0) {
+                // Hessenberg column j in the inner precision (stored as double)
+                double *Hj = s->H + j * (m + 1);
+                for (int c = 0; c <= j; ++c)
+                    Hj[c] = (double)hacc[c];
+                Hj[j + 1] = (double)hn;
+                for (int i = 0; i < j; ++i) {
+                    const T a = (T)Hj[i], c2 = (T)Hj[i + 1];
+                    const T ci = (T)s->cs[i], si = (T)s->sn[i];
+                    Hj[i] = (double)(ci * a + si * c2);
+                    Hj[i + 1] = (double)(-si * a + ci * c2);
+                }
+                const T a = (T)Hj[j], c2 = (T)Hj[j + 1];
+                const T dd = sqrt(a * a + c2 * c2);
+                int stop = 0;
+                if (dd == T(0)) {
+                    stop = 2;           // singular least-squares problem
+                } else {
+                    const T cj = a / dd, sj = c2 / dd, gj = (T)s->g[j];
+                    s->cs[j] = (double)cj;
+                    s->sn[j] = (double)sj;
+                    Hj[j] = (double)dd;
+                    Hj[j + 1] = 0;
+                    s->g[j + 1] = (double)(-sj * gj);
+                    s->g[j] = (double)(cj * gj);
+                    s->j = j + 1;
+                    s->iter += 1;
+                    const double est = fabs((double)s->g[j + 1]) * s->beta / s->bnorm;
+                    if (est <= s->tol || hn == T(0) || j + 1 == m || s->iter >= s->max_iter)
+                        stop = 1;
+                }
+                stop_sh = stop;
+                inv_sh = hn > T(0) ? T(1) / hn : T(0);
+            }
+            __syncthreads();
+            const int stop = stop_sh;
+            if (stop == 2) {
+                phase = s->j == 0 ? ck::B_DONE : ck::B_UPDATE;
+                if (phase == ck::B_DONE && tid == 0)
+                    s->status = ck::BREAKDOWN;
+            } else if (stop == 1) {
+                phase = ck::B_UPDATE;
+            } else {
+                const T inv = inv_sh;
+                for (int i = tid; i < n; i += kB)
+                    w[i] *= inv;
+            }
+            __syncthreads();
+            continue;
+        }
+        // B_UPDATE: x += beta * d
+        const double beta = s->beta;
+        if (s->kind == ck::B_CG) {
+            const T *d = wsp<T>(s, 3);
+            for (int i = tid; i < n; i += kB)
+                s->x[i] += beta * (double)d[i];
+        } else {
+            const int k = s->j, m = s->m;
+            if (tid == 0) {
+                for (int i = k - 1; i >= 0; --i) {
+                    T acc = (T)s->g[i];
+                    for (int t = i + 1; t < k; ++t)
+                        acc -= (T)s->H[t * (m + 1) + i] * (T)s->y[t];
+                    s->y[i] = (double)(acc / (T)s->H[i * (m + 1) + i]);
+                }
+            }
+            __syncthreads();
+            const T *V = wsp<T>(s, 0);
+            for (int i = tid; i < n; i += kB) {
+                double acc = 0;
+                for (int c = 0; c < k; ++c)
+                    acc += (double)s->y[c] * (double)V[(int64_t)c * s->ld + i];
+                s->x[i] += beta * acc;
+            }
+        }
+        phase = ck::B_OUTER;
+        __syncthreads();
+    }
+    __syncthreads();
+    if (tid == 0) {
+        s->phase = phase;
+        s->launches += 1;
+        ck::BStat &o = stat[active[blockIdx.x]];
+        o.phase = phase;
+        o.status = s->status;
+        o.iter = s->iter;
+        o.outer = s->outer;
+        o.relres = s->relres;
+    }
+}
+
+namespace ck {
+
+int64_t bslot_work_elems(int kind, int64_t n, int m) {
+    const int64_t ld = ceil_div(std::max<int64_t>(n, 1), 64) * 64;
+    return kind == B_CG ? 4 * ld : (int64_t)(m + 1) * ld;
+}
+
+ck_status launch_batched_chunk(BSlot *slots, BStat *stat, const int *active, int nactive,
+                               int budget, bool fp32, hipStream_t s) {
+    if (nactive <= 0)
+        return CK_OK;
+    if (fp32)
+        hipLaunchKernelGGL((batched_chunk<float>), dim3(nactive), dim3(256), 0, s, slots, stat,
+                           active, budget);
+    else
+        hipLaunchKernelGGL((batched_chunk<double>), dim3(nactive), dim3(256), 0, s, slots, stat,
+                           active, budget);
+    CK_HIP(hipGetLastError());
+    return CK_OK;
+}
+
+}  // namespace ck

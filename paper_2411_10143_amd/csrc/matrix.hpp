@@ -3,6 +3,7 @@
 #pragma once
 
 #include <atomic>
+#include <map>
 #include <mutex>
 
 #include "krylov.hpp"
@@ -27,7 +28,10 @@ struct ck_matrix {
     std::atomic<bool> has_coo{false};
     int64_t max_row = -1;             // longest row, once known
     ck_config active{};
-    std::mutex mu;                    // guards conversions and `active`
+    std::mutex mu;                    // guards conversions, `active` and `carry`
+    // merge-path / COO carry workspace of spmv_apply, one per stream (work on
+    // one stream is ordered, so reuse on that stream is safe)
+    std::map<hipStream_t, void *> carry;
 };
 
 namespace ck {

@@ -1,0 +1,205 @@
+"""Offline phase of the method (Section III-B): time every SpMV configuration
+on a corpus of matrices, label each matrix per cascade stage, fit one
+decision tree per stage and export the trees as the library's model file.
+
+  collect : features (GPU kernels) + mean time of every configuration (the
+            library's event-timed loop of back-to-back products) per matrix
+  label   : stage 1 = format of the fastest configuration overall;
+            stage 2 = fastest CSR algorithm (vector at its best lane count,
+            scalar, merge-path); stage 3 = fastest lane count.  Ties go to
+            the lower configuration index.  With a perfect classifier the
+            cascade therefore reaches the fastest configuration.
+  fit     : a CART tree per stage (scikit-learn), exported as node tables.
+
+The corpus is synthetic (stencil, power-law, block-diagonal and uniform-random
+families, disjoint seeds from the 48 held-out evaluation matrices), timed on
+this GPU.
+
+  python -m paper_2411_10143_amd.train collect --out data.csv [--count 200]
+  python -m paper_2411_10143_amd.train fit --data data.csv --model cascade_model.txt
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+FEATURES = ["nrows", "ncols", "nnz", "density", "mean", "sd", "cov", "max", "min", "maxavg",
+            "distavg", "clusteravg", "fill", "ndiag", "diagfill"]
+CONFIGS = 11
+
+
+def reps_for(us_probe: float, budget_us: float = 4000.0, lo: int = 20, hi: int = 200) -> int:
+    return int(min(hi, max(lo, budget_us / max(us_probe, 1e-3))))
+
+
+def time_all_configs(ck, Mx, x, y, warmup=10, reps=None):
+    """Mean us per product for each of the 11 configurations (inf if refused)."""
+    out = []
+    for cid in range(CONFIGS):
+        cfg = ck.config_from_id(cid)
+        try:
+            ck.spmv_convert(Mx.handle, cfg)
+        except ck.CkError as e:
+            if e.status != ck.CK_E_UNSUPPORTED:
+                raise
+            out.append(math.inf)
+            continue
+        r = reps
+        if r is None:
+            probe = ck.time_spmv(Mx.handle, cfg, x, y, warmup=warmup, reps=5)
+            r = reps_for(probe)
+        out.append(ck.time_spmv(Mx.handle, cfg, x, y, warmup=2, reps=r))
+    return out
+
+
+def labels(times):
+    """(format, algorithm, log2 lanes) labels from the 11 configuration times."""
+    t = np.asarray(times, dtype=np.float64)
+    best = int(np.argmin(t))          # argmin takes the first (lowest index) on ties
+    fmt = 0 if best <= 8 else (1 if best == 9 else 2)
+    lanes = int(np.argmin(t[:7]))
+    alg_times = [t[7], t[lanes], t[8]]   # scalar, vector at its best lanes, merge
+    alg = int(np.argmin(alg_times))
+    return fmt, alg, lanes
+
+
+def collect(out_csv, count=200, seed=9000, reps=None):
+    import torch
+
+    import paper_2411_10143_amd as ck
+    from synth import workloads as W
+
+    specs = W.training_specs(count=count, seed=seed)
+    new = not os.path.exists(out_csv)
+    done = set()
+    if not new:
+        with open(out_csv) as f:
+            done = {row["name"] for row in csv.DictReader(f)}
+    f = open(out_csv, "a", newline="")
+    w = csv.writer(f)
+    if new:
+        w.writerow(["name", "family", "n", "nnz"] + FEATURES + [f"t{c}" for c in range(CONFIGS)])
+    t0 = time.time()
+    for i, spec in enumerate(specs):
+        name, fam, k, n, s = spec
+        if name in done:
+            continue
+        A = W.family_matrix(fam, k, n, s)
+        Mx = ck.Matrix.from_csr(A)
+        F = ck.spmv_features(Mx.handle)
+        x = torch.from_numpy(np.random.default_rng(s).uniform(-1, 1, A.ncols)).cuda()
+        y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        times = time_all_configs(ck, Mx, x, y, reps=reps)
+        Mx.close()
+        del x, y
+        w.writerow([name, fam, A.n, A.nnz] + [repr(v) for v in F.model_inputs()] +
+                   [repr(v) for v in times])
+        f.flush()
+        best = int(np.argmin(times))
+        print(f"[{i + 1}/{len(specs)}] {name} nnz={A.nnz} best={ck.CONFIG_NAMES[best]} "
+              f"{min(times):.2f}us elapsed={time.time() - t0:.0f}s", flush=True)
+    f.close()
+
+
+def load(path):
+    X, T, names = [], [], []
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            X.append([float(row[k]) for k in FEATURES])
+            T.append([float(row[f"t{c}"]) for c in range(CONFIGS)])
+            names.append(row["name"])
+    return np.array(X), np.array(T), names
+
+
+def fit_trees(X, T, max_depth=8, min_leaf=2, seed=0):
+    """Three classifiers; stage-2/3 trees are trained on every matrix (the
+    labels are defined for all of them), as the cascade may reach them."""
+    from sklearn.tree import DecisionTreeClassifier
+    Y = np.array([labels(t) for t in T])
+    # inputs as the library evaluates them: rounded to float32
+    X32 = X.astype(np.float32)
+    trees = []
+    for stage in range(3):
+        clf = DecisionTreeClassifier(max_depth=max_depth, min_samples_leaf=min_leaf,
+                                     random_state=seed)
+        clf.fit(X32, Y[:, stage])
+        trees.append(clf)
+    return trees, Y
+
+
+def export(trees, path, note=""):
+    names = ["format", "algorithm", "lanes"]
+    with open(path, "w") as f:
+        f.write("# caskrylov cascade model: CART trees fitted on MI355X SpMV timings\n")
+        if note:
+            f.write(f"# {note}\n")
+        f.write("# node: feature threshold(hex) left right class; features in feature-table "
+                "order:\n# " + " ".join(f"{i} {n}" for i, n in enumerate(FEATURES)) + "\n")
+        for name, clf in zip(names, trees):
+            tr = clf.tree_
+            f.write(f"tree {name} {tr.node_count}\n")
+            for t in range(tr.node_count):
+                leaf = tr.children_left[t] < 0
+                cls = int(clf.classes_[int(np.argmax(tr.value[t, 0, :]))]) if leaf else -1
+                feat = -1 if leaf else int(tr.feature[t])
+                thr = 0.0 if leaf else float(tr.threshold[t])
+                f.write(f"{feat} {thr.hex()} {int(tr.children_left[t])} "
+                        f"{int(tr.children_right[t])} {cls}\n")
+
+
+def cascade_predict(trees, x):
+    """Configuration id the cascade picks for one feature row (sklearn side)."""
+    x = np.asarray(x, dtype=np.float32)[None, :]
+    fmt = int(trees[0].predict(x)[0])
+    if fmt == 1:
+        return 9
+    if fmt == 2:
+        return 10
+    alg = int(trees[1].predict(x)[0])
+    if alg == 0:
+        return 7
+    if alg == 2:
+        return 8
+    return int(trees[2].predict(x)[0])
+
+
+def main(argv=None):
+    p = argparse.ArgumentParser()
+    sub = p.add_subparsers(dest="cmd", required=True)
+    c = sub.add_parser("collect")
+    c.add_argument("--out", required=True)
+    c.add_argument("--count", type=int, default=200)
+    c.add_argument("--seed", type=int, default=9000)
+    c.add_argument("--reps", type=int, default=None)
+    fa = sub.add_parser("fit")
+    fa.add_argument("--data", required=True, nargs="+")
+    fa.add_argument("--model", required=True)
+    fa.add_argument("--max-depth", type=int, default=8)
+    fa.add_argument("--min-leaf", type=int, default=2)
+    a = p.parse_args(argv)
+    if a.cmd == "collect":
+        collect(a.out, a.count, a.seed, a.reps)
+    else:
+        Xs, Ts = [], []
+        for d in a.data:
+            X, T, _ = load(d)
+            Xs.append(X)
+            Ts.append(T)
+        X, T = np.concatenate(Xs), np.concatenate(Ts)
+        trees, Y = fit_trees(X, T, a.max_depth, a.min_leaf)
+        picks = np.array([cascade_predict(trees, x) for x in X])
+        slow = T[np.arange(len(T)), picks] / T.min(axis=1)
+        note = (f"{len(X)} training matrices; training-set geomean t_pred/t_best = "
+                f"{math.exp(np.mean(np.log(slow))):.4f}")
+        export(trees, a.model, note)
+        print(note)
+
+
+if __name__ == "__main__":
+    sys.exit(main())

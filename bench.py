@@ -517,7 +517,52 @@ def bench_gmres_mixed(args):
 
 
 def bench_serve(args):
-    raise SystemExit("serve workload: see paper_2411_10143_amd.serving")
+    import oracle
+    import paper_2411_10143_amd as ck
+    from paper_2411_10143_amd.serving import ServingWorkload, latency_summary, poisson_arrivals
+    from synth import workloads as W
+    t0 = time.time()
+    pool = W.serving_pool()
+    log(f"[serve] pool of {len(pool)} matrices generated in {time.time() - t0:.0f}s; "
+        f"n from {min(A.n for A, _ in pool)} to {max(A.n for A, _ in pool)}")
+    Wl = ServingWorkload(pool, args.requests, tol=args.tol, precision=ck.CK_PREC_MIXED,
+                         budget_bytes=64 << 30, max_slots=256, chunk_iters=32, small_n=32768,
+                         large_workers=4)
+    log(f"[serve] {args.requests} requests prepared")
+    # closed loop: capacity C (also warms the prediction cache and residency)
+    cap = latency_summary(Wl.run())
+    log(f"[serve] closed loop: {cap['solves_per_s']:.1f} solves/s")
+    rate = 0.8 * cap["solves_per_s"]
+    runs = []
+    for s in range(args.steps):
+        done = Wl.run(arrivals_s=poisson_arrivals(args.requests, rate, seed=5001 + s))
+        runs.append((latency_summary(done), done))
+        log(f"[serve] open loop {s + 1}: p50 {runs[-1][0]['p50_ms']:.2f} ms "
+            f"p99 {runs[-1][0]['p99_ms']:.2f} ms")
+    summ, done = runs[-1]
+    # every result checked by an oracle residual (FP64, on the host)
+    worst = 0.0
+    for c in done:
+        t = c["tag"]
+        A = pool[Wl.mid[t]][0]
+        worst = max(worst, oracle.relres(A, Wl.b[t].cpu().numpy(), Wl.x[t].cpu().numpy()))
+    st = Wl.stats()
+    Wl.close()
+    mean_sps = float(np.mean([r[0]["solves_per_s"] for r in runs]))
+    _solve_json(args, mean_sps, "solves/s",
+                1e3 * float(np.mean([r[0]["makespan_s"] for r in runs])),
+                f"serve: {args.requests} requests, Poisson arrivals at 0.8x closed-loop "
+                f"capacity, 64-matrix pool (n log-uniform 1e3-1e6), CG if symmetric else "
+                f"GMRES(30), mixed FP32/FP64, tol {args.tol:g}, batched slots for n <= 32768",
+                {"latency_ms": {"p50": round(summ["p50_ms"], 3), "p99": round(summ["p99_ms"], 3),
+                                "mean": round(summ["mean_ms"], 3)},
+                 "closed_loop_solves_per_s": round(cap["solves_per_s"], 3),
+                 "arrival_rate_per_s": round(rate, 3),
+                 "batched_fraction": round(summ["batched"] / summ["solves"], 3),
+                 "ok": summ["ok"], "worst_oracle_relres": worst, "server_stats": st},
+                {"bound": "hbm", "kernel": "batched_chunk + solver kernels", "achieved": None,
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None},
+                None, dtype="f32+f64")
 
 
 # ---------------------------------------------------------------------------
@@ -533,6 +578,8 @@ def main():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--table", default=None, help="write the per-matrix timing table (JSON)")
     p.add_argument("--grid", type=int, default=1024, help="gmres_mixed grid side")
+    p.add_argument("--requests", type=int, default=2000, help="serve: requests per trace")
+    p.add_argument("--tol", type=float, default=1e-8, help="serve: tolerance")
     args = p.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build runs on a single MI355X (the serving and "

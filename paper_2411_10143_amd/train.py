@@ -64,8 +64,10 @@ def labels(times):
     best = int(np.argmin(t))          # argmin takes the first (lowest index) on ties
     fmt = 0 if best <= 8 else (1 if best == 9 else 2)
     lanes = int(np.argmin(t[:7]))
-    alg_times = [t[7], t[lanes], t[8]]   # scalar, vector at its best lanes, merge
-    alg = int(np.argmin(alg_times))
+    # candidates in configuration-index order: vector at its best lanes (id
+    # 0..6), scalar (7), merge (8); argmin keeps the first on ties
+    cand = [(t[lanes], 1), (t[7], 0), (t[8], 2)]
+    alg = cand[int(np.argmin([c[0] for c in cand]))][1]
     return fmt, alg, lanes
 
 
@@ -180,8 +182,8 @@ def main(argv=None):
     fa = sub.add_parser("fit")
     fa.add_argument("--data", required=True, nargs="+")
     fa.add_argument("--model", required=True)
-    fa.add_argument("--max-depth", type=int, default=8)
-    fa.add_argument("--min-leaf", type=int, default=2)
+    fa.add_argument("--max-depth", type=int, default=5)
+    fa.add_argument("--min-leaf", type=int, default=1)
     a = p.parse_args(argv)
     if a.cmd == "collect":
         collect(a.out, a.count, a.seed, a.reps)

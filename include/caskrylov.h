@@ -56,14 +56,17 @@ typedef struct ck_matrix *ck_handle;
  * format    : CK_FMT_CSR, CK_FMT_ELL or CK_FMT_COO
  * algorithm : for CSR only -- CK_ALG_SCALAR (one lane per row, row block
  *             staged through LDS), CK_ALG_VECTOR (`lanes` lanes per row),
- *             CK_ALG_MERGE (merge-path load balancing)
+ *             CK_ALG_MERGE (merge-path load balancing), CK_ALG_PANEL (column
+ *             panels sized so each XCD's L2 holds its slice of x; a
+ *             panel-major copy made by spmv_convert)
  * lanes     : for CSR-vector, 1, 2, 4, 8, 16, 32 or 64 lanes per row
  * stages_done: how many cascade stages produced this configuration (0-3)
- * Eleven configurations in all: 7 CSR-vector lane counts, CSR-scalar,
- * CSR-merge, ELL, COO.  ck_config_id() numbers them 0..10 in that order. */
+ * Twelve configurations in all: 7 CSR-vector lane counts, CSR-scalar,
+ * CSR-merge, ELL, COO, CSR-panel.  ck_config_id() numbers them 0..11 in
+ * that order. */
 enum { CK_FMT_CSR = 0, CK_FMT_ELL = 1, CK_FMT_COO = 2 };
-enum { CK_ALG_SCALAR = 0, CK_ALG_VECTOR = 1, CK_ALG_MERGE = 2 };
-#define CK_NUM_CONFIGS 11
+enum { CK_ALG_SCALAR = 0, CK_ALG_VECTOR = 1, CK_ALG_MERGE = 2, CK_ALG_PANEL = 3 };
+#define CK_NUM_CONFIGS 12
 
 typedef struct {
     int32_t format;
@@ -145,8 +148,8 @@ void spmv_destroy(ck_handle h);
 ck_status spmv_features(ck_handle h, ck_features *out, hipStream_t s);
 
 /* spmv_select -- host-only cascaded inference (Section III-C-1): stage 1
- * format, stage 2 CSR algorithm (only if CSR), stage 3 lanes (only if
- * CSR-vector).  model_path: a cascade model file, or NULL for the model
+ * format, stage 2 CSR algorithm (only if CSR; scalar, vector, merge or
+ * panel), stage 3 lanes (only if CSR-vector).  model_path: a cascade model file, or NULL for the model
  * shipped next to the library.  A stage that does not run keeps the default
  * configuration's value for its field.  *out->stages_done = stages run. */
 ck_status spmv_select(const ck_features *f, const char *model_path, ck_config *out);
@@ -165,7 +168,9 @@ ck_status ck_default_config(ck_handle h, ck_config *out);
  * switch converts the matrix).  CSR needs nothing.  ELL: column-major,
  * K = longest row, pitch = nrows rounded up to 64, padding column -1 and
  * value +0.0; refused with CK_E_UNSUPPORTED when K*pitch > 8*nnz.  COO: a
- * row-index array (column and value arrays are shared with CSR).  Enqueued
+ * row-index array (column and value arrays are shared with CSR).  CSR-panel:
+ * panel-major copy of the column and value arrays plus per-panel row
+ * pointers (P*nrows + 1 int32).  Enqueued
  * on s; the copy is usable by later work on s.  Idempotent. */
 ck_status spmv_convert(ck_handle h, const ck_config *cfg, hipStream_t s);
 
@@ -221,9 +226,9 @@ ck_status ck_export_coo_rows(ck_handle h, int32_t *d_row, hipStream_t s);
  * the device scalar d_out.  Same inputs give the same bits on every call. */
 ck_status ck_dot(int64_t n, const double *d_x, const double *d_y, double *d_out, hipStream_t s);
 
-/* ck_config_id / ck_config_from_id -- number the 11 configurations 0..10:
+/* ck_config_id / ck_config_from_id -- number the 12 configurations 0..11:
  * CSR-vector lanes 1,2,4,...,64 = 0..6, CSR-scalar = 7, CSR-merge = 8,
- * ELL = 9, COO = 10.  Invalid input gives -1 / CK_E_INVALID. */
+ * ELL = 9, COO = 10, CSR-panel = 11.  Invalid input gives -1 / CK_E_INVALID. */
 int32_t ck_config_id(const ck_config *cfg);
 ck_status ck_config_from_id(int32_t id, ck_config *out);
 

@@ -18,13 +18,13 @@ CK_E_NOT_CONVERGED, CK_E_BREAKDOWN, CK_E_UNSUPPORTED, CK_E_CANCELLED = -4, -5, -
 STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "NOT_CONVERGED",
                 -5: "BREAKDOWN", -6: "UNSUPPORTED", -7: "CANCELLED"}
 CK_FMT_CSR, CK_FMT_ELL, CK_FMT_COO = 0, 1, 2
-CK_ALG_SCALAR, CK_ALG_VECTOR, CK_ALG_MERGE = 0, 1, 2
+CK_ALG_SCALAR, CK_ALG_VECTOR, CK_ALG_MERGE, CK_ALG_PANEL = 0, 1, 2, 3
 CK_PREC_FP64, CK_PREC_MIXED = 0, 1
 CK_KEEP_FP32 = 1
-NUM_CONFIGS = 11
+NUM_CONFIGS = 12
 CONFIG_NAMES = ["csr-vector-1", "csr-vector-2", "csr-vector-4", "csr-vector-8",
                 "csr-vector-16", "csr-vector-32", "csr-vector-64", "csr-scalar", "csr-merge",
-                "ell", "coo"]
+                "ell", "coo", "csr-panel"]
 
 
 class CkError(RuntimeError):

@@ -6,6 +6,7 @@
 #include <limits>
 
 #include "matrix.hpp"
+#include "panel.hpp"
 #include "predictor.hpp"
 #include "solvers.hpp"
 
@@ -62,6 +63,10 @@ static void release(ck_matrix *M) {
     (void)hipFree(M->ell_val);
     (void)hipFree(M->ell_val32);
     (void)hipFree(M->coo_row);
+    (void)hipFree(M->panel_rp);
+    (void)hipFree(M->panel_col);
+    (void)hipFree(M->panel_val);
+    (void)hipFree(M->panel_val32);
     for (auto &kv : M->carry)
         (void)hipFree(kv.second);
     delete M;
@@ -99,9 +104,35 @@ ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s) {
 ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
     if (!config_valid(c))
         return fail(CK_E_INVALID, "invalid SpMV configuration");
-    if (c.format == CK_FMT_CSR)
+    if (c.format == CK_FMT_CSR && c.algorithm != CK_ALG_PANEL)
         return CK_OK;
     std::lock_guard<std::mutex> lk(M.mu);
+    if (c.format == CK_FMT_CSR) {   // CSR-panel
+        if (M.has_panel.load())
+            return CK_OK;
+        const int P = panel_count_for(M.ncols, 8);
+        const int64_t W = ceil_div(std::max<int64_t>(M.ncols, 1), P);
+        const int64_t N = (int64_t)P * M.n;
+        if (N + 1 > (int64_t)std::numeric_limits<int32_t>::max())
+            return fail(CK_E_UNSUPPORTED, "too many panel rows");
+        CK_TRY(dev_alloc(&M.panel_rp, N + 1));
+        CK_TRY(dev_alloc(&M.panel_col, M.nnz));
+        CK_TRY(dev_alloc(&M.panel_val, M.nnz));
+        if (M.val32)
+            CK_TRY(dev_alloc(&M.panel_val32, M.nnz));
+        int *tmp = nullptr;
+        const int64_t tmp_elems = N + panel_scan_tmp_elems(N);
+        CK_HIP(hipMallocAsync((void **)&tmp, (size_t)tmp_elems * sizeof(int), s));
+        const ck_status st = launch_to_panel(M, P, W, tmp, tmp + N, M.panel_rp, M.panel_col,
+                                             M.panel_val, M.panel_val32, s);
+        CK_HIP(hipFreeAsync(tmp, s));
+        CK_TRY(st);
+        M.panel_P = P;
+        M.panel_W = W;
+        M.panel_L = kPanelLanes;
+        M.has_panel.store(true);
+        return CK_OK;
+    }
     if (c.format == CK_FMT_COO) {
         if (M.has_coo.load())
             return CK_OK;
@@ -158,6 +189,8 @@ int32_t ck_config_id(const ck_config *c) {
         return 7;
     if (c->algorithm == CK_ALG_MERGE)
         return 8;
+    if (c->algorithm == CK_ALG_PANEL)
+        return 11;
     int idx = 0;
     while ((1 << idx) < c->lanes)
         ++idx;
@@ -166,7 +199,11 @@ int32_t ck_config_id(const ck_config *c) {
 
 ck_status ck_config_from_id(int32_t id, ck_config *out) {
     if (!out || id < 0 || id >= CK_NUM_CONFIGS)
-        return fail(CK_E_INVALID, "configuration id must be in [0, 10]");
+        return fail(CK_E_INVALID, "configuration id must be in [0, %d]", CK_NUM_CONFIGS - 1);
+    if (id == 11) {
+        *out = ck_config{CK_FMT_CSR, CK_ALG_PANEL, 0, 0};
+        return CK_OK;
+    }
     if (id <= 6)
         *out = ck_config{CK_FMT_CSR, CK_ALG_VECTOR, 1 << id, 0};
     else if (id == 7)
@@ -280,7 +317,7 @@ ck_status ck_select_stages(const ck_features *f, const char *model_path, int32_t
         if (stage[1] == CK_ALG_VECTOR)
             stage[2] = C->tree[2].eval(in);
     }
-    if (stage[0] < 0 || stage[0] > 2 || stage[1] > 2 || stage[2] > 6)
+    if (stage[0] < 0 || stage[0] > 2 || stage[1] > 3 || stage[2] > 6)
         return fail(CK_E_INVALID, "cascade model produced an unknown class");
     return CK_OK;
 }
@@ -337,7 +374,8 @@ static ck_config active_of(ck_handle h) {
 // Carry workspace for merge-path / COO products on stream s, sized for both.
 static ck_status carry_for(ck_handle h, const ck_config &c, hipStream_t s, void **out) {
     *out = nullptr;
-    if (!(c.format == CK_FMT_COO || (c.format == CK_FMT_CSR && c.algorithm == CK_ALG_MERGE)))
+    if (!(c.format == CK_FMT_COO ||
+          (c.format == CK_FMT_CSR && (c.algorithm == CK_ALG_MERGE || c.algorithm == CK_ALG_PANEL))))
         return CK_OK;
     std::lock_guard<std::mutex> lk(h->mu);
     auto it = h->carry.find(s);
@@ -347,7 +385,8 @@ static ck_status carry_for(ck_handle h, const ck_config &c, hipStream_t s, void 
     }
     const int64_t bytes =
         std::max(spmv_carry_bytes(*h, ck_config{CK_FMT_CSR, CK_ALG_MERGE, 0, 0}, false),
-                 spmv_carry_bytes(*h, ck_config{CK_FMT_COO, 0, 0, 0}, false));
+                 std::max(spmv_carry_bytes(*h, ck_config{CK_FMT_COO, 0, 0, 0}, false),
+                          spmv_carry_bytes(*h, ck_config{CK_FMT_CSR, CK_ALG_PANEL, 0, 0}, false)));
     char *p = nullptr;
     CK_TRY(dev_alloc(&p, bytes));
     h->carry[s] = p;
@@ -414,10 +453,7 @@ ck_status ck_dot(int64_t n, const double *d_x, const double *d_y, double *d_out,
         return fail(CK_E_INVALID, "bad arguments");
     void *ws = nullptr;
     CK_HIP(hipMallocAsync(&ws, 1024 * sizeof(double) + 256, s));
-    unsigned *counter = (unsigned *)((char *)ws + 1024 * sizeof(double));
-    ck_status st = launch_fill<int>(1, (int *)counter, 0, s);
-    if (st == CK_OK)
-        st = launch_dot(n, d_x, d_y, (double *)ws, counter, d_out, s);
+    const ck_status st = launch_dot(n, d_x, d_y, (double *)ws, d_out, s);
     CK_HIP(hipFreeAsync(ws, s));
     return st;
 }

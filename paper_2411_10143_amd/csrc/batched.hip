@@ -10,7 +10,10 @@
 //           one GMRES(m) cycle (classical Gram-Schmidt twice, Givens), on
 //           the FP32 values with FP32 vectors and FP32 accumulation
 //   update: x += beta * d  (FP64)
-// (precision = FP64 runs the same loop with FP64 inner vectors.)
+// With FP64 inner vectors the same loop is plain CG (inner target
+// tol ||b||/beta, then the true-residual check) or plain restarted GMRES(m);
+// the solvers use it, with 1024 threads, for systems too small to fill the
+// GPU, where one workgroup running the whole solve beats a launch per step.
 // Every reduction stays inside the workgroup in a fixed order, so a slot's
 // bits do not depend on which other slots share the launch.
 #include <algorithm>
@@ -19,28 +22,29 @@
 
 namespace {
 
-constexpr int kB = 256;
-
-// sum over the workgroup, returned to every thread (fixed order)
-template <typename T>
+// sum over the workgroup of BS threads, returned to every thread (fixed order)
+template <int BS, typename T>
 __device__ __forceinline__ T wg_sum(T v, T *lds) {
     v = ck::wave_sum(v);
     const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0)
         lds[w] = v;
     __syncthreads();
-    const T r = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+    T r = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+#pragma unroll
+    for (int t = 4; t < BS / 64; t += 4)
+        r += (lds[t] + lds[t + 1]) + (lds[t + 2] + lds[t + 3]);
     __syncthreads();
     return r;
 }
 
 // y[i] = s1 * (A x)[i] + s0 * z[i] with L lanes per row (runtime power of two)
-template <typename TV, typename TX, typename TA>
+template <int BS, typename TV, typename TX, typename TA>
 __device__ void wg_spmv(int n, int L, const int *__restrict__ rp, const int *__restrict__ col,
                         const TV *__restrict__ val, const TX *__restrict__ x, TA s1, TA s0,
                         const TA *__restrict__ z, TA *__restrict__ y) {
     const int lane = threadIdx.x & (L - 1);
-    const int rpp = kB / L;
+    const int rpp = BS / L;
     for (int r0 = 0; r0 < n; r0 += rpp) {
         const int row = r0 + threadIdx.x / L;
         TA acc = 0;
@@ -63,15 +67,17 @@ __device__ __forceinline__ T *wsp(ck::BSlot *s, int which) {
 
 }  // namespace
 
-// One launch: every listed slot advances by up to `budget` steps.
-template <typename T>
-__global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat *stat,
-                                                     const int *active, int budget) {
-    __shared__ T lds[4];
-    __shared__ double lds64[4];
+// One launch: every listed slot advances by up to `budget` steps; BS threads
+// per slot (256 when many slots share the GPU, 1024 for a single system).
+template <typename T, int BS>
+__global__ __launch_bounds__(BS) void batched_chunk(ck::BSlot *slots, ck::BStat *stat,
+                                                    const int *active, int budget) {
+    constexpr int NW = BS / 64;
+    __shared__ T lds[NW];
+    __shared__ double lds64[NW];
     __shared__ T hcol[ck::kBMaxM + 1];
     __shared__ T hacc[ck::kBMaxM + 1];
-    __shared__ T wred[4][ck::kBMaxM + 1];
+    __shared__ T wred[NW][ck::kBMaxM + 1];
     ck::BSlot *s = slots + active[blockIdx.x];
     const int tid = threadIdx.x;
     const int n = s->n, L = s->lanes;
@@ -80,15 +86,18 @@ __global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat
         return;
     if (s->bnorm < 0) {   // first launch of this request: ||b||, x0 = 0
         double q = 0;
-        for (int i = tid; i < n; i += kB) {
+        for (int i = tid; i < n; i += BS) {
             q += s->b[i] * s->b[i];
-            s->x[i] = 0.0;
+            if (!s->keep_x0)
+                s->x[i] = 0.0;
         }
-        const double bn = sqrt(wg_sum(q, lds64));
+        const double bn = sqrt(wg_sum<BS>(q, lds64));
         if (tid == 0)
             s->bnorm = bn;
         __syncthreads();
-        if (bn == 0.0) {
+        if (bn == 0.0) {   // b = 0: x = 0 is the solution
+            for (int i = tid; i < n; i += BS)
+                s->x[i] = 0.0;
             phase = ck::B_DONE;
             if (tid == 0) {
                 s->status = ck::CONVERGED;
@@ -101,13 +110,13 @@ __global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat
         ++steps;
         if (phase == ck::B_OUTER) {
             // r = b - A x in FP64; beta = ||r||
-            wg_spmv<double, double, double>(n, L, s->rp, s->col, s->val64, s->x, -1.0, 1.0, s->b,
+            wg_spmv<BS, double, double, double>(n, L, s->rp, s->col, s->val64, s->x, -1.0, 1.0, s->b,
                                             s->r64);
             __syncthreads();
             double q = 0;
-            for (int i = tid; i < n; i += kB)
+            for (int i = tid; i < n; i += BS)
                 q += s->r64[i] * s->r64[i];
-            const double beta = sqrt(wg_sum(q, lds64));
+            const double beta = sqrt(wg_sum<BS>(q, lds64));
             const double rel = beta / s->bnorm;
             if (tid == 0) {
                 s->relres = rel;
@@ -129,22 +138,24 @@ __global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat
             if (s->kind == ck::B_CG) {
                 T *r = wsp<T>(s, 0), *p = wsp<T>(s, 1), *d = wsp<T>(s, 3);
                 T rr = 0;
-                for (int i = tid; i < n; i += kB) {
+                for (int i = tid; i < n; i += BS) {
                     const T ri = (T)(s->r64[i] * inv);
                     r[i] = ri;
                     p[i] = ri;
                     d[i] = 0;
                     rr += ri * ri;
                 }
-                rr = wg_sum(rr, lds);
+                rr = wg_sum<BS>(rr, lds);
                 if (tid == 0) {
                     s->rho = (double)rr;
-                    s->inner_tol = fmax(s->tol * s->bnorm / beta, 1e-5);
+                    // FP32 inner solves stop at 1e-5 (their attainable
+                    // accuracy); FP64 inner solves go to the outer target
+                    s->inner_tol = fmax(s->tol * s->bnorm / beta, sizeof(T) == 4 ? 1e-5 : 0.0);
                     s->inner_iter = 0;
                 }
             } else {
                 T *v0 = wsp<T>(s, 0);
-                for (int i = tid; i < n; i += kB)
+                for (int i = tid; i < n; i += BS)
                     v0[i] = (T)(s->r64[i] * inv);
                 if (tid == 0) {
                     s->j = 0;
@@ -162,12 +173,12 @@ __global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat
         if (phase == ck::B_INNER && s->kind == ck::B_CG) {
             T *r = wsp<T>(s, 0), *p = wsp<T>(s, 1), *q = wsp<T>(s, 2), *d = wsp<T>(s, 3);
             const T *val = sizeof(T) == 4 ? (const T *)s->val32 : (const T *)s->val64;
-            wg_spmv<T, T, T>(n, L, s->rp, s->col, val, p, T(1), T(0), (const T *)nullptr, q);
+            wg_spmv<BS, T, T, T>(n, L, s->rp, s->col, val, p, T(1), T(0), (const T *)nullptr, q);
             __syncthreads();
             T pq = 0;
-            for (int i = tid; i < n; i += kB)
+            for (int i = tid; i < n; i += BS)
                 pq += p[i] * q[i];
-            const T sigma = wg_sum(pq, lds);
+            const T sigma = wg_sum<BS>(pq, lds);
             if (!(sigma > T(0))) {
                 phase = s->inner_iter == 0 ? ck::B_DONE : ck::B_UPDATE;
                 if (phase == ck::B_DONE && tid == 0)
@@ -178,19 +189,19 @@ __global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat
             const T rho = (T)s->rho;
             const T alpha = rho / sigma;
             T rr = 0;
-            for (int i = tid; i < n; i += kB) {
+            for (int i = tid; i < n; i += BS) {
                 d[i] += alpha * p[i];
                 const T ri = r[i] - alpha * q[i];
                 r[i] = ri;
                 rr += ri * ri;
             }
-            const T rho_new = wg_sum(rr, lds);
+            const T rho_new = wg_sum<BS>(rr, lds);
             const int it = s->inner_iter + 1;
             const bool stop = sqrt((double)rho_new) <= s->inner_tol || it >= s->inner_cap ||
                               s->iter + 1 >= s->max_iter;
             const T bcg = rho_new / rho;
             if (!stop)
-                for (int i = tid; i < n; i += kB)
+                for (int i = tid; i < n; i += BS)
                     p[i] = r[i] + bcg * p[i];
             __syncthreads();
             if (tid == 0) {
@@ -208,7 +219,7 @@ __global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat
             T *V = wsp<T>(s, 0);
             T *w = V + (int64_t)(j + 1) * s->ld;
             const T *val = sizeof(T) == 4 ? (const T *)s->val32 : (const T *)s->val64;
-            wg_spmv<T, T, T>(n, L, s->rp, s->col, val, V + (int64_t)j * s->ld, T(1), T(0),
+            wg_spmv<BS, T, T, T>(n, L, s->rp, s->col, val, V + (int64_t)j * s->ld, T(1), T(0),
                              (const T *)nullptr, w);
             __syncthreads();
             for (int pass = 0; pass < 2; ++pass) {
@@ -216,7 +227,7 @@ __global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat
 #pragma unroll
                 for (int c = 0; c <= ck::kBMaxM; ++c)
                     acc[c] = 0;
-                for (int i = tid; i < n; i += kB) {
+                for (int i = tid; i < n; i += BS) {
                     const T wi = w[i];
 #pragma unroll
                     for (int c = 0; c <= ck::kBMaxM; ++c)
@@ -232,12 +243,14 @@ __global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat
                     }
                 __syncthreads();
                 if (tid <= j) {
-                    const T h = (wred[0][tid] + wred[1][tid]) + (wred[2][tid] + wred[3][tid]);
+                    T h = (wred[0][tid] + wred[1][tid]) + (wred[2][tid] + wred[3][tid]);
+                    for (int t = 4; t < NW; t += 4)
+                        h += (wred[t][tid] + wred[t + 1][tid]) + (wred[t + 2][tid] + wred[t + 3][tid]);
                     hcol[tid] = h;
                     hacc[tid] = pass == 0 ? h : hacc[tid] + h;
                 }
                 __syncthreads();
-                for (int i = tid; i < n; i += kB) {
+                for (int i = tid; i < n; i += BS) {
                     T wi = w[i];
                     for (int c = 0; c <= j; ++c)
                         wi -= hcol[c] * V[(int64_t)c * s->ld + i];
@@ -246,9 +259,9 @@ __global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat
                 __syncthreads();
             }
             T nn = 0;
-            for (int i = tid; i < n; i += kB)
+            for (int i = tid; i < n; i += BS)
                 nn += w[i] * w[i];
-            const T hn = sqrt(wg_sum(nn, lds));
+            const T hn = sqrt(wg_sum<BS>(nn, lds));
             __shared__ int stop_sh;
             __shared__ T inv_sh;
             if (tid == 0) {
@@ -295,7 +308,7 @@ __global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat
                 phase = ck::B_UPDATE;
             } else {
                 const T inv = inv_sh;
-                for (int i = tid; i < n; i += kB)
+                for (int i = tid; i < n; i += BS)
                     w[i] *= inv;
             }
             __syncthreads();
@@ -305,7 +318,7 @@ __global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat
         const double beta = s->beta;
         if (s->kind == ck::B_CG) {
             const T *d = wsp<T>(s, 3);
-            for (int i = tid; i < n; i += kB)
+            for (int i = tid; i < n; i += BS)
                 s->x[i] += beta * (double)d[i];
         } else {
             const int k = s->j, m = s->m;
@@ -319,7 +332,7 @@ __global__ __launch_bounds__(256) void batched_chunk(ck::BSlot *slots, ck::BStat
             }
             __syncthreads();
             const T *V = wsp<T>(s, 0);
-            for (int i = tid; i < n; i += kB) {
+            for (int i = tid; i < n; i += BS) {
                 double acc = 0;
                 for (int c = 0; c < k; ++c)
                     acc += (double)s->y[c] * (double)V[(int64_t)c * s->ld + i];
@@ -350,15 +363,23 @@ int64_t bslot_work_elems(int kind, int64_t n, int m) {
 }
 
 ck_status launch_batched_chunk(BSlot *slots, BStat *stat, const int *active, int nactive,
-                               int budget, bool fp32, hipStream_t s) {
+                               int budget, bool fp32, hipStream_t s, bool wide) {
     if (nactive <= 0)
         return CK_OK;
-    if (fp32)
-        hipLaunchKernelGGL((batched_chunk<float>), dim3(nactive), dim3(256), 0, s, slots, stat,
-                           active, budget);
-    else
-        hipLaunchKernelGGL((batched_chunk<double>), dim3(nactive), dim3(256), 0, s, slots, stat,
-                           active, budget);
+    if (wide) {
+        if (fp32)
+            hipLaunchKernelGGL((batched_chunk<float, 1024>), dim3(nactive), dim3(1024), 0, s,
+                               slots, stat, active, budget);
+        else
+            hipLaunchKernelGGL((batched_chunk<double, 1024>), dim3(nactive), dim3(1024), 0, s,
+                               slots, stat, active, budget);
+    } else if (fp32) {
+        hipLaunchKernelGGL((batched_chunk<float, 256>), dim3(nactive), dim3(256), 0, s, slots,
+                           stat, active, budget);
+    } else {
+        hipLaunchKernelGGL((batched_chunk<double, 256>), dim3(nactive), dim3(256), 0, s, slots,
+                           stat, active, budget);
+    }
     CK_HIP(hipGetLastError());
     return CK_OK;
 }

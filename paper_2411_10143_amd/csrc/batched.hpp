@@ -23,6 +23,8 @@ struct BSlot {
     int64_t ld;           // length of one inner vector (n rounded up to 64)
     double bnorm, tol;
     int max_iter, inner_cap;
+    int keep_x0;          // 1: start from the x given; 0: start from x = 0
+    int pad0;
     // state
     int phase, status, iter, outer, inner_iter, j, launches, pad;
     double beta, relres, inner_tol, rho;
@@ -39,7 +41,8 @@ struct BStat {
 
 // elements (of the inner type) of a slot's `work`
 int64_t bslot_work_elems(int kind, int64_t n, int m);
+// wide = 1024 threads per slot (single-system path), else 256
 ck_status launch_batched_chunk(BSlot *slots, BStat *stat, const int *active, int nactive,
-                               int budget, bool fp32, hipStream_t s);
+                               int budget, bool fp32, hipStream_t s, bool wide = false);
 
 }  // namespace ck

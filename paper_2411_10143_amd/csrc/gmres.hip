@@ -2,19 +2,17 @@
 //
 // One Arnoldi step j after the SpMV w = A v_j (written straight into basis
 // column j+1) is classical Gram-Schmidt applied twice, in three fused passes
-// over the basis:
-//   pass 1: h1 = V_j^T w
-//   pass 2: w -= V_j h1, and in the same sweep h2 = V_j^T w
-//   pass 3: w -= V_j h2, and ||w||^2; the last block then forms column j of
-//           the Hessenberg matrix (h1 + h2, ||w||), applies the previous
-//           Givens rotations, makes rotation j, updates the residual estimate
-//           |g_{j+1}| and decides whether the cycle stops.
+// over the basis, each followed by a one-block finish kernel:
+//   pass 1: partials of V_j^T w                       -> finish: h1
+//   pass 2: w -= V_j h1, and in the same sweep partials of V_j^T w -> h2
+//   pass 3: w -= V_j h2, and partials of ||w||^2     -> finish: column j of
+//           the Hessenberg matrix (h1 + h2, ||w||), previous Givens rotations,
+//           rotation j, residual estimate |g_{j+1}|, cycle stop decision
 //   scale : v_{j+1} = w / h_{j+1,j}
-// Each pass streams the j+1 basis columns once; the per-column dot products
-// are reduced in fixed order (wave butterfly, then block order in the last
-// block), so results are deterministic.  The least-squares solve and the
-// solution update close the cycle on the device; nothing returns to the host
-// inside a cycle.
+// Each pass streams the j+1 basis columns once; per-column sums are reduced in
+// a fixed order (wave butterfly, 4 waves, then block order), so results are
+// deterministic.  The least-squares solve and the solution update close the
+// cycle on the device; nothing returns to the host inside a cycle.
 #include "solvers.hpp"
 
 using ck::GmDev;
@@ -44,27 +42,13 @@ __device__ __forceinline__ void block_cols(const T (&acc)[NC], int ncols, T *par
     }
 }
 
-// out[c] = sum_b partials[c*G + b], wave w handles columns w, w+4, ...
-template <typename T>
-__device__ __forceinline__ void reduce_cols(const T *partials, int64_t G, int ncols, T *out) {
-    const int w = threadIdx.x / 64, lane = threadIdx.x & 63;
-    for (int c = w; c < ncols; c += 4) {
-        T s = 0;
-        for (int64_t b = lane; b < G; b += 64)
-            s += __builtin_nontemporal_load(&partials[c * G + b]);
-        s = ck::wave_sum(s);
-        if (lane == 0)
-            out[c] = s;
-    }
-}
-
 }  // namespace
 
 template <typename T, int NC>
 __global__ __launch_bounds__(256) void gm_pass1(int64_t n, int64_t G, int ncols,
                                                 const T *__restrict__ V, int64_t ldv,
                                                 const T *__restrict__ w,
-                                                T *__restrict__ partials, GmDev<T> *st) {
+                                                T *__restrict__ partials, const GmDev<T> *st) {
     if (st->halt)
         return;
     const int64_t b = blockIdx.x;
@@ -80,15 +64,13 @@ __global__ __launch_bounds__(256) void gm_pass1(int64_t n, int64_t G, int ncols,
                 acc[c] += V[c * ldv + i] * wi;
     }
     block_cols<T, NC>(acc, ncols, partials, b, G);
-    if (ck::arrive_last(&st->counter[0], (unsigned)G))
-        reduce_cols(partials, G, ncols, st->h1);
 }
 
 template <typename T, int NC>
 __global__ __launch_bounds__(256) void gm_pass2(int64_t n, int64_t G, int ncols,
                                                 const T *__restrict__ V, int64_t ldv,
                                                 T *__restrict__ w, T *__restrict__ partials,
-                                                GmDev<T> *st) {
+                                                const GmDev<T> *st) {
     if (st->halt)
         return;
     const int64_t b = blockIdx.x;
@@ -114,15 +96,32 @@ __global__ __launch_bounds__(256) void gm_pass2(int64_t n, int64_t G, int ncols,
                 acc[c] += vv[c] * wi;
     }
     block_cols<T, NC>(acc, ncols, partials, b, G);
-    if (ck::arrive_last(&st->counter[1], (unsigned)G))
-        reduce_cols(partials, G, ncols, st->h2);
+}
+
+// out[c] = sum_b partials[c*G + b]; wave w handles columns w, w+4, ...
+template <typename T>
+__global__ __launch_bounds__(256) void gm_finish_cols(int64_t G, int ncols,
+                                                      const T *__restrict__ partials, int which,
+                                                      GmDev<T> *st) {
+    if (st->halt)
+        return;
+    T *out = which == 1 ? st->h1 : st->h2;
+    const int w = threadIdx.x / 64, lane = threadIdx.x & 63;
+    for (int c = w; c < ncols; c += 4) {
+        T s = 0;
+        for (int64_t b = lane; b < G; b += 64)
+            s += partials[c * G + b];
+        s = ck::wave_sum(s);
+        if (lane == 0)
+            out[c] = s;
+    }
 }
 
 template <typename T, int NC>
 __global__ __launch_bounds__(256) void gm_pass3(int64_t n, int64_t G, int ncols,
                                                 const T *__restrict__ V, int64_t ldv,
                                                 T *__restrict__ w, T *__restrict__ partials,
-                                                GmDev<T> *st) {
+                                                const GmDev<T> *st) {
     __shared__ T lds[4];
     if (st->halt)
         return;
@@ -144,12 +143,18 @@ __global__ __launch_bounds__(256) void gm_pass3(int64_t n, int64_t G, int ncols,
     s = ck::block_sum(s, lds);
     if (threadIdx.x == 0)
         partials[b] = s;
-    if (!ck::arrive_last(&st->counter[2], (unsigned)G))
+}
+
+// ||w||, Hessenberg column j, previous rotations, new rotation, estimate
+template <typename T>
+__global__ __launch_bounds__(256) void gm_finish_givens(int64_t G, const T *__restrict__ partials,
+                                                        GmDev<T> *st) {
+    __shared__ T lds[4];
+    if (st->halt)
         return;
     const T nrm2 = ck::sum_partials(partials, G, lds);
     if (threadIdx.x != 0)
         return;
-    // Hessenberg column j, previous rotations, new rotation, residual estimate
     const int m = st->m;
     const int j = st->j;
     T *Hj = st->H + (int64_t)j * (m + 1);
@@ -194,7 +199,7 @@ __global__ __launch_bounds__(256) void gm_pass3(int64_t n, int64_t G, int ncols,
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void gm_scale(int64_t n, T *__restrict__ w, GmDev<T> *st) {
+__global__ __launch_bounds__(256) void gm_scale(int64_t n, T *__restrict__ w, const GmDev<T> *st) {
     if (st->halt)
         return;
     const T inv = st->inv;
@@ -203,12 +208,12 @@ __global__ __launch_bounds__(256) void gm_scale(int64_t n, T *__restrict__ w, Gm
         w[i] *= inv;
 }
 
-// Cycle start: beta = ||r|| (FP64), true-residual convergence test, g = beta e1.
+// Cycle start: partials of ||r||^2 (FP64)
 template <typename T>
 __global__ __launch_bounds__(256) void gm_start_norm(int64_t n, int64_t G,
                                                      const double *__restrict__ r,
                                                      double *__restrict__ partials,
-                                                     GmDev<T> *st) {
+                                                     const GmDev<T> *st) {
     __shared__ double lds[4];
     if (st->final_state != ck::RUN)
         return;
@@ -219,7 +224,15 @@ __global__ __launch_bounds__(256) void gm_start_norm(int64_t n, int64_t G,
     s = ck::block_sum(s, lds);
     if (threadIdx.x == 0)
         partials[b] = s;
-    if (!ck::arrive_last(&st->counter[3], (unsigned)G))
+}
+
+// beta = ||r||, true-residual convergence test, g = beta e1
+template <typename T>
+__global__ __launch_bounds__(256) void gm_start_finish(int64_t G,
+                                                       const double *__restrict__ partials,
+                                                       GmDev<T> *st) {
+    __shared__ double lds[4];
+    if (st->final_state != ck::RUN)
         return;
     const double tot = ck::sum_partials(partials, G, lds);
     if (threadIdx.x != 0)
@@ -315,6 +328,7 @@ ck_status launch_gm_cycle_start(int64_t n, const double *r64, T *v0, double *par
                                 GmDev<T> *st, hipStream_t s) {
     const int64_t G = gm_blocks(n);
     hipLaunchKernelGGL((gm_start_norm<T>), dim3(G), dim3(256), 0, s, n, G, r64, partials64, st);
+    hipLaunchKernelGGL((gm_start_finish<T>), dim3(1), dim3(256), 0, s, G, partials64, st);
     hipLaunchKernelGGL((gm_start_v0<T>), dim3(gm_stream_grid(n)), dim3(256), 0, s, n, v0, r64, st);
     CK_HIP(hipGetLastError());
     return CK_OK;
@@ -325,10 +339,13 @@ static void arnoldi_nc(int64_t n, int64_t G, int ncols, T *V, int64_t ldv, T *w,
                        GmDev<T> *st, hipStream_t s) {
     hipLaunchKernelGGL((gm_pass1<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w,
                        partials, st);
+    hipLaunchKernelGGL((gm_finish_cols<T>), dim3(1), dim3(256), 0, s, G, ncols, partials, 1, st);
     hipLaunchKernelGGL((gm_pass2<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w,
                        partials, st);
+    hipLaunchKernelGGL((gm_finish_cols<T>), dim3(1), dim3(256), 0, s, G, ncols, partials, 2, st);
     hipLaunchKernelGGL((gm_pass3<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w,
                        partials, st);
+    hipLaunchKernelGGL((gm_finish_givens<T>), dim3(1), dim3(256), 0, s, G, partials, st);
 }
 
 // Orthogonalisation and normalisation of w = V[:, j+1] (the SpMV output)

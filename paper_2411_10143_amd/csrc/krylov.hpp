@@ -27,7 +27,6 @@ struct CgDev {
     int iter;         // iterations completed
     int max_iter;
     int pad;
-    unsigned counter[4];   // arrival counters (always back to 0 after a launch)
 };
 
 // GMRES(m) cycle scalars (Givens form of the Hessenberg least squares).
@@ -53,30 +52,15 @@ struct GmDev {
     int final_state;            // RUN, CONVERGED, BREAKDOWN (singular), BUDGET
     int cycles;
     int halt;                   // 1 when cycle_stop or final_state is not RUN
-    unsigned counter[4];
 };
 
 constexpr int FULL = 4;         // cycle_stop value: m steps done
 
-// ---- last-block reductions --------------------------------------------------
-// Each block stores its partial(s), then the block that arrives last (an
-// integer counter; no floating-point atomics) sums all partials in block
-// order and finishes the scalar algebra.  The counter is reset by that block.
-__device__ __forceinline__ bool arrive_last(unsigned *counter, unsigned nblocks) {
-    __shared__ bool last;
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const unsigned prev = atomicAdd(counter, 1u);
-        last = (prev == nblocks - 1);
-        if (last)
-            atomicExch(counter, 0u);
-    }
-    __syncthreads();
-    if (last)
-        __threadfence();
-    return last;
-}
+// ---- two-stage reductions ----------------------------------------------------
+// Every reduction writes one partial per block; a separate one-block
+// "finish" kernel then sums the partials in block order and does the scalar
+// algebra.  The kernel boundary makes the partials visible across XCDs, so no
+// device-scope fence (an L2 write-back on this chip) is issued per block.
 
 // Fixed-order sum of n partials by the 256 threads of one block (valid in
 // thread 0 only).

@@ -26,6 +26,15 @@ struct ck_matrix {
     // COO (after conversion): row index per stored entry; col/val shared with CSR
     int32_t *coo_row = nullptr;
     std::atomic<bool> has_coo{false};
+    // CSR-panel (after conversion): P column panels of width W, panel-major;
+    // panel_rp[p*n + i] = start of row i in panel p (P*n + 1 entries)
+    int panel_P = 0, panel_L = 0;
+    int64_t panel_W = 0;
+    int32_t *panel_rp = nullptr;
+    int32_t *panel_col = nullptr;
+    double *panel_val = nullptr;
+    float *panel_val32 = nullptr;
+    std::atomic<bool> has_panel{false};
     int64_t max_row = -1;             // longest row, once known
     ck_config active{};
     std::mutex mu;                    // guards conversions, `active` and `carry`
@@ -43,8 +52,9 @@ namespace ck {
 //           forms sigma = y.x (x = p, y = q = A p) and its last block sets
 //           alpha = rho/sigma, or state = BREAKDOWN when sigma <= 0.
 //           dot_partials needs spmv_dot_blocks() entries.
-//  carry  : workspace of spmv_carry_bytes() for merge-path and COO; when null
-//           the launch allocates it stream-ordered.
+//  carry  : workspace of spmv_carry_bytes() for merge-path and COO carries
+//           and CSR-panel partial sums; when null the launch allocates it
+//           stream-ordered.
 template <typename T>
 struct SpmvArgs {
     T alpha = 1, beta = 0;

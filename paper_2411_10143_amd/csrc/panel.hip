@@ -1,0 +1,290 @@
+// CSR-panel SpMV: an MI355X-specific CSR algorithm for matrices whose column
+// pattern is scattered (the gathered vector x does not fit one XCD's L2).
+//
+// The GPU has 8 XCDs, each with a private 4 MB L2, and deals workgroups to
+// them round-robin.  The columns are split into P = 8q panels whose slice of
+// x is at most 2 MB; the matrix is stored panel-major (all of panel 0, row by
+// row, then panel 1, ...).  Workgroup b works on panel b % P, so every
+// workgroup of panel p runs on XCD p % 8 and finds its x slice in that XCD's
+// L2 instead of fetching a cache line from the fabric for every entry.  Each
+// panel writes its partial row sums; a combine kernel adds the P partials in
+// panel order (deterministic) and applies alpha/beta (and the fused CG dot).
+#include <algorithm>
+
+#include "matrix.hpp"
+#include "panel.hpp"
+
+using ck::ld_stream;
+
+// cnt[p*n + i] = entries of row i whose column lies in panel p
+__global__ __launch_bounds__(256) void panel_count(int64_t n, int P, int64_t W,
+                                                   const int *__restrict__ rp,
+                                                   const int *__restrict__ col,
+                                                   int *__restrict__ cnt) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n)
+        return;
+    const int k0 = rp[i], k1 = rp[i + 1];
+    int k = k0;
+    for (int p = 0; p < P; ++p) {
+        const int64_t hi = (int64_t)(p + 1) * W;   // first column past panel p
+        int lo = k, top = k1;                        // first entry with col >= hi
+        while (lo < top) {
+            const int mid = (lo + top) >> 1;
+            if (col[mid] < hi)
+                lo = mid + 1;
+            else
+                top = mid;
+        }
+        cnt[(int64_t)p * n + i] = lo - k;
+        k = lo;
+    }
+}
+
+// Panel-major copy: row i's panel-p entries go to prp[p*n + i] onwards.
+template <bool F32>
+__global__ __launch_bounds__(256) void panel_fill(int64_t n, int P, const int *__restrict__ rp,
+                                                  const int *__restrict__ col,
+                                                  const double *__restrict__ val,
+                                                  const int *__restrict__ prp,
+                                                  int *__restrict__ pcol, double *__restrict__ pval,
+                                                  float *__restrict__ pval32) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n)
+        return;
+    int k = rp[i];
+    for (int p = 0; p < P; ++p) {
+        const int dst0 = prp[(int64_t)p * n + i];
+        const int len = prp[(int64_t)p * n + i + 1] - dst0;
+        for (int t = 0; t < len; ++t, ++k) {
+            pcol[dst0 + t] = col[k];
+            pval[dst0 + t] = val[k];
+            if (F32)
+                pval32[dst0 + t] = (float)val[k];
+        }
+    }
+}
+
+// Exclusive scan of Nin int counts into Nout >= Nin outputs (inputs past Nin
+// read as 0, so out[Nin] is the total): 2048 items per workgroup, each thread
+// scanning 8 consecutive items, then the 256 thread totals in order.  The
+// block totals go to sums[] for the next level.
+__global__ __launch_bounds__(256) void scan_blocks(int64_t Nin, int64_t Nout,
+                                                   const int *__restrict__ in,
+                                                   int *__restrict__ out, int *__restrict__ sums) {
+    __shared__ int s[2048];
+    const int64_t base = (int64_t)blockIdx.x * 2048;
+    for (int t = threadIdx.x; t < 2048; t += 256)
+        s[t] = base + t < Nin ? in[base + t] : 0;
+    __syncthreads();
+    int local[8];
+    int acc = 0;
+    for (int t = 0; t < 8; ++t) {
+        local[t] = acc;
+        acc += s[threadIdx.x * 8 + t];
+    }
+    __shared__ int tsum[256];
+    tsum[threadIdx.x] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int run = 0;
+        for (int t = 0; t < 256; ++t) {
+            const int v = tsum[t];
+            tsum[t] = run;
+            run += v;
+        }
+        sums[blockIdx.x] = run;
+    }
+    __syncthreads();
+    const int off = tsum[threadIdx.x];
+    for (int t = 0; t < 8; ++t) {
+        const int64_t g = base + threadIdx.x * 8 + t;
+        if (g < Nout)
+            out[g] = off + local[t];
+    }
+}
+
+__global__ __launch_bounds__(256) void scan_add(int64_t N, int *__restrict__ out,
+                                                const int *__restrict__ offs) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (g < N)
+        out[g] += offs[g / 2048];
+}
+
+// One panel's partial products.  Workgroup b -> panel b % P (and so XCD
+// b % 8), row groups b / P, b / P + Gp, ...
+template <int L, typename T>
+__global__ __launch_bounds__(256) void spmv_panel(int n, int P, int64_t Gp,
+                                                  const int *__restrict__ prp,
+                                                  const int *__restrict__ pcol,
+                                                  const T *__restrict__ pval,
+                                                  const T *__restrict__ x, T *__restrict__ ypart,
+                                                  const int *__restrict__ skip) {
+    if (skip != nullptr && *skip != 0)
+        return;
+    const int p = blockIdx.x % P;
+    const int64_t g0 = blockIdx.x / P;
+    constexpr int R = 256 / L;
+    const int lane = threadIdx.x & (L - 1);
+    const int64_t groups = ((int64_t)n + R - 1) / R;
+    const int *pr = prp + (int64_t)p * n;
+    T *yp = ypart + (int64_t)p * n;
+    for (int64_t g = g0; g < groups; g += Gp) {
+        const int64_t row = g * R + threadIdx.x / L;
+        T sum = 0;
+        if (row < n) {
+            const int k0 = pr[row], k1 = pr[row + 1];
+            T s0 = 0, s1 = 0;
+            int k = k0 + lane;
+            for (; k + L < k1; k += 2 * L) {
+                s0 += ld_stream(&pval[k]) * x[ld_stream(&pcol[k])];
+                s1 += ld_stream(&pval[k + L]) * x[ld_stream(&pcol[k + L])];
+            }
+            if (k < k1)
+                s0 += ld_stream(&pval[k]) * x[ld_stream(&pcol[k])];
+            sum = s0 + s1;
+        }
+        sum = ck::group_sum<L>(sum);
+        if (lane == 0 && row < n)
+            yp[row] = sum;
+    }
+}
+
+// y = alpha * sum_p ypart[p] + beta * y   (+ per-block partial of y.x for CG)
+template <typename T, bool BETA, bool DOT>
+__global__ __launch_bounds__(256) void panel_combine(int64_t n, int P, int64_t G,
+                                                     const T *__restrict__ ypart, T alpha, T beta,
+                                                     T *__restrict__ y, const T *__restrict__ x,
+                                                     T *__restrict__ partials,
+                                                     const int *__restrict__ skip) {
+    if (skip != nullptr && *skip != 0)
+        return;
+    const int64_t b = ck::xcd_block(G);
+    if (b < 0)
+        return;
+    T mine = 0;
+    for (int64_t i = b * 256 + threadIdx.x; i < n; i += G * 256) {
+        T s = 0;
+        for (int p = 0; p < P; ++p)
+            s += ypart[(int64_t)p * n + i];
+        T out = alpha * s;
+        if (BETA)
+            out += beta * y[i];
+        y[i] = out;
+        if (DOT)
+            mine += out * x[i];
+    }
+    if constexpr (DOT) {
+        __shared__ T lds[4];
+        const T d = ck::block_sum(mine, lds);
+        if (threadIdx.x == 0)
+            partials[b] = d;
+    }
+}
+
+namespace ck {
+
+ck_status launch_scan_exclusive(int64_t N, const int *in, int *out, int *tmp, hipStream_t s);
+
+int panel_count_for(int64_t ncols, int value_bytes) {
+    const int64_t per_panel = (2 << 20) / value_bytes;        // x slice <= 2 MB
+    const int64_t q = std::max<int64_t>(1, ceil_div(ncols, 8 * per_panel));
+    return (int)(8 * q);
+}
+
+int panel_lanes_for(int64_t n, int64_t nnz, int P) {
+    const int64_t mean = n > 0 ? nnz / (n * P) : 0;
+    int L = 1;
+    while ((int64_t)L * 2 <= mean && L < 64)
+        L *= 2;
+    return L;
+}
+
+int64_t panel_scan_tmp_elems(int64_t N) {
+    const int64_t b1 = ceil_div(N + 1, 2048);
+    const int64_t b2 = ceil_div(b1, 2048);
+    return b1 + b1 + b2 + b2 + 2048 + 64;
+}
+
+// Exclusive scan of N ints (N + 1 outputs: out[N] = total), three levels.
+ck_status launch_scan_exclusive(int64_t N, const int *in, int *out, int *tmp, hipStream_t s) {
+    const int64_t M = N + 1;                     // in[N] is read as 0 via the bound
+    const int64_t b1 = ceil_div(M, 2048);
+    int *s1 = tmp, *s1x = tmp + b1;              // block sums and their scan
+    const int64_t b2 = ceil_div(b1, 2048);
+    int *s2 = s1x + b1, *s2x = s2 + b2;
+    int *s3 = s2x + b2;
+    if (b2 > 2048)
+        return fail(CK_E_UNSUPPORTED, "scan too large");
+    hipLaunchKernelGGL(scan_blocks, dim3(b1), dim3(256), 0, s, N, M, in, out, s1);
+    hipLaunchKernelGGL(scan_blocks, dim3(b2), dim3(256), 0, s, b1, b1, s1, s1x, s2);
+    hipLaunchKernelGGL(scan_blocks, dim3(1), dim3(256), 0, s, b2, b2, s2, s2x, s3);
+    hipLaunchKernelGGL(scan_add, dim3(ceil_div(b1, 256)), dim3(256), 0, s, b1, s1x, s2x);
+    hipLaunchKernelGGL(scan_add, dim3(ceil_div(M, 256)), dim3(256), 0, s, M, out, s1x);
+    CK_HIP(hipGetLastError());
+    return CK_OK;
+}
+
+ck_status launch_to_panel(const ck_matrix &M, int P, int64_t W, int *cnt, int *tmp, int *prp,
+                          int *pcol, double *pval, float *pval32, hipStream_t s) {
+    const int64_t g = ceil_div(M.n, 256);
+    hipLaunchKernelGGL(panel_count, dim3(g), dim3(256), 0, s, M.n, P, W, M.rp, M.col, cnt);
+    CK_TRY(launch_scan_exclusive((int64_t)P * M.n, cnt, prp, tmp, s));
+    if (pval32)
+        hipLaunchKernelGGL((panel_fill<true>), dim3(g), dim3(256), 0, s, M.n, P, M.rp, M.col,
+                           M.val, prp, pcol, pval, pval32);
+    else
+        hipLaunchKernelGGL((panel_fill<false>), dim3(g), dim3(256), 0, s, M.n, P, M.rp, M.col,
+                           M.val, prp, pcol, pval, pval32);
+    CK_HIP(hipGetLastError());
+    return CK_OK;
+}
+
+template <int L, typename T>
+static void go_panel(const ck_matrix &M, const T *pv, const T *x, T *ypart, const int *skip,
+                     hipStream_t s) {
+    const int64_t groups = ceil_div(M.n, 256 / L);
+    hipLaunchKernelGGL((spmv_panel<L, T>), dim3(groups * M.panel_P), dim3(256), 0, s, (int)M.n,
+                       M.panel_P, groups, M.panel_rp, M.panel_col, pv, x, ypart, skip);
+}
+
+template <typename T>
+ck_status launch_panel_spmv(const ck_matrix &M, const SpmvArgs<T> &a, T *ypart, int64_t G_dot,
+                            hipStream_t s) {
+    const T *pv;
+    if constexpr (sizeof(T) == 4)
+        pv = M.panel_val32;
+    else
+        pv = M.panel_val;
+    switch (M.panel_L) {
+    case 1: go_panel<1, T>(M, pv, a.x, ypart, a.skip, s); break;
+    case 2: go_panel<2, T>(M, pv, a.x, ypart, a.skip, s); break;
+    case 4: go_panel<4, T>(M, pv, a.x, ypart, a.skip, s); break;
+    case 8: go_panel<8, T>(M, pv, a.x, ypart, a.skip, s); break;
+    case 16: go_panel<16, T>(M, pv, a.x, ypart, a.skip, s); break;
+    case 32: go_panel<32, T>(M, pv, a.x, ypart, a.skip, s); break;
+    default: go_panel<64, T>(M, pv, a.x, ypart, a.skip, s); break;
+    }
+    const bool beta = a.beta != T(0);
+    const bool dot = a.cg != nullptr;
+    const int64_t G = dot ? G_dot : ceil_div(M.n, 256);
+    const dim3 grid(xcd_grid(G));
+    if (dot)
+        hipLaunchKernelGGL((panel_combine<T, false, true>), grid, dim3(256), 0, s, M.n, M.panel_P,
+                           G, ypart, a.alpha, a.beta, a.y, a.x, a.dot_partials, a.skip);
+    else if (beta)
+        hipLaunchKernelGGL((panel_combine<T, true, false>), grid, dim3(256), 0, s, M.n, M.panel_P,
+                           G, ypart, a.alpha, a.beta, a.y, a.x, a.dot_partials, a.skip);
+    else
+        hipLaunchKernelGGL((panel_combine<T, false, false>), grid, dim3(256), 0, s, M.n,
+                           M.panel_P, G, ypart, a.alpha, a.beta, a.y, a.x, a.dot_partials, a.skip);
+    CK_HIP(hipGetLastError());
+    return CK_OK;
+}
+
+template ck_status launch_panel_spmv<double>(const ck_matrix &, const SpmvArgs<double> &,
+                                             double *, int64_t, hipStream_t);
+template ck_status launch_panel_spmv<float>(const ck_matrix &, const SpmvArgs<float> &, float *,
+                                            int64_t, hipStream_t);
+
+}  // namespace ck

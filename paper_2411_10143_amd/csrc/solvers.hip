@@ -15,6 +15,7 @@
 #include <cstring>
 #include <thread>
 
+#include "batched.hpp"
 #include "matrix.hpp"
 #include "predictor.hpp"
 #include "solvers.hpp"
@@ -255,9 +256,8 @@ ck_status spmv(SolveCtx &c, T alpha, const T *x, T beta, T *y, const int *skip,
 }
 
 // ||v|| in FP64, blocking (used once per solve / refinement step)
-ck_status norm_host(SolveCtx &c, const double *v, double *partials, unsigned *counter,
-                    double *dout, double &out) {
-    CK_TRY(launch_dot(c.M.n, v, v, partials, counter, dout, c.s));
+ck_status norm_host(SolveCtx &c, const double *v, double *partials, double *dout, double &out) {
+    CK_TRY(launch_dot(c.M.n, v, v, partials, dout, c.s));
     double h = 0;
     CK_HIP(hipMemcpyAsync(&h, dout, sizeof h, hipMemcpyDeviceToHost, c.s));
     CK_HIP(hipStreamSynchronize(c.s));
@@ -267,12 +267,10 @@ ck_status norm_host(SolveCtx &c, const double *v, double *partials, unsigned *co
 
 struct Fp64Scratch {
     double *partials = nullptr, *dout = nullptr;
-    unsigned *counter = nullptr;
-    ck_status init(Workspace &ws, hipStream_t s) {
+    ck_status init(Workspace &ws, hipStream_t) {
         CK_TRY(ws.get(&partials, 1024));
         CK_TRY(ws.get(&dout, 4));
-        CK_TRY(ws.get(&counter, 64));
-        return launch_fill<int>(64, (int *)counter, 0, s);
+        return CK_OK;
     }
 };
 
@@ -282,7 +280,7 @@ ck_status true_relres(SolveCtx &c, const double *b, const double *x, double *r, 
     CK_TRY(launch_copy<double, double>(c.M.n, r, b, nullptr, c.s));
     CK_TRY(spmv<double>(c, -1.0, x, 1.0, r, nullptr));
     double nr = 0;
-    CK_TRY(norm_host(c, r, f.partials, f.counter, f.dout, nr));
+    CK_TRY(norm_host(c, r, f.partials, f.dout, nr));
     out = bnorm > 0 ? nr / bnorm : nr;
     return CK_OK;
 }
@@ -314,6 +312,7 @@ ck_status cg_core(SolveCtx &c, T *x, T *r, T *p, T *q, T *partials, CgDev<T> *de
         const bool fused = spmv_fuses_dot(c.cfg);
         if (fused) {
             CK_TRY(spmv<T>(c, T(1), p, T(0), q, state_ptr, dev, partials));
+            CK_TRY(launch_cg_sigma_finish<T>(spmv_dot_blocks(c.M, c.cfg), partials, dev, c.s));
         } else {
             CK_TRY(spmv<T>(c, T(1), p, T(0), q, state_ptr));
             CK_TRY(launch_cg_sigma<T>(c.M.n, p, q, partials, dev, c.s));
@@ -360,7 +359,7 @@ ck_status cg_fp64(SolveCtx &c, const double *b, double *x) {
     CK_TRY(ws.get(&dev, 1));
     CK_TRY(f.init(ws, c.s));
     double bnorm = 0;
-    CK_TRY(norm_host(c, b, f.partials, f.counter, f.dout, bnorm));
+    CK_TRY(norm_host(c, b, f.partials, f.dout, bnorm));
     if (bnorm == 0.0) {
         CK_TRY(launch_fill<double>(M.n, x, 0.0, c.s));
         c.res.true_relres = 0;
@@ -413,7 +412,7 @@ ck_status cg_mixed(SolveCtx &c, const double *b, double *x) {
     CK_TRY(ws.get(&dev, 1));
     CK_TRY(f.init(ws, c.s));
     double bnorm = 0;
-    CK_TRY(norm_host(c, b, f.partials, f.counter, f.dout, bnorm));
+    CK_TRY(norm_host(c, b, f.partials, f.dout, bnorm));
     if (bnorm == 0.0) {
         CK_TRY(launch_fill<double>(M.n, x, 0.0, c.s));
         c.res.true_relres = 0;
@@ -480,7 +479,7 @@ ck_status gmres_run(SolveCtx &c, const double *b, double *x) {
     CK_TRY(ws.get(&st, 1));
     CK_TRY(f.init(ws, c.s));
     double bnorm = 0;
-    CK_TRY(norm_host(c, b, f.partials, f.counter, f.dout, bnorm));
+    CK_TRY(norm_host(c, b, f.partials, f.dout, bnorm));
     if (bnorm == 0.0) {
         CK_TRY(launch_fill<double>(M.n, x, 0.0, c.s));
         c.res.true_relres = 0;
@@ -552,6 +551,68 @@ ck_status gmres_run(SolveCtx &c, const double *b, double *x) {
 
 enum class Solver { CG, GMRES };
 
+// Systems up to this size run the whole solve inside one 1024-thread
+// workgroup (the batched slot kernel): at this size a launch per step costs
+// more than the step itself.
+constexpr int64_t kSmallN = 16384;
+
+ck_status small_solve(SolveCtx &c, const double *b, double *x, bool cg, int m) {
+    ck_matrix &M = c.M;
+    const bool fp32 = c.o.precision == CK_PREC_MIXED;
+    const int kind = cg ? B_CG : B_GMRES;
+    const int64_t ld = ceil_div(M.n, 64) * 64;
+    Workspace ws(c.s);
+    BSlot *slot;
+    BStat *stat;
+    int *active;
+    char *work;
+    double *r64;
+    CK_TRY(ws.get(&slot, 1));
+    CK_TRY(ws.get(&stat, 1));
+    CK_TRY(ws.get(&active, 1));
+    CK_TRY(ws.get(&work, bslot_work_elems(kind, M.n, m) * (fp32 ? 4 : 8)));
+    CK_TRY(ws.get(&r64, ld));
+    BSlot *h = (BSlot *)std::calloc(1, sizeof(BSlot));
+    h->kind = kind;
+    h->n = (int)M.n;
+    h->lanes = c.cfg.lanes;
+    h->m = m;
+    h->rp = M.rp;
+    h->col = M.col;
+    h->val64 = M.val;
+    h->val32 = M.val32;
+    h->b = b;
+    h->x = x;
+    h->r64 = r64;
+    h->work = work;
+    h->ld = ld;
+    h->bnorm = -1.0;
+    h->tol = c.o.tol;
+    h->max_iter = c.o.max_iter > 0 ? c.o.max_iter : 100000;
+    h->inner_cap = fp32 ? std::max(50, (int)(4.0 * std::sqrt((double)M.n))) : h->max_iter;
+    h->keep_x0 = 1;
+    h->phase = B_OUTER;
+    h->status = RUN;
+    const int budget = 3 * h->max_iter + 64;
+    BStat hs{};
+    hipError_t e = hipMemcpyAsync(slot, h, sizeof(BSlot), hipMemcpyHostToDevice, c.s);
+    std::free(h);
+    CK_HIP(e);
+    CK_TRY(launch_fill<int>(1, active, 0, c.s));
+    CK_TRY(launch_batched_chunk(slot, stat, active, 1, budget, fp32, c.s, true));
+    CK_HIP(hipMemcpyAsync(&hs, stat, sizeof hs, hipMemcpyDeviceToHost, c.s));
+    CK_HIP(hipStreamSynchronize(c.s));
+    c.res.iterations = hs.iter;
+    c.res.outer_steps = hs.outer;
+    c.res.true_relres = hs.relres;
+    if (hs.status == CONVERGED)
+        return CK_OK;
+    if (hs.status == BREAKDOWN)
+        return fail(CK_E_BREAKDOWN, "breakdown (p.Ap <= 0 or a singular least-squares system)");
+    return fail(CK_E_NOT_CONVERGED, "iteration budget spent at relative residual %.3e",
+                hs.relres);
+}
+
 ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *opts,
                 ck_solve_result *res, hipStream_t s, Solver which) {
     if (!hnd || !opts || !res || (hnd->n > 0 && (!b || !x)))
@@ -578,9 +639,20 @@ ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *
         res->final_config = c.cfg;
         return CK_OK;
     }
+    const int m = opts->restart > 0 ? opts->restart : 30;
+    const bool vector_cfg = c.cfg.format == CK_FMT_CSR && c.cfg.algorithm == CK_ALG_VECTOR;
+    if (M.n <= kSmallN && !opts->async && vector_cfg && (which == Solver::CG || m <= kBMaxM)) {
+        const ck_status st = small_solve(c, b, x, which == Solver::CG, m);
+        res->final_config = c.cfg;
+        res->status = st;
+        res->t_total_us = us_since(t0);
+        return st;
+    }
     Workspace ws(s);
     int64_t carry = std::max(spmv_carry_bytes(M, ck_config{CK_FMT_CSR, CK_ALG_MERGE, 0, 0}, false),
-                             spmv_carry_bytes(M, ck_config{CK_FMT_COO, 0, 0, 0}, false));
+                             std::max(spmv_carry_bytes(M, ck_config{CK_FMT_COO, 0, 0, 0}, false),
+                                      spmv_carry_bytes(M, ck_config{CK_FMT_CSR, CK_ALG_PANEL, 0, 0},
+                                                       false)));
     char *cbuf = nullptr;
     CK_TRY(ws.get(&cbuf, carry));
     c.carry = cbuf;

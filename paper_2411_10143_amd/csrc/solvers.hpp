@@ -7,12 +7,15 @@
 namespace ck {
 
 ck_status launch_dot(int64_t n, const double *x, const double *y, double *partials,
-                     unsigned *counter, double *out, hipStream_t s);
+                     double *out, hipStream_t s);
 template <typename T>
 ck_status launch_cg_start(int64_t n, const T *r, T *p, T *partials, CgDev<T> *cg, hipStream_t s);
 template <typename T>
 ck_status launch_cg_sigma(int64_t n, const T *p, const T *q, T *partials, CgDev<T> *cg,
                           hipStream_t s);
+// finishes sigma/alpha from the G partials a fused SpMV launch wrote
+template <typename T>
+ck_status launch_cg_sigma_finish(int64_t G, T *partials, CgDev<T> *cg, hipStream_t s);
 template <typename T>
 ck_status launch_cg_update(int64_t n, T *x, T *r, T *p, const T *q, T *partials, CgDev<T> *cg,
                            hipStream_t s);

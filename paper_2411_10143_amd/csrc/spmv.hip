@@ -24,6 +24,7 @@
 // Every reduction has a fixed order, so a configuration always returns the
 // same bits for the same input.
 #include "matrix.hpp"
+#include "panel.hpp"
 
 using ck::ld_stream;
 
@@ -37,9 +38,9 @@ constexpr int kScalarCap = 4096;  // products staged per LDS chunk (CSR-scalar)
 // CG dot G is capped at kMaxPartials so that the last block can finish the
 // reduction quickly.
 //
-// Fused CG step: every block adds q_i * p_i over its rows (x = p, y = q), the
-// last block to arrive sums the partials in block order and sets
-// alpha = rho / sigma (or flags a breakdown when sigma <= 0).
+// Fused CG step: every block adds q_i * p_i over its rows (x = p, y = q) and
+// stores its partial; the CG "sigma" finish kernel sums them in block order
+// and sets alpha = rho / sigma (or flags a breakdown when sigma <= 0).
 template <typename T, bool DOT>
 __device__ __forceinline__ void cg_sigma_epilogue(T mine, ck::CgDev<T> *cg, T *partials,
                                                   int64_t b, int64_t G) {
@@ -48,16 +49,6 @@ __device__ __forceinline__ void cg_sigma_epilogue(T mine, ck::CgDev<T> *cg, T *p
         const T d = ck::block_sum(mine, lds);
         if (threadIdx.x == 0)
             partials[b] = d;
-        if (ck::arrive_last(&cg->counter[0], (unsigned)G)) {
-            const T sigma = ck::sum_partials(partials, G, lds);
-            if (threadIdx.x == 0) {
-                cg->sigma = sigma;
-                if (!(sigma > T(0)))
-                    cg->state = ck::BREAKDOWN;
-                else
-                    cg->alpha = cg->rho / sigma;
-            }
-        }
     }
 }
 
@@ -413,7 +404,8 @@ bool config_valid(const ck_config &c) {
         return true;
     if (c.format != CK_FMT_CSR)
         return false;
-    if (c.algorithm == CK_ALG_SCALAR || c.algorithm == CK_ALG_MERGE)
+    if (c.algorithm == CK_ALG_SCALAR || c.algorithm == CK_ALG_MERGE ||
+        c.algorithm == CK_ALG_PANEL)
         return true;
     if (c.algorithm != CK_ALG_VECTOR)
         return false;
@@ -422,7 +414,9 @@ bool config_valid(const ck_config &c) {
 
 bool spmv_fuses_dot(const ck_config &c) {
     return c.format == CK_FMT_ELL ||
-           (c.format == CK_FMT_CSR && (c.algorithm == CK_ALG_VECTOR || c.algorithm == CK_ALG_SCALAR));
+           (c.format == CK_FMT_CSR && (c.algorithm == CK_ALG_VECTOR ||
+                                       c.algorithm == CK_ALG_SCALAR ||
+                                       c.algorithm == CK_ALG_PANEL));
 }
 
 static int64_t row_groups(const ck_matrix &M, const ck_config &c) {
@@ -447,6 +441,8 @@ static int64_t carry_blocks(const ck_matrix &M, const ck_config &c) {
 }
 
 int64_t spmv_carry_bytes(const ck_matrix &M, const ck_config &c, bool fp32) {
+    if (c.format == CK_FMT_CSR && c.algorithm == CK_ALG_PANEL)   // per-panel partial sums
+        return (int64_t)panel_count_for(M.ncols, 8) * M.n * (fp32 ? 4 : 8) + 256;
     const int64_t G = carry_blocks(M, c);
     return ((G * (int64_t)sizeof(int) + 255) / 256) * 256 + G * (fp32 ? 4 : 8) + 256;
 }
@@ -480,6 +476,8 @@ const char *kernel_name(const ck_config &c, bool fp32) {
         return fp32 ? "spmv_csr_scalar<float, false, false>" : "spmv_csr_scalar<double, false, false>";
     if (c.algorithm == CK_ALG_MERGE)
         return fp32 ? "spmv_merge<float, false>" : "spmv_merge<double, false>";
+    if (c.algorithm == CK_ALG_PANEL)
+        return fp32 ? "spmv_panel<4, float>" : "spmv_panel<4, double>";
     int idx = 0;
     while ((1 << idx) < c.lanes)
         ++idx;
@@ -578,6 +576,9 @@ ck_status launch_spmv(const ck_matrix &M, const ck_config &c, const SpmvArgs<T> 
         return fail(CK_E_INVALID, "ELL requested but the matrix has not been converted");
     if (c.format == CK_FMT_COO && !M.has_coo.load())
         return fail(CK_E_INVALID, "COO requested but the matrix has not been converted");
+    const bool panel = c.format == CK_FMT_CSR && c.algorithm == CK_ALG_PANEL;
+    if (panel && !M.has_panel.load())
+        return fail(CK_E_INVALID, "CSR-panel requested but the matrix has not been converted");
     const bool beta = a.beta != T(0);
     const bool dot = a.cg != nullptr;
     if (dot && (!spmv_fuses_dot(c) || a.dot_partials == nullptr))
@@ -585,7 +586,14 @@ ck_status launch_spmv(const ck_matrix &M, const ck_config &c, const SpmvArgs<T> 
     if (M.n == 0)
         return CK_OK;
     ck_status st;
-    if (M.nnz == 0 && !dot) {
+    if (panel) {
+        void *ws = a.carry;
+        if (ws == nullptr)
+            CK_HIP(hipMallocAsync(&ws, (size_t)spmv_carry_bytes(M, c, sizeof(T) == 4), s));
+        st = launch_panel_spmv<T>(M, a, (T *)ws, spmv_dot_blocks(M, c), s);
+        if (a.carry == nullptr)
+            CK_HIP(hipFreeAsync(ws, s));
+    } else if (M.nnz == 0 && !dot) {
         if (beta)
             hipLaunchKernelGGL((scale_rows<T, true>), dim3(ceil_div(M.n, 256)), dim3(256), 0, s,
                                M.n, a.beta, a.y, a.skip);

@@ -1,8 +1,9 @@
 // Krylov vector kernels: deterministic dot products and the fused CG updates
 // (the "vector inner product and other kernels" beside SpMV in CG and GMRES,
-// Introduction).  All are HBM-bound streams; reductions use a fixed order
-// (grid-stride per thread -> wave butterfly -> 4 waves -> partial per block,
-// then the last block to arrive sums the partials in block order).
+// Introduction).  All are HBM-bound streams.  Reductions are two-stage with a
+// fixed order: grid-stride sum per thread -> wave butterfly -> 4 waves ->
+// one partial per block; a one-block finish kernel then sums the partials in
+// block order and updates the device-resident scalars.
 #include "matrix.hpp"
 #include "solvers.hpp"
 
@@ -24,11 +25,11 @@ using ck::CgDev;
 
 __device__ __forceinline__ bool skipped_v(const int *skip) { return skip != nullptr && *skip != 0; }
 
-// out[0] = x . y  (FP64 in, FP64 accumulate)
-__global__ __launch_bounds__(256) void dot_kernel(int64_t n, int64_t G, const double *__restrict__ x,
-                                                  const double *__restrict__ y,
-                                                  double *__restrict__ partials,
-                                                  unsigned *counter, double *__restrict__ out) {
+// partials[b] = sum over this block's grid-stride share of x_i * y_i
+__global__ __launch_bounds__(256) void dot_partial(int64_t n, int64_t G,
+                                                   const double *__restrict__ x,
+                                                   const double *__restrict__ y,
+                                                   double *__restrict__ partials) {
     __shared__ double lds[4];
     const int64_t b = blockIdx.x;
     double s = 0;
@@ -37,19 +38,21 @@ __global__ __launch_bounds__(256) void dot_kernel(int64_t n, int64_t G, const do
     s = ck::block_sum(s, lds);
     if (threadIdx.x == 0)
         partials[b] = s;
-    if (ck::arrive_last(counter, (unsigned)G)) {
-        const double t = ck::sum_partials(partials, G, lds);
-        if (threadIdx.x == 0)
-            out[0] = t;
-    }
 }
 
-// Start of a CG run from a residual r already in place:
-// rho = r.r, relres = sqrt(rho)/bnorm, p = r; CONVERGED if relres <= tol.
+__global__ __launch_bounds__(256) void dot_finish(int64_t G, const double *__restrict__ partials,
+                                                  double *__restrict__ out) {
+    __shared__ double lds[4];
+    const double t = ck::sum_partials(partials, G, lds);
+    if (threadIdx.x == 0)
+        out[0] = t;
+}
+
+// CG start from a residual already in r: p = r, partials of r.r
 template <typename T>
 __global__ __launch_bounds__(256) void cg_start(int64_t n, int64_t G, const T *__restrict__ r,
                                                 T *__restrict__ p, T *__restrict__ partials,
-                                                CgDev<T> *cg) {
+                                                const CgDev<T> *cg) {
     __shared__ T lds[4];
     if (cg->state != ck::RUN)
         return;
@@ -63,25 +66,31 @@ __global__ __launch_bounds__(256) void cg_start(int64_t n, int64_t G, const T *_
     s = ck::block_sum(s, lds);
     if (threadIdx.x == 0)
         partials[b] = s;
-    if (ck::arrive_last(&cg->counter[1], (unsigned)G)) {
-        const T rho = ck::sum_partials(partials, G, lds);
-        if (threadIdx.x == 0) {
-            cg->rho = rho;
-            cg->relres = sqrt((double)rho) / cg->bnorm;
-            if (cg->relres <= cg->tol)
-                cg->state = ck::CONVERGED;
-            else if (cg->iter >= cg->max_iter)
-                cg->state = ck::BUDGET;
-        }
+}
+
+// rho = r.r, relres = sqrt(rho)/bnorm; CONVERGED or BUDGET ends the run
+template <typename T>
+__global__ __launch_bounds__(256) void cg_start_finish(int64_t G, const T *__restrict__ partials,
+                                                       CgDev<T> *cg) {
+    __shared__ T lds[4];
+    if (cg->state != ck::RUN)
+        return;
+    const T rho = ck::sum_partials(partials, G, lds);
+    if (threadIdx.x == 0) {
+        cg->rho = rho;
+        cg->relres = sqrt((double)rho) / cg->bnorm;
+        if (cg->relres <= cg->tol)
+            cg->state = ck::CONVERGED;
+        else if (cg->iter >= cg->max_iter)
+            cg->state = ck::BUDGET;
     }
 }
 
-// sigma = p.q and alpha = rho/sigma, for configurations whose SpMV does not
-// fuse the dot product (merge-path, COO).
+// partials of p.q, for configurations whose SpMV does not fuse the dot
 template <typename T>
 __global__ __launch_bounds__(256) void cg_sigma(int64_t n, int64_t G, const T *__restrict__ p,
                                                 const T *__restrict__ q, T *__restrict__ partials,
-                                                CgDev<T> *cg) {
+                                                const CgDev<T> *cg) {
     __shared__ T lds[4];
     if (cg->state != ck::RUN)
         return;
@@ -92,25 +101,31 @@ __global__ __launch_bounds__(256) void cg_sigma(int64_t n, int64_t G, const T *_
     s = ck::block_sum(s, lds);
     if (threadIdx.x == 0)
         partials[b] = s;
-    if (ck::arrive_last(&cg->counter[0], (unsigned)G)) {
-        const T sigma = ck::sum_partials(partials, G, lds);
-        if (threadIdx.x == 0) {
-            cg->sigma = sigma;
-            if (!(sigma > T(0)))
-                cg->state = ck::BREAKDOWN;
-            else
-                cg->alpha = cg->rho / sigma;
-        }
+}
+
+// sigma = p.Ap; alpha = rho/sigma, or BREAKDOWN when sigma <= 0
+template <typename T>
+__global__ __launch_bounds__(256) void cg_sigma_finish(int64_t G, const T *__restrict__ partials,
+                                                       CgDev<T> *cg) {
+    __shared__ T lds[4];
+    if (cg->state != ck::RUN)
+        return;
+    const T sigma = ck::sum_partials(partials, G, lds);
+    if (threadIdx.x == 0) {
+        cg->sigma = sigma;
+        if (!(sigma > T(0)))
+            cg->state = ck::BREAKDOWN;
+        else
+            cg->alpha = cg->rho / sigma;
     }
 }
 
-// x += alpha p; r -= alpha q; rho' = r.r; beta = rho'/rho; convergence test on
-// the recurred residual sqrt(rho')/bnorm.
+// x += alpha p; r -= alpha q; partials of r.r
 template <typename T>
 __global__ __launch_bounds__(256) void cg_update_xr(int64_t n, int64_t G, T *__restrict__ x,
                                                     T *__restrict__ r, const T *__restrict__ p,
                                                     const T *__restrict__ q,
-                                                    T *__restrict__ partials, CgDev<T> *cg) {
+                                                    T *__restrict__ partials, const CgDev<T> *cg) {
     __shared__ T lds[4];
     if (cg->state != ck::RUN)
         return;
@@ -126,18 +141,25 @@ __global__ __launch_bounds__(256) void cg_update_xr(int64_t n, int64_t G, T *__r
     s = ck::block_sum(s, lds);
     if (threadIdx.x == 0)
         partials[b] = s;
-    if (ck::arrive_last(&cg->counter[2], (unsigned)G)) {
-        const T rho_new = ck::sum_partials(partials, G, lds);
-        if (threadIdx.x == 0) {
-            cg->beta = rho_new / cg->rho;
-            cg->rho = rho_new;
-            cg->iter += 1;
-            cg->relres = sqrt((double)rho_new) / cg->bnorm;
-            if (cg->relres <= cg->tol)
-                cg->state = ck::CONVERGED;
-            else if (cg->iter >= cg->max_iter)
-                cg->state = ck::BUDGET;
-        }
+}
+
+// rho' = r.r; beta = rho'/rho; convergence test on sqrt(rho')/bnorm
+template <typename T>
+__global__ __launch_bounds__(256) void cg_rho_finish(int64_t G, const T *__restrict__ partials,
+                                                     CgDev<T> *cg) {
+    __shared__ T lds[4];
+    if (cg->state != ck::RUN)
+        return;
+    const T rho_new = ck::sum_partials(partials, G, lds);
+    if (threadIdx.x == 0) {
+        cg->beta = rho_new / cg->rho;
+        cg->rho = rho_new;
+        cg->iter += 1;
+        cg->relres = sqrt((double)rho_new) / cg->bnorm;
+        if (cg->relres <= cg->tol)
+            cg->state = ck::CONVERGED;
+        else if (cg->iter >= cg->max_iter)
+            cg->state = ck::BUDGET;
     }
 }
 
@@ -210,10 +232,11 @@ static int64_t stream_grid(int64_t n) {
     return g < 8192 ? g : 8192;
 }
 
-ck_status launch_dot(int64_t n, const double *x, const double *y, double *partials,
-                     unsigned *counter, double *out, hipStream_t s) {
+ck_status launch_dot(int64_t n, const double *x, const double *y, double *partials, double *out,
+                     hipStream_t s) {
     const int64_t G = dot_blocks<double>(n);
-    hipLaunchKernelGGL(dot_kernel, dim3(G), dim3(256), 0, s, n, G, x, y, partials, counter, out);
+    hipLaunchKernelGGL(dot_partial, dim3(G), dim3(256), 0, s, n, G, x, y, partials);
+    hipLaunchKernelGGL(dot_finish, dim3(1), dim3(256), 0, s, G, partials, out);
     CK_HIP(hipGetLastError());
     return CK_OK;
 }
@@ -222,6 +245,7 @@ template <typename T>
 ck_status launch_cg_start(int64_t n, const T *r, T *p, T *partials, CgDev<T> *cg, hipStream_t s) {
     const int64_t G = dot_blocks<T>(n);
     hipLaunchKernelGGL((cg_start<T>), dim3(G), dim3(256), 0, s, n, G, r, p, partials, cg);
+    hipLaunchKernelGGL((cg_start_finish<T>), dim3(1), dim3(256), 0, s, G, partials, cg);
     CK_HIP(hipGetLastError());
     return CK_OK;
 }
@@ -231,6 +255,14 @@ ck_status launch_cg_sigma(int64_t n, const T *p, const T *q, T *partials, CgDev<
                           hipStream_t s) {
     const int64_t G = dot_blocks<T>(n);
     hipLaunchKernelGGL((cg_sigma<T>), dim3(G), dim3(256), 0, s, n, G, p, q, partials, cg);
+    hipLaunchKernelGGL((cg_sigma_finish<T>), dim3(1), dim3(256), 0, s, G, partials, cg);
+    CK_HIP(hipGetLastError());
+    return CK_OK;
+}
+
+template <typename T>
+ck_status launch_cg_sigma_finish(int64_t G, T *partials, CgDev<T> *cg, hipStream_t s) {
+    hipLaunchKernelGGL((cg_sigma_finish<T>), dim3(1), dim3(256), 0, s, G, partials, cg);
     CK_HIP(hipGetLastError());
     return CK_OK;
 }
@@ -241,6 +273,7 @@ ck_status launch_cg_update(int64_t n, T *x, T *r, T *p, const T *q, T *partials,
     const int64_t G = dot_blocks<T>(n);
     hipLaunchKernelGGL((cg_update_xr<T>), dim3(G), dim3(256), 0, s, n, G, x, r, p, q, partials,
                        cg);
+    hipLaunchKernelGGL((cg_rho_finish<T>), dim3(1), dim3(256), 0, s, G, partials, cg);
     hipLaunchKernelGGL((cg_update_p<T>), dim3(stream_grid(n)), dim3(256), 0, s, n, p, r, cg);
     CK_HIP(hipGetLastError());
     return CK_OK;
@@ -286,6 +319,7 @@ ck_status launch_fill(int64_t n, T *dst, T v, hipStream_t s) {
                                           hipStream_t);                                     \
     template ck_status launch_cg_sigma<T>(int64_t, const T *, const T *, T *, CgDev<T> *,   \
                                           hipStream_t);                                     \
+    template ck_status launch_cg_sigma_finish<T>(int64_t, T *, CgDev<T> *, hipStream_t);    \
     template ck_status launch_cg_update<T>(int64_t, T *, T *, T *, const T *, T *,          \
                                            CgDev<T> *, hipStream_t);                        \
     template ck_status launch_scale_cast<T>(int64_t, T *, const double *, const double *,   \

@@ -31,7 +31,8 @@ import numpy as np
 
 FEATURES = ["nrows", "ncols", "nnz", "density", "mean", "sd", "cov", "max", "min", "maxavg",
             "distavg", "clusteravg", "fill", "ndiag", "diagfill"]
-CONFIGS = 11
+CONFIGS = 12
+CSR_IDS = (0, 1, 2, 3, 4, 5, 6, 7, 8, 11)   # configurations stored in CSR (incl. CSR-panel)
 
 
 def reps_for(us_probe: float, budget_us: float = 4000.0, lo: int = 20, hi: int = 200) -> int:
@@ -59,14 +60,17 @@ def time_all_configs(ck, Mx, x, y, warmup=10, reps=None):
 
 
 def labels(times):
-    """(format, algorithm, log2 lanes) labels from the 11 configuration times."""
-    t = np.asarray(times, dtype=np.float64)
+    """(format, algorithm, log2 lanes) labels from the configuration times
+    (ids: 0-6 CSR-vector lanes 1..64, 7 scalar, 8 merge, 9 ELL, 10 COO,
+    11 CSR-panel; a time of inf marks a refused conversion)."""
+    t = np.full(CONFIGS, np.inf)
+    t[:len(times)] = np.asarray(times, dtype=np.float64)
     best = int(np.argmin(t))          # argmin takes the first (lowest index) on ties
-    fmt = 0 if best <= 8 else (1 if best == 9 else 2)
+    fmt = 1 if best == 9 else (2 if best == 10 else 0)
     lanes = int(np.argmin(t[:7]))
     # candidates in configuration-index order: vector at its best lanes (id
-    # 0..6), scalar (7), merge (8); argmin keeps the first on ties
-    cand = [(t[lanes], 1), (t[7], 0), (t[8], 2)]
+    # 0..6), scalar (7), merge (8), panel (11); argmin keeps the first on ties
+    cand = [(t[lanes], 1), (t[7], 0), (t[8], 2), (t[11], 3)]
     alg = cand[int(np.argmin([c[0] for c in cand]))][1]
     return fmt, alg, lanes
 
@@ -114,7 +118,9 @@ def load(path):
     with open(path) as f:
         for row in csv.DictReader(f):
             X.append([float(row[k]) for k in FEATURES])
-            T.append([float(row[f"t{c}"]) for c in range(CONFIGS)])
+            # files written before a configuration existed lack its column
+            T.append([float(row[f"t{c}"]) if f"t{c}" in row else math.inf
+                      for c in range(CONFIGS)])
             names.append(row["name"])
     return np.array(X), np.array(T), names
 
@@ -168,6 +174,8 @@ def cascade_predict(trees, x):
         return 7
     if alg == 2:
         return 8
+    if alg == 3:
+        return 11
     return int(trees[2].predict(x)[0])
 
 
@@ -182,7 +190,7 @@ def main(argv=None):
     fa = sub.add_parser("fit")
     fa.add_argument("--data", required=True, nargs="+")
     fa.add_argument("--model", required=True)
-    fa.add_argument("--max-depth", type=int, default=5)
+    fa.add_argument("--max-depth", type=int, default=4)
     fa.add_argument("--min-leaf", type=int, default=1)
     a = p.parse_args(argv)
     if a.cmd == "collect":

@@ -48,7 +48,7 @@ def test_host_only_calls_work_without_gpu():
         assert ck.config_id(c) == i
         assert ck.kernel_name(c).startswith("spmv_")
     try:
-        ck.config_from_id(11)
+        ck.config_from_id(ck.NUM_CONFIGS)
         raise AssertionError("expected an error")
     except ck.CkError as e:
         assert e.status == ck.CK_E_INVALID

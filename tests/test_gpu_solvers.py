@@ -46,7 +46,7 @@ def test_cg_lap2d_64_default_config(ck, orc):
     Mx.close()
 
 
-@pytest.mark.parametrize("cid", range(11))
+@pytest.mark.parametrize("cid", range(12))
 def test_cg_every_config(ck, orc, cid):
     A = M.laplacian_2d(40)
     xs, b = problem(orc, A, 2)
@@ -118,7 +118,7 @@ def test_gmres_convdiff_fp64(ck, orc):
     Mx.close()
 
 
-@pytest.mark.parametrize("cid", range(11))
+@pytest.mark.parametrize("cid", range(12))
 def test_gmres_every_config(ck, orc, cid):
     A = M.convection_diffusion_2d(24, 10.0)
     xs, b = problem(orc, A, 5)

@@ -22,6 +22,9 @@ def test_labels_rule_and_ties():
     # ties go to the lower configuration index
     t = [2.0, 2.0, 3, 3, 3, 3, 3, 2.0, 2.0, 2.0, 2.0]
     assert train.labels(t) == (0, 1, 0)
+    # CSR-panel (id 11) fastest: a CSR format label and algorithm class 3
+    t = [9, 8, 7, 6, 5, 4, 4, 5, 3.0, 8, 2.0, 1.0]
+    assert train.labels(t) == (0, 3, 5)
 
 
 def test_export_round_trip_matches_sklearn(orc, tmp_path):
@@ -46,6 +49,8 @@ def test_export_round_trip_matches_sklearn(orc, tmp_path):
             assert cid == 7
         elif stages[1] == 2:
             assert cid == 8
+        elif stages[1] == 3:
+            assert cid == 11
         else:
             assert cid == stages[2]
 
@@ -60,5 +65,5 @@ def test_shipped_model_is_well_formed():
                 assert 0 <= t["feature"][i] < 15
                 assert i < t["left"][i] < n and i < t["right"][i] < n
     assert {c for c in trees[0]["cls"] if c >= 0} <= {0, 1, 2}
-    assert {c for c in trees[1]["cls"] if c >= 0} <= {0, 1, 2}
+    assert {c for c in trees[1]["cls"] if c >= 0} <= {0, 1, 2, 3}
     assert {c for c in trees[2]["cls"] if c >= 0} <= set(range(7))

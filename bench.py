@@ -46,8 +46,8 @@ def log(*a):
 
 
 class KernelLedger:
-    """Event-timed batches of SpMV launches, per device kernel symbol, over the
-    whole process (so the per-launch average matches a profiler's)."""
+    """Event-timed batches of SpMV launches inside the timed steps, per device
+    kernel symbol (HIP events recorded by the library on the launch stream)."""
 
     def __init__(self):
         self.k = {}
@@ -61,6 +61,10 @@ class KernelLedger:
     def summary(self, name):
         n, us, by = self.k[name]
         return dict(launches=n, avg_us=us / n, achieved_GBs=by / (us * 1e3))
+
+    def dominant(self):
+        """Kernel with the largest total time."""
+        return max(self.k, key=lambda name: self.k[name][1])
 
 
 def flush_cache(buf):
@@ -114,6 +118,9 @@ def bench_spmv_set(args):
     for m, (A, d) in enumerate(zip(mats, dev)):
         Mx = ck.Matrix(d["rp"], d["col"], d["val"], A.ncols)
         default_id.append(ck.config_id(ck.default_config(Mx.handle)))
+        if args.no_table:
+            Mx.close()
+            continue
         for cid in range(ck.NUM_CONFIGS):
             cfg = ck.config_from_id(cid)
             try:
@@ -122,9 +129,7 @@ def bench_spmv_set(args):
                 if e.status != ck.CK_E_UNSUPPORTED:
                     raise
                 continue
-            us = ck.time_spmv(Mx.handle, cfg, d["x"], d["y"], warmup=10, reps=R)
-            T[m, cid] = us
-            ledger.add(ck.kernel_name(cfg), R, us, nbytes[m])
+            T[m, cid] = ck.time_spmv(Mx.handle, cfg, d["x"], d["y"], warmup=10, reps=R)
         Mx.close()
         log(f"[table {m + 1}/{len(mats)}] {A.name} best={ck.CONFIG_NAMES[int(np.argmin(T[m]))]}"
             f" {T[m].min():.2f}us default={T[m, default_id[-1]]:.2f}us")
@@ -165,25 +170,15 @@ def bench_spmv_set(args):
     bytes_step = R * sum(nbytes)
     value = bytes_step * len(step_times) / sum(step_times) / 1e9
 
-    # ---- predicted vs best vs default from the exhaustive table -------------
-    best = T.min(axis=1)
-    t_pred = np.array([T[m, p] for m, p in enumerate(picks)])
-    t_def = np.array([T[m, default_id[m]] for m in range(len(mats))])
-    ratio = t_pred / best
-    agg = lambda t: float(sum(nbytes) / (np.sum(t) * 1e3))   # GB/s over the set
-    # per-kernel totals inside the timed steps decide the dominant kernel
-    timed = {}
-    for m, p in enumerate(picks):
-        name = ck.kernel_name(ck.config_from_id(p))
-        timed[name] = timed.get(name, 0.0) + T[m, p]
-    dominant = max(timed, key=timed.get)
+    # the kernel with the largest total time inside the timed steps
+    dominant = ledger.dominant()
     ks = ledger.summary(dominant)
 
     # ---- cold products on the large matrices ---------------------------------
     cold = []
     flushbuf = torch.empty(2 ** 27, dtype=torch.float64, device="cuda")
     for m, (A, d) in enumerate(zip(mats, dev)):
-        if nbytes[m] < LARGE_BYTES:
+        if nbytes[m] < LARGE_BYTES or args.no_table:
             continue
         Mx = ck.Matrix(d["rp"], d["col"], d["val"], A.ncols)
         row = dict(matrix=A.name, MB=round(nbytes[m] / 1e6, 1))
@@ -250,17 +245,27 @@ def bench_spmv_set(args):
                      "traffic": traffic_for(dominant)},
         "cpu_baseline": cpu,
         "spmv": {
+            "kernel_GBs_in_steps": round(bytes_step / (np.mean(spmv_totals) * 1e3), 1),
+            "copy_GBs": round(copy_gbs, 1),
+            "kernels_in_steps": {k: dict(launches=v[0], avg_us=round(v[1] / v[0], 3))
+                                 for k, v in sorted(ledger.k.items())},
+        },
+    }
+    if not args.no_table:
+        # predicted vs exhaustive-best vs default, all from the warm table
+        best = T.min(axis=1)
+        t_pred = np.array([T[m, p] for m, p in enumerate(picks)])
+        t_def = np.array([T[m, default_id[m]] for m in range(len(mats))])
+        ratio = t_pred / best
+        agg = lambda t: float(sum(nbytes) / (np.sum(t) * 1e3))   # GB/s over the set
+        out["spmv"].update({
             "predicted_GBs": round(agg(t_pred), 1), "best_GBs": round(agg(best), 1),
             "default_csr_vector_GBs": round(agg(t_def), 1),
             "geomean_t_pred_over_t_best": round(geomean(ratio), 4),
             "geomean_t_default_over_t_best": round(geomean(t_def / best), 4),
             "picked_best": int(np.sum(ratio <= 1.0)), "within_10pct": int(np.sum(ratio <= 1.10)),
-            "of": len(mats),
-            "kernel_GBs_in_steps": round(bytes_step / (np.mean(spmv_totals) * 1e3), 1),
-            "copy_GBs": round(copy_gbs, 1), "cold_large": cold,
-        },
-    }
-    if args.table:
+            "of": len(mats), "cold_large": cold})
+    if args.table and not args.no_table:
         rows = []
         for m, A in enumerate(mats):
             rows.append(dict(matrix=A.name, n=A.n, nnz=A.nnz, MB=round(nbytes[m] / 1e6, 2),
@@ -577,6 +582,8 @@ def main():
     p.add_argument("--max-n", type=int, default=None, help="drop set members above this n")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--table", default=None, help="write the per-matrix timing table (JSON)")
+    p.add_argument("--no-table", action="store_true",
+                   help="spmv_set: skip the untimed exhaustive and cold tables (profiler runs)")
     p.add_argument("--grid", type=int, default=1024, help="gmres_mixed grid side")
     p.add_argument("--requests", type=int, default=2000, help="serve: requests per trace")
     p.add_argument("--tol", type=float, default=1e-8, help="serve: tolerance")

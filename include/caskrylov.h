@@ -288,6 +288,9 @@ typedef struct {
     double t_submit_us, t_admit_us, t_done_us;   /* ck_server_clock_us() times     */
 } ck_completion;
 
+/* prediction_cache_hits counts admissions that found the matrix's features
+ * and cascade decision already cached; prediction_cache_misses counts the
+ * feature extractions and predictions actually run. */
 typedef struct {
     int64_t submitted, completed, queued, in_flight, resident_matrices, evictions,
         bytes_in_use, batched_launches, prediction_cache_hits, prediction_cache_misses;

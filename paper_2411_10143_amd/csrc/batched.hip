@@ -38,25 +38,54 @@ __device__ __forceinline__ T wg_sum(T v, T *lds) {
     return r;
 }
 
-// y[i] = s1 * (A x)[i] + s0 * z[i] with L lanes per row (runtime power of two)
+// y[i] = s1 * (A x)[i] + s0 * z[i] with L lanes per row (runtime power of two).
+// Each thread carries kRowsInFlight rows at once so that their dependent
+// loads (row pointer -> column -> x) overlap: the matrix and vectors of a
+// small system sit in L2, and the product is bound by load latency, not
+// bandwidth.  Per row the lanes still sum entries k = start + lane,
+// start + lane + L, ... in order, then butterfly over the L lanes.
+constexpr int kRowsInFlight = 4;
+
 template <int BS, typename TV, typename TX, typename TA>
 __device__ void wg_spmv(int n, int L, const int *__restrict__ rp, const int *__restrict__ col,
                         const TV *__restrict__ val, const TX *__restrict__ x, TA s1, TA s0,
                         const TA *__restrict__ z, TA *__restrict__ y) {
+    constexpr int U = kRowsInFlight;
     const int lane = threadIdx.x & (L - 1);
     const int rpp = BS / L;
-    for (int r0 = 0; r0 < n; r0 += rpp) {
-        const int row = r0 + threadIdx.x / L;
-        TA acc = 0;
-        if (row < n) {
-            const int k1 = rp[row + 1];
-            for (int k = rp[row] + lane; k < k1; k += L)
-                acc += (TA)val[k] * (TA)x[col[k]];
+    for (int r0 = 0; r0 < n; r0 += U * rpp) {
+        int kb[U], ke[U];
+        TA acc[U];
+        int trips = 0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int row = r0 + u * rpp + threadIdx.x / L;
+            kb[u] = 0;
+            ke[u] = 0;
+            acc[u] = 0;
+            if (row < n) {
+                kb[u] = rp[row] + lane;
+                ke[u] = rp[row + 1];
+            }
+            trips = max(trips, (ke[u] - kb[u] + L - 1) / L);
         }
-        for (int off = L >> 1; off > 0; off >>= 1)
-            acc += __shfl_xor(acc, off, 64);
-        if (lane == 0 && row < n)
-            y[row] = z ? s1 * acc + s0 * z[row] : s1 * acc;
+        for (int t = 0; t < trips; ++t) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = kb[u] + t * L;
+                if (k < ke[u])
+                    acc[u] += (TA)val[k] * (TA)x[col[k]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            TA a = acc[u];
+            for (int off = L >> 1; off > 0; off >>= 1)
+                a += __shfl_xor(a, off, 64);
+            const int row = r0 + u * rpp + threadIdx.x / L;
+            if (lane == 0 && row < n)
+                y[row] = z ? s1 * a + s0 * z[row] : s1 * a;
+        }
     }
 }
 

@@ -64,37 +64,58 @@ __global__ void feat_init(FeatAcc *acc) {
     }
 }
 
+// Grid-stride over rows; each block folds its rows in registers and LDS and
+// adds one value per field to the global accumulators, so no address sees
+// more atomics than there are blocks.
 __global__ __launch_bounds__(256) void feat_rows(int64_t n, const int *__restrict__ rp,
                                                  const int *__restrict__ col, FeatAcc *acc) {
     __shared__ unsigned long long h[16];
+    __shared__ unsigned long long part[5][4];
     if (threadIdx.x < 16)
         h[threadIdx.x] = 0;
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long r = 0, r2 = 0, mx = 0, mn = ~0ull, span = 0;
-    if (i < n) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * 256) {
         const int k0 = rp[i], k1 = rp[i + 1];
-        r = (unsigned long long)(k1 - k0);
-        r2 = r * r;
-        mx = r;
-        mn = r;
+        const unsigned long long ri = (unsigned long long)(k1 - k0);
+        r += ri;
+        r2 += ri * ri;
+        mx = ri > mx ? ri : mx;
+        mn = ri < mn ? ri : mn;
         if (k1 > k0)
-            span = (unsigned long long)(col[k1 - 1] - col[k0]);
-        atomicAdd(&h[hist_bin((long long)r)], 1ull);
+            span += (unsigned long long)(col[k1 - 1] - col[k0]);
+        atomicAdd(&h[hist_bin((long long)ri)], 1ull);
     }
     r = ck::wave_sum(r);
     r2 = ck::wave_sum(r2);
     span = ck::wave_sum(span);
     mx = wave_max_u64(mx);
     mn = wave_min_u64(mn);
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd(&acc->sum_r, r);
-        atomicAdd(&acc->sum_r2, r2);
-        atomicAdd(&acc->span, span);
-        atomicMax(&acc->max_r, mx);
-        atomicMin(&acc->min_r, mn);
+        part[0][w] = r;
+        part[1][w] = r2;
+        part[2][w] = span;
+        part[3][w] = mx;
+        part[4][w] = mn;
     }
     __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long t[5] = {0, 0, 0, 0, ~0ull};
+        for (int v = 0; v < 4; ++v) {
+            t[0] += part[0][v];
+            t[1] += part[1][v];
+            t[2] += part[2][v];
+            t[3] = part[3][v] > t[3] ? part[3][v] : t[3];
+            t[4] = part[4][v] < t[4] ? part[4][v] : t[4];
+        }
+        atomicAdd(&acc->sum_r, t[0]);
+        atomicAdd(&acc->sum_r2, t[1]);
+        atomicAdd(&acc->span, t[2]);
+        atomicMax(&acc->max_r, t[3]);
+        atomicMin(&acc->min_r, t[4]);
+    }
     if (threadIdx.x < 16 && h[threadIdx.x])
         atomicAdd(&acc->hist[threadIdx.x], h[threadIdx.x]);
 }
@@ -135,6 +156,9 @@ __global__ __launch_bounds__(256) void feat_nnz(int64_t n, const int *__restrict
     const int64_t i = (int64_t)blockIdx.x * (256 / L) + threadIdx.x / L;
     unsigned long long dcount = 0, asym = 0, cl = 0;
     Run mine{0, 0, 0, 0, 0, 0};
+    // once any block has found an unmatched entry the answer is fixed, so
+    // later blocks skip the transposed-entry searches
+    const bool search = SYM && __builtin_nontemporal_load(&acc->asym) == 0;
     if (i < n) {
         const int k0 = rp[i], k1 = rp[i + 1];
         const int r = k1 - k0;
@@ -154,10 +178,14 @@ __global__ __launch_bounds__(256) void feat_nnz(int64_t n, const int *__restrict
                 mine.best = max(mine.best, mine.suf);
                 mine.last = c;
             }
-            diag_flag[(int64_t)c - i + (n - 1)] = 1;
+            // test before setting: most entries land on an already-set diagonal,
+            // and a read costs far less than a partial-line byte write
+            unsigned char *fl = &diag_flag[(int64_t)c - i + (n - 1)];
+            if (*fl == 0)
+                *fl = 1;
             if (c == i)
                 dcount += 1;
-            if (SYM) {
+            if (search && asym == 0) {
                 // transposed entry (c, i) must be stored with the same value
                 int lo = rp[c], hi = rp[c + 1];
                 while (lo < hi) {
@@ -324,8 +352,8 @@ ck_status launch_features(const ck_matrix &M, void *scratch, hipStream_t s) {
         hipLaunchKernelGGL((fill_u8), dim3(g), dim3(256), 0, s, nd, flags);
     }
     if (M.n > 0) {
-        hipLaunchKernelGGL(feat_rows, dim3(ceil_div(M.n, 256)), dim3(256), 0, s, M.n, M.rp, M.col,
-                           acc);
+        hipLaunchKernelGGL(feat_rows, dim3(std::min<int64_t>(ceil_div(M.n, 256), 2048)), dim3(256),
+                           0, s, M.n, M.rp, M.col, acc);
         const int64_t G = ceil_div(M.n, 256 / 8);
         if (M.n == M.ncols)
             hipLaunchKernelGGL((feat_nnz<true>), dim3(G), dim3(256), 0, s, M.n, M.rp, M.col,

@@ -2,24 +2,26 @@
 //
 // One Arnoldi step j after the SpMV w = A v_j (written straight into basis
 // column j+1) is classical Gram-Schmidt applied twice, in three fused passes
-// over the basis, each followed by a one-block finish kernel:
-//   pass 1: partials of V_j^T w                       -> finish: h1
-//   pass 2: w -= V_j h1, and in the same sweep partials of V_j^T w -> h2
-//   pass 3: w -= V_j h2, and partials of ||w||^2     -> finish: column j of
-//           the Hessenberg matrix (h1 + h2, ||w||), previous Givens rotations,
-//           rotation j, residual estimate |g_{j+1}|, cycle stop decision
-//   scale : v_{j+1} = w / h_{j+1,j}
-// Each pass streams the j+1 basis columns once; per-column sums are reduced in
-// a fixed order (wave butterfly, 4 waves, then block order), so results are
-// deterministic.  The least-squares solve and the solution update close the
+// over the basis:
+//   pass 1: partials of V_j^T w                        -> finish: h1
+//   pass 2: w' = w - V_j h1, and in the same sweep partials of V_j^T w' (h2)
+//           and of ||w'||^2                            -> finish: h2, ||w'||^2
+//   givens: h_{j+1,j} = sqrt(||w'||^2 - ||h2||^2) (Pythagoras: w' - V_j h2 is
+//           w' minus its projection on the orthonormal V_j), column j of the
+//           Hessenberg matrix (h1 + h2), previous Givens rotations, rotation
+//           j, residual estimate |g_{j+1}|, cycle stop decision
+//   pass 3: v_{j+1} = (w' - V_j h2) / h_{j+1,j}
+// After the first projection h2 is of rounding size relative to w', so the
+// subtraction loses nothing that matters, and the norm needs no third
+// reduction.  Each pass streams the j+1 basis columns once; per-column sums
+// are reduced in a fixed order (wave butterfly, 4 waves, then block order),
+// so results are deterministic.  The least-squares solve and the solution update close the
 // cycle on the device; nothing returns to the host inside a cycle.
 #include "solvers.hpp"
 
 using ck::GmDev;
 
 namespace {
-
-constexpr int kGmMaxBlocks = 1024;
 
 // partials[c*G + b] = block b's sum of acc[c]  (c < ncols)
 template <typename T, int NC>
@@ -74,7 +76,7 @@ __global__ __launch_bounds__(256) void gm_pass2(int64_t n, int64_t G, int ncols,
     if (st->halt)
         return;
     const int64_t b = blockIdx.x;
-    T h[NC], acc[NC];
+    T h[NC], acc[NC], nn = 0;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         h[c] = c < ncols ? st->h1[c] : T(0);
@@ -90,39 +92,37 @@ __global__ __launch_bounds__(256) void gm_pass2(int64_t n, int64_t G, int ncols,
                 wi -= h[c] * vv[c];
             }
         w[i] = wi;
+        nn += wi * wi;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             if (c < ncols)
                 acc[c] += vv[c] * wi;
     }
     block_cols<T, NC>(acc, ncols, partials, b, G);
+    __shared__ T lds[4];
+    nn = ck::block_sum(nn, lds);
+    if (threadIdx.x == 0)
+        partials[ncols * G + b] = nn;
 }
 
-// out[c] = sum_b partials[c*G + b]; wave w handles columns w, w+4, ...
+// out[c] = sum_b partials[c*G + b]; block c reduces column c in block order
 template <typename T>
-__global__ __launch_bounds__(256) void gm_finish_cols(int64_t G, int ncols,
-                                                      const T *__restrict__ partials, int which,
-                                                      GmDev<T> *st) {
+__global__ __launch_bounds__(256) void gm_finish_cols(int64_t G, const T *__restrict__ partials,
+                                                      int which, GmDev<T> *st) {
+    __shared__ T lds[4];
     if (st->halt)
         return;
-    T *out = which == 1 ? st->h1 : st->h2;
-    const int w = threadIdx.x / 64, lane = threadIdx.x & 63;
-    for (int c = w; c < ncols; c += 4) {
-        T s = 0;
-        for (int64_t b = lane; b < G; b += 64)
-            s += partials[c * G + b];
-        s = ck::wave_sum(s);
-        if (lane == 0)
-            out[c] = s;
-    }
+    const int c = blockIdx.x;
+    const T s = ck::sum_partials(partials + c * G, G, lds);
+    if (threadIdx.x == 0)
+        (which == 1 ? st->h1 : st->h2)[c] = s;
 }
 
+// v_{j+1} = (w' - V_j h2) * inv
 template <typename T, int NC>
 __global__ __launch_bounds__(256) void gm_pass3(int64_t n, int64_t G, int ncols,
                                                 const T *__restrict__ V, int64_t ldv,
-                                                T *__restrict__ w, T *__restrict__ partials,
-                                                const GmDev<T> *st) {
-    __shared__ T lds[4];
+                                                T *__restrict__ w, const GmDev<T> *st) {
     if (st->halt)
         return;
     const int64_t b = blockIdx.x;
@@ -130,35 +130,31 @@ __global__ __launch_bounds__(256) void gm_pass3(int64_t n, int64_t G, int ncols,
 #pragma unroll
     for (int c = 0; c < NC; ++c)
         h[c] = c < ncols ? st->h2[c] : T(0);
-    T s = 0;
+    const T inv = st->inv;
     for (int64_t i = b * 256 + threadIdx.x; i < n; i += G * 256) {
         T wi = w[i];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
             if (c < ncols)
                 wi -= h[c] * V[c * ldv + i];
-        w[i] = wi;
-        s += wi * wi;
+        w[i] = wi * inv;
     }
-    s = ck::block_sum(s, lds);
-    if (threadIdx.x == 0)
-        partials[b] = s;
 }
 
-// ||w||, Hessenberg column j, previous rotations, new rotation, estimate
+// h_{j+1,j}, Hessenberg column j, previous rotations, new rotation, estimate
+// (one thread; h2[j+1] holds ||w'||^2 from the pass-2 finish)
 template <typename T>
-__global__ __launch_bounds__(256) void gm_finish_givens(int64_t G, const T *__restrict__ partials,
-                                                        GmDev<T> *st) {
-    __shared__ T lds[4];
-    if (st->halt)
-        return;
-    const T nrm2 = ck::sum_partials(partials, G, lds);
-    if (threadIdx.x != 0)
+__global__ __launch_bounds__(64) void gm_finish_givens(GmDev<T> *st) {
+    if (st->halt || threadIdx.x != 0)
         return;
     const int m = st->m;
     const int j = st->j;
     T *Hj = st->H + (int64_t)j * (m + 1);
-    const T hn = sqrt(nrm2);
+    T proj = 0;
+    for (int c = 0; c <= j; ++c)
+        proj += st->h2[c] * st->h2[c];
+    const T nrm2 = st->h2[j + 1] - proj;
+    const T hn = nrm2 > T(0) ? sqrt(nrm2) : T(0);
     for (int c = 0; c <= j; ++c)
         Hj[c] = st->h1[c] + st->h2[c];
     Hj[j + 1] = hn;
@@ -196,16 +192,6 @@ __global__ __launch_bounds__(256) void gm_finish_givens(int64_t G, const T *__re
     st->cycle_stop = stop;
     st->halt = stop != ck::RUN;
     st->inv = hn > T(0) ? T(1) / hn : T(0);
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void gm_scale(int64_t n, T *__restrict__ w, const GmDev<T> *st) {
-    if (st->halt)
-        return;
-    const T inv = st->inv;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * 256)
-        w[i] *= inv;
 }
 
 // Cycle start: partials of ||r||^2 (FP64)
@@ -310,7 +296,7 @@ __global__ __launch_bounds__(256) void gm_update_x(int64_t n, double *__restrict
 namespace ck {
 
 int64_t gm_blocks(int64_t n) {
-    int64_t g = ceil_div(n, 2048);
+    int64_t g = ceil_div(n, 1024);
     if (g < 1)
         g = 1;
     return g < kGmMaxBlocks ? g : kGmMaxBlocks;
@@ -339,13 +325,13 @@ static void arnoldi_nc(int64_t n, int64_t G, int ncols, T *V, int64_t ldv, T *w,
                        GmDev<T> *st, hipStream_t s) {
     hipLaunchKernelGGL((gm_pass1<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w,
                        partials, st);
-    hipLaunchKernelGGL((gm_finish_cols<T>), dim3(1), dim3(256), 0, s, G, ncols, partials, 1, st);
+    hipLaunchKernelGGL((gm_finish_cols<T>), dim3(ncols), dim3(256), 0, s, G, partials, 1, st);
     hipLaunchKernelGGL((gm_pass2<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w,
                        partials, st);
-    hipLaunchKernelGGL((gm_finish_cols<T>), dim3(1), dim3(256), 0, s, G, ncols, partials, 2, st);
-    hipLaunchKernelGGL((gm_pass3<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w,
-                       partials, st);
-    hipLaunchKernelGGL((gm_finish_givens<T>), dim3(1), dim3(256), 0, s, G, partials, st);
+    hipLaunchKernelGGL((gm_finish_cols<T>), dim3(ncols + 1), dim3(256), 0, s, G, partials, 2,
+                       st);
+    hipLaunchKernelGGL((gm_finish_givens<T>), dim3(1), dim3(64), 0, s, st);
+    hipLaunchKernelGGL((gm_pass3<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w, st);
 }
 
 // Orthogonalisation and normalisation of w = V[:, j+1] (the SpMV output)
@@ -370,7 +356,6 @@ ck_status launch_gm_arnoldi(int64_t n, int j, T *V, int64_t ldv, T *partials, Gm
         arnoldi_nc<T, 64>(n, G, ncols, V, ldv, w, partials, st, s);
     else
         return fail(CK_E_INVALID, "restart length above %d", kMaxRestart);
-    hipLaunchKernelGGL((gm_scale<T>), dim3(gm_stream_grid(n)), dim3(256), 0, s, n, w, st);
     CK_HIP(hipGetLastError());
     return CK_OK;
 }

@@ -8,7 +8,16 @@
 namespace ck {
 
 constexpr int kMaxRestart = 64;    // largest GMRES restart length m
-constexpr int kMaxPartials = 4096; // blocks that feed one last-block reduction
+// Row-blocked kernels launch at most this many workgroups (32 per CU) and
+// loop over row groups inside each one: the dispatcher issues roughly one
+// workgroup per nanosecond, so a workgroup per short row group would make
+// the launch, not memory, the bound.  Also the most partials one reduction
+// ever finishes.
+constexpr int kMaxPartials = 8192;
+constexpr int kRowBlocks = kMaxPartials;
+// GMRES Gram-Schmidt passes: at most this many blocks, one partial per
+// block and basis column.
+constexpr int kGmMaxBlocks = 2048;
 
 // Run states shared by the solvers
 enum : int { RUN = 0, CONVERGED = 1, BREAKDOWN = 2, BUDGET = 3 };

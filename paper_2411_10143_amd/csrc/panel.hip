@@ -243,9 +243,10 @@ ck_status launch_to_panel(const ck_matrix &M, int P, int64_t W, int *cnt, int *t
 template <int L, typename T>
 static void go_panel(const ck_matrix &M, const T *pv, const T *x, T *ypart, const int *skip,
                      hipStream_t s) {
-    const int64_t groups = ceil_div(M.n, 256 / L);
-    hipLaunchKernelGGL((spmv_panel<L, T>), dim3(groups * M.panel_P), dim3(256), 0, s, (int)M.n,
-                       M.panel_P, groups, M.panel_rp, M.panel_col, pv, x, ypart, skip);
+    const int64_t groups = std::max<int64_t>(ceil_div(M.n, 256 / L), 1);
+    const int64_t Gp = std::min<int64_t>(groups, std::max(kRowBlocks / M.panel_P, 1));
+    hipLaunchKernelGGL((spmv_panel<L, T>), dim3(Gp * M.panel_P), dim3(256), 0, s, (int)M.n,
+                       M.panel_P, Gp, M.panel_rp, M.panel_col, pv, x, ypart, skip);
 }
 
 template <typename T>
@@ -267,7 +268,7 @@ ck_status launch_panel_spmv(const ck_matrix &M, const SpmvArgs<T> &a, T *ypart, 
     }
     const bool beta = a.beta != T(0);
     const bool dot = a.cg != nullptr;
-    const int64_t G = dot ? G_dot : ceil_div(M.n, 256);
+    const int64_t G = dot ? G_dot : std::min<int64_t>(ceil_div(M.n, 256), kRowBlocks);
     const dim3 grid(xcd_grid(G));
     if (dot)
         hipLaunchKernelGGL((panel_combine<T, false, true>), grid, dim3(256), 0, s, M.n, M.panel_P,

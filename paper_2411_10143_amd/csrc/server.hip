@@ -152,8 +152,10 @@ void complete(ck_server &S, Request *r, int status, int iters, double relres, in
 // prediction cache.  Called by the scheduler thread only.
 ck_status ensure_resident(ck_server &S, MatEntry &e, int64_t extra) {
     e.last_use = ++S.use_clock;
-    if (e.h)
+    if (e.h) {
+        S.st.prediction_cache_hits += 1;   // resident, and predicted when first made so
         return CK_OK;
+    }
     const int64_t need = 16 * e.nnz + 4 * (e.n + 1) + extra;
     // evict least-recently-used idle matrices until it fits
     while (S.bytes_in_use + need > S.o.budget_bytes) {

@@ -268,7 +268,7 @@ ck_status norm_host(SolveCtx &c, const double *v, double *partials, double *dout
 struct Fp64Scratch {
     double *partials = nullptr, *dout = nullptr;
     ck_status init(Workspace &ws, hipStream_t) {
-        CK_TRY(ws.get(&partials, 1024));
+        CK_TRY(ws.get(&partials, kMaxPartials));
         CK_TRY(ws.get(&dout, 4));
         return CK_OK;
     }
@@ -474,7 +474,7 @@ ck_status gmres_run(SolveCtx &c, const double *b, double *x) {
     GmDev<T> *st;
     Fp64Scratch f;
     CK_TRY(ws.get(&V, ldv * (m + 1)));
-    CK_TRY(ws.get(&partials, (int64_t)(kMaxRestart + 1) * 1024));
+    CK_TRY(ws.get(&partials, (int64_t)(kMaxRestart + 1) * kGmMaxBlocks));
     CK_TRY(ws.get(&r64, M.n));
     CK_TRY(ws.get(&st, 1));
     CK_TRY(f.init(ws, c.s));

@@ -33,10 +33,10 @@ constexpr int kCooIPT = 8;     // entries per thread       (2048 per workgroup)
 constexpr int kScalarCap = 4096;  // products staged per LDS chunk (CSR-scalar)
 
 // ---------------------------------------------------------------------------
-// Row-blocked kernels process row groups g = b, b+G, b+2G, ... (G logical
-// blocks).  Without a fused dot G equals the number of groups; with the fused
-// CG dot G is capped at kMaxPartials so that the last block can finish the
-// reduction quickly.
+// Row-blocked kernels process row groups g = b, b+G, b+2G, ... with
+// G = min(groups, kRowBlocks) logical blocks: at every step the 8 XCDs each
+// cover one contiguous slice of rows, and no launch needs more workgroups
+// than the dispatcher can issue in a few microseconds.
 //
 // Fused CG step: every block adds q_i * p_i over its rows (x = p, y = q) and
 // stores its partial; the CG "sigma" finish kernel sums them in block order
@@ -510,7 +510,7 @@ static void go_vector(const ck_matrix &M, int64_t G, const SpmvArgs<T> &a, hipSt
 template <typename T, bool BETA, bool DOT>
 static ck_status dispatch_rows(const ck_matrix &M, const ck_config &c, const SpmvArgs<T> &a,
                                hipStream_t s) {
-    const int64_t G = DOT ? spmv_dot_blocks(M, c) : row_groups(M, c);
+    const int64_t G = std::min<int64_t>(std::max<int64_t>(row_groups(M, c), 1), kRowBlocks);
     if (c.format == CK_FMT_ELL) {
         hipLaunchKernelGGL((spmv_ell<T, BETA, DOT>), dim3(xcd_grid(G)), dim3(256), 0, s,
                            (int)M.n, G, (int)M.ell_K, M.ell_pitch, M.ell_col, ell_values<T>(M),

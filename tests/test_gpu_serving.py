@@ -61,7 +61,9 @@ def test_alone_equals_mix_and_tolerance(ck, orc, precision):
         else:                # worker path: same cached configuration, same kernels
             d = (W.x[t] - alone[t]).abs().max().item()
             assert d <= 1e-6 * alone[t].abs().max().item(), (t, d)
-    assert st["prediction_cache_misses"] == len(pool) or st["prediction_cache_misses"] <= len(pool)
+    # each matrix is predicted once; every other admission reuses the cached prediction
+    assert st["prediction_cache_misses"] <= len(pool)
+    assert st["prediction_cache_hits"] + st["prediction_cache_misses"] >= len(done)
     assert st["batched_launches"] > 0
     W.close()
 

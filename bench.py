@@ -476,6 +476,16 @@ def bench_gmres_mixed(args):
     log(f"[gmres_mixed] n={A.n} nnz={A.nnz}")
     Mx = ck.Matrix.from_csr(A, keep_fp32=True)
     b = _rhs(ck, Mx, xs)
+    # the method's configuration for this matrix, predicted once and kept (as
+    # the request loop's prediction cache does); both precisions use it
+    cfg = ck.spmv_select(ck.spmv_features(Mx.handle))
+    try:
+        ck.spmv_convert(Mx.handle, cfg)
+    except ck.CkError as e:
+        if e.status != ck.CK_E_UNSUPPORTED:
+            raise
+        cfg = ck.default_config(Mx.handle)
+    log(f"[gmres_mixed] predicted configuration {ck.CONFIG_NAMES[ck.config_id(cfg)]}")
     res = {"mixed": [], "fp64": []}
     for s in range(args.warmup + args.steps):
         for mode in res:
@@ -483,7 +493,8 @@ def bench_gmres_mixed(args):
             torch.cuda.synchronize()
             t = time.perf_counter()
             r = ck.gmres_solve(Mx.handle, b, x, tol=1e-10, restart=30, max_iter=200000,
-                               precision=ck.CK_PREC_MIXED if mode == "mixed" else ck.CK_PREC_FP64)
+                               precision=ck.CK_PREC_MIXED if mode == "mixed" else ck.CK_PREC_FP64,
+                               config=cfg)
             dt = time.perf_counter() - t
             assert r["status"] == ck.CK_OK, (mode, r)
             log(f"[gmres_mixed] {mode} {dt:.3f}s it={r['iterations']} relres={r['true_relres']:.2e}")
@@ -512,7 +523,8 @@ def bench_gmres_mixed(args):
     keep = ("iterations", "outer_steps", "true_relres", "oracle_relres", "forward_error")
     _solve_json(args, mixed_sps, "solves/s", 1e3 * (tm + t64) / args.steps,
                 f"gmres_mixed: GMRES(30), 2D convection-diffusion {args.grid}^2 upwind, "
-                "Peclet 10, tol 1e-10; mixed FP32 inner / FP64 refinement vs plain FP64",
+                "Peclet 10, tol 1e-10; mixed FP32 inner / FP64 refinement vs plain FP64; "
+                f"predicted SpMV configuration {ck.CONFIG_NAMES[ck.config_id(cfg)]}",
                 {"mixed": {**{k: rm[k] for k in keep}, "solves_per_s": round(mixed_sps, 4)},
                  "fp64": {**{k: r64[k] for k in keep}, "solves_per_s": round(fp64_sps, 4)},
                  "mixed_speedup": round(mixed_sps / fp64_sps, 3)},

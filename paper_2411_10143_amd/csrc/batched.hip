@@ -38,19 +38,27 @@ __device__ __forceinline__ T wg_sum(T v, T *lds) {
     return r;
 }
 
-// y[i] = s1 * (A x)[i] + s0 * z[i] with L lanes per row (runtime power of two).
-// Each thread carries kRowsInFlight rows at once so that their dependent
-// loads (row pointer -> column -> x) overlap: the matrix and vectors of a
-// small system sit in L2, and the product is bound by load latency, not
-// bandwidth.  Per row the lanes still sum entries k = start + lane,
-// start + lane + L, ... in order, then butterfly over the L lanes.
-constexpr int kRowsInFlight = 4;
+// A small system's matrix and vectors sit in L2, so its products and vector
+// sweeps are bound by load latency, not bandwidth.  Every loop below issues
+// its loads unconditionally (indices clamped into range) and applies the
+// bounds test only to the arithmetic and the stores; a scheduling barrier
+// after each group of loads stops the compiler from sinking a load next to
+// its use (which it does to save registers), so the group is in flight
+// together.  The summation order is the plain one.
+constexpr int kVec = 4;   // vector elements in flight per thread
 
+// rows in flight per thread in the workgroup SpMV
+template <int BS>
+constexpr int rows_in_flight() { return BS >= 1024 ? 8 : 4; }
+
+// y[i] = s1 * (A x)[i] + s0 * z[i] with L lanes per row (runtime power of
+// two).  Per row the lanes sum entries start + lane, start + lane + L, ...
+// in order, then butterfly over the L lanes.
 template <int BS, typename TV, typename TX, typename TA>
 __device__ void wg_spmv(int n, int L, const int *__restrict__ rp, const int *__restrict__ col,
                         const TV *__restrict__ val, const TX *__restrict__ x, TA s1, TA s0,
                         const TA *__restrict__ z, TA *__restrict__ y) {
-    constexpr int U = kRowsInFlight;
+    constexpr int U = rows_in_flight<BS>();
     const int lane = threadIdx.x & (L - 1);
     const int rpp = BS / L;
     for (int r0 = 0; r0 < n; r0 += U * rpp) {
@@ -59,23 +67,33 @@ __device__ void wg_spmv(int n, int L, const int *__restrict__ rp, const int *__r
         int trips = 0;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int row = r0 + u * rpp + threadIdx.x / L;
-            kb[u] = 0;
-            ke[u] = 0;
+            const int row = min(r0 + u * rpp + (int)threadIdx.x / L, n - 1);
+            kb[u] = rp[row] + lane;
+            ke[u] = r0 + u * rpp + (int)threadIdx.x / L < n ? rp[row + 1] : 0;
             acc[u] = 0;
-            if (row < n) {
-                kb[u] = rp[row] + lane;
-                ke[u] = rp[row + 1];
-            }
             trips = max(trips, (ke[u] - kb[u] + L - 1) / L);
         }
+        // trips > 0 means some row here has entries, so entry 0 exists and
+        // serves as the in-range index of finished rows
         for (int t = 0; t < trips; ++t) {
+            int cc[U];
+            TV vv[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int k = kb[u] + t * L;
-                if (k < ke[u])
-                    acc[u] += (TA)val[k] * (TA)x[col[k]];
+                const int kk = k < ke[u] ? k : 0;
+                cc[u] = col[kk];
+                vv[u] = val[kk];
             }
+            TX xv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                xv[u] = x[cc[u]];
+            __builtin_amdgcn_sched_barrier(0);   // all gathers in flight before the first use
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (kb[u] + t * L < ke[u])
+                    acc[u] += (TA)vv[u] * (TA)xv[u];
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -143,8 +161,18 @@ __global__ __launch_bounds__(BS) void batched_chunk(ck::BSlot *slots, ck::BStat 
                                             s->r64);
             __syncthreads();
             double q = 0;
-            for (int i = tid; i < n; i += BS)
-                q += s->r64[i] * s->r64[i];
+            const double *r64 = s->r64;
+            for (int i0 = tid; i0 < n; i0 += kVec * BS) {
+                double rv[kVec];
+#pragma unroll
+                for (int u = 0; u < kVec; ++u)
+                    rv[u] = r64[min(i0 + u * BS, n - 1)];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < kVec; ++u)
+                    if (i0 + u * BS < n)
+                        q += rv[u] * rv[u];
+            }
             const double beta = sqrt(wg_sum<BS>(q, lds64));
             const double rel = beta / s->bnorm;
             if (tid == 0) {
@@ -205,8 +233,20 @@ __global__ __launch_bounds__(BS) void batched_chunk(ck::BSlot *slots, ck::BStat 
             wg_spmv<BS, T, T, T>(n, L, s->rp, s->col, val, p, T(1), T(0), (const T *)nullptr, q);
             __syncthreads();
             T pq = 0;
-            for (int i = tid; i < n; i += BS)
-                pq += p[i] * q[i];
+            for (int i0 = tid; i0 < n; i0 += kVec * BS) {
+                T pv[kVec], qv[kVec];
+#pragma unroll
+                for (int u = 0; u < kVec; ++u) {
+                    const int i = min(i0 + u * BS, n - 1);
+                    pv[u] = p[i];
+                    qv[u] = q[i];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < kVec; ++u)
+                    if (i0 + u * BS < n)
+                        pq += pv[u] * qv[u];
+            }
             const T sigma = wg_sum<BS>(pq, lds);
             if (!(sigma > T(0))) {
                 phase = s->inner_iter == 0 ? ck::B_DONE : ck::B_UPDATE;
@@ -218,11 +258,27 @@ __global__ __launch_bounds__(BS) void batched_chunk(ck::BSlot *slots, ck::BStat 
             const T rho = (T)s->rho;
             const T alpha = rho / sigma;
             T rr = 0;
-            for (int i = tid; i < n; i += BS) {
-                d[i] += alpha * p[i];
-                const T ri = r[i] - alpha * q[i];
-                r[i] = ri;
-                rr += ri * ri;
+            for (int i0 = tid; i0 < n; i0 += kVec * BS) {
+                T dv[kVec], pv[kVec], rv[kVec], qv[kVec];
+#pragma unroll
+                for (int u = 0; u < kVec; ++u) {
+                    const int i = min(i0 + u * BS, n - 1);
+                    dv[u] = d[i];
+                    pv[u] = p[i];
+                    rv[u] = r[i];
+                    qv[u] = q[i];
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < kVec; ++u) {
+                    const int i = i0 + u * BS;
+                    if (i < n) {
+                        d[i] = dv[u] + alpha * pv[u];
+                        const T ri = rv[u] - alpha * qv[u];
+                        r[i] = ri;
+                        rr += ri * ri;
+                    }
+                }
             }
             const T rho_new = wg_sum<BS>(rr, lds);
             const int it = s->inner_iter + 1;
@@ -230,8 +286,20 @@ __global__ __launch_bounds__(BS) void batched_chunk(ck::BSlot *slots, ck::BStat 
                               s->iter + 1 >= s->max_iter;
             const T bcg = rho_new / rho;
             if (!stop)
-                for (int i = tid; i < n; i += BS)
-                    p[i] = r[i] + bcg * p[i];
+                for (int i0 = tid; i0 < n; i0 += kVec * BS) {
+                    T rv[kVec], pv[kVec];
+#pragma unroll
+                    for (int u = 0; u < kVec; ++u) {
+                        const int i = min(i0 + u * BS, n - 1);
+                        rv[u] = r[i];
+                        pv[u] = p[i];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int u = 0; u < kVec; ++u)
+                        if (i0 + u * BS < n)
+                            p[i0 + u * BS] = rv[u] + bcg * pv[u];
+                }
             __syncthreads();
             if (tid == 0) {
                 s->rho = (double)rho_new;
@@ -245,6 +313,7 @@ __global__ __launch_bounds__(BS) void batched_chunk(ck::BSlot *slots, ck::BStat 
         }
         if (phase == ck::B_INNER) {   // GMRES: one Arnoldi step (CGS2) + Givens
             const int j = s->j, m = s->m;
+            const int64_t ld = s->ld;
             T *V = wsp<T>(s, 0);
             T *w = V + (int64_t)(j + 1) * s->ld;
             const T *val = sizeof(T) == 4 ? (const T *)s->val32 : (const T *)s->val64;
@@ -258,10 +327,21 @@ __global__ __launch_bounds__(BS) void batched_chunk(ck::BSlot *slots, ck::BStat 
                     acc[c] = 0;
                 for (int i = tid; i < n; i += BS) {
                     const T wi = w[i];
+                    // columns in groups of 8 loads in flight
 #pragma unroll
-                    for (int c = 0; c <= ck::kBMaxM; ++c)
-                        if (c <= j)
-                            acc[c] += V[(int64_t)c * s->ld + i] * wi;
+                    for (int g = 0; g <= ck::kBMaxM; g += 8) {
+                        if (g <= j) {
+                            T vv[8];
+#pragma unroll
+                            for (int c = 0; c < 8; ++c)
+                                vv[c] = V[(int64_t)min(g + c, j) * ld + i];
+                            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                            for (int c = 0; c < 8; ++c)
+                                if (g + c <= ck::kBMaxM && g + c <= j)
+                                    acc[g + c] += vv[c] * wi;
+                        }
+                    }
                 }
 #pragma unroll
                 for (int c = 0; c <= ck::kBMaxM; ++c)
@@ -281,15 +361,33 @@ __global__ __launch_bounds__(BS) void batched_chunk(ck::BSlot *slots, ck::BStat 
                 __syncthreads();
                 for (int i = tid; i < n; i += BS) {
                     T wi = w[i];
-                    for (int c = 0; c <= j; ++c)
-                        wi -= hcol[c] * V[(int64_t)c * s->ld + i];
+                    for (int g = 0; g <= j; g += 8) {
+                        T vv[8];
+#pragma unroll
+                        for (int c = 0; c < 8; ++c)
+                            vv[c] = V[(int64_t)min(g + c, j) * ld + i];
+                        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                        for (int c = 0; c < 8; ++c)
+                            if (g + c <= j)
+                                wi -= hcol[min(g + c, j)] * vv[c];
+                    }
                     w[i] = wi;
                 }
                 __syncthreads();
             }
             T nn = 0;
-            for (int i = tid; i < n; i += BS)
-                nn += w[i] * w[i];
+            for (int i0 = tid; i0 < n; i0 += kVec * BS) {
+                T wv[kVec];
+#pragma unroll
+                for (int u = 0; u < kVec; ++u)
+                    wv[u] = w[min(i0 + u * BS, n - 1)];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < kVec; ++u)
+                    if (i0 + u * BS < n)
+                        nn += wv[u] * wv[u];
+            }
             const T hn = sqrt(wg_sum<BS>(nn, lds));
             __shared__ int stop_sh;
             __shared__ T inv_sh;

@@ -23,6 +23,14 @@ using ck::GmDev;
 
 namespace {
 
+// The passes below are written for NC >= ncols columns with no branch per
+// column: column c >= ncols reloads column ncols - 1 (an L2 hit), its
+// coefficient h[c] is 0 (so the subtraction is exact) and its accumulator is
+// never written out.  Without branches every column's load of an element is
+// in flight at once; with a branch per column each load waited for the one
+// before it.
+__device__ __forceinline__ int64_t clampc(int c, int ncols) { return c < ncols ? c : ncols - 1; }
+
 // partials[c*G + b] = block b's sum of acc[c]  (c < ncols)
 template <typename T, int NC>
 __device__ __forceinline__ void block_cols(const T (&acc)[NC], int ncols, T *partials, int64_t b,
@@ -60,10 +68,14 @@ __global__ __launch_bounds__(256) void gm_pass1(int64_t n, int64_t G, int ncols,
         acc[c] = 0;
     for (int64_t i = b * 256 + threadIdx.x; i < n; i += G * 256) {
         const T wi = w[i];
+        T vv[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (c < ncols)
-                acc[c] += V[c * ldv + i] * wi;
+            vv[c] = V[clampc(c, ncols) * ldv + i];
+        __builtin_amdgcn_sched_barrier(0);   // every load issued before the first use
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            acc[c] += vv[c] * wi;
     }
     block_cols<T, NC>(acc, ncols, partials, b, G);
 }
@@ -87,16 +99,16 @@ __global__ __launch_bounds__(256) void gm_pass2(int64_t n, int64_t G, int ncols,
         T wi = w[i];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (c < ncols) {
-                vv[c] = V[c * ldv + i];
-                wi -= h[c] * vv[c];
-            }
+            vv[c] = V[clampc(c, ncols) * ldv + i];
+        __builtin_amdgcn_sched_barrier(0);   // every load issued before the first use
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            wi -= h[c] * vv[c];
         w[i] = wi;
         nn += wi * wi;
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (c < ncols)
-                acc[c] += vv[c] * wi;
+            acc[c] += vv[c] * wi;
     }
     block_cols<T, NC>(acc, ncols, partials, b, G);
     __shared__ T lds[4];
@@ -133,37 +145,58 @@ __global__ __launch_bounds__(256) void gm_pass3(int64_t n, int64_t G, int ncols,
     const T inv = st->inv;
     for (int64_t i = b * 256 + threadIdx.x; i < n; i += G * 256) {
         T wi = w[i];
+        T vv[NC];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
-            if (c < ncols)
-                wi -= h[c] * V[c * ldv + i];
+            vv[c] = V[clampc(c, ncols) * ldv + i];
+        __builtin_amdgcn_sched_barrier(0);   // every load issued before the first use
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            wi -= h[c] * vv[c];
         w[i] = wi * inv;
     }
 }
 
-// h_{j+1,j}, Hessenberg column j, previous rotations, new rotation, estimate
-// (one thread; h2[j+1] holds ||w'||^2 from the pass-2 finish)
+// h_{j+1,j}, Hessenberg column j, previous rotations, new rotation, estimate.
+// h2[j+1] holds ||w'||^2 from the pass-2 finish.  The values the rotation
+// chain needs are first loaded in parallel into LDS; one thread then runs the
+// chain without a global-memory round trip per rotation.
 template <typename T>
 __global__ __launch_bounds__(64) void gm_finish_givens(GmDev<T> *st) {
-    if (st->halt || threadIdx.x != 0)
+    __shared__ T col[ck::kMaxRestart], h2[ck::kMaxRestart], cs[ck::kMaxRestart],
+        sn[ck::kMaxRestart];
+    if (st->halt)
         return;
     const int m = st->m;
     const int j = st->j;
+    for (int c = threadIdx.x; c <= j; c += 64) {
+        const T b = st->h2[c];
+        col[c] = st->h1[c] + b;
+        h2[c] = b;
+        if (c < j) {
+            cs[c] = st->cs[c];
+            sn[c] = st->sn[c];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x != 0)
+        return;
     T *Hj = st->H + (int64_t)j * (m + 1);
     T proj = 0;
     for (int c = 0; c <= j; ++c)
-        proj += st->h2[c] * st->h2[c];
+        proj += h2[c] * h2[c];
     const T nrm2 = st->h2[j + 1] - proj;
     const T hn = nrm2 > T(0) ? sqrt(nrm2) : T(0);
-    for (int c = 0; c <= j; ++c)
-        Hj[c] = st->h1[c] + st->h2[c];
-    Hj[j + 1] = hn;
+    // previous rotations applied to (h_0j, ..., h_jj, hn); `a` carries entry i
+    T a = col[0];
     for (int i = 0; i < j; ++i) {
-        const T a = Hj[i], c2 = Hj[i + 1];
-        Hj[i] = st->cs[i] * a + st->sn[i] * c2;
-        Hj[i + 1] = -st->sn[i] * a + st->cs[i] * c2;
+        const T c2 = col[i + 1];
+        Hj[i] = cs[i] * a + sn[i] * c2;
+        a = -sn[i] * a + cs[i] * c2;
     }
-    const T a = Hj[j], c2 = Hj[j + 1];
+    const T c2 = hn;
+    Hj[j] = a;
+    Hj[j + 1] = c2;
     const T d = sqrt(a * a + c2 * c2);
     if (d == T(0)) {
         st->final_state = ck::BREAKDOWN;
@@ -171,21 +204,27 @@ __global__ __launch_bounds__(64) void gm_finish_givens(GmDev<T> *st) {
         st->halt = 1;
         return;
     }
-    st->cs[j] = a / d;
-    st->sn[j] = c2 / d;
+    const T cj = a / d, sj = c2 / d;
+    const T gj = st->g[j];
+    const double bnorm = st->bnorm, tol = st->tol;
+    const int iter = st->iter + 1, max_iter = st->max_iter;
+    st->cs[j] = cj;
+    st->sn[j] = sj;
     Hj[j] = d;
     Hj[j + 1] = 0;
-    st->g[j + 1] = -st->sn[j] * st->g[j];
-    st->g[j] = st->cs[j] * st->g[j];
+    const T gj1 = -sj * gj;
+    st->g[j + 1] = gj1;
+    st->g[j] = cj * gj;
     st->j = j + 1;
-    st->iter += 1;
-    st->relres = fabs((double)st->g[j + 1]) / st->bnorm;
+    st->iter = iter;
+    const double relres = fabs((double)gj1) / bnorm;
+    st->relres = relres;
     int stop = ck::RUN;
-    if (st->relres <= st->tol)
+    if (relres <= tol)
         stop = ck::CONVERGED;
     else if (hn == T(0))
         stop = ck::BREAKDOWN;
-    else if (st->iter >= st->max_iter)
+    else if (iter >= max_iter)
         stop = ck::BUDGET;
     else if (j + 1 == m)
         stop = ck::FULL;
@@ -350,8 +389,12 @@ ck_status launch_gm_arnoldi(int64_t n, int j, T *V, int64_t ldv, T *partials, Gm
         arnoldi_nc<T, 24>(n, G, ncols, V, ldv, w, partials, st, s);
     else if (ncols <= 32)
         arnoldi_nc<T, 32>(n, G, ncols, V, ldv, w, partials, st, s);
+    else if (ncols <= 40)
+        arnoldi_nc<T, 40>(n, G, ncols, V, ldv, w, partials, st, s);
     else if (ncols <= 48)
         arnoldi_nc<T, 48>(n, G, ncols, V, ldv, w, partials, st, s);
+    else if (ncols <= 56)
+        arnoldi_nc<T, 56>(n, G, ncols, V, ldv, w, partials, st, s);
     else if (ncols <= 64)
         arnoldi_nc<T, 64>(n, G, ncols, V, ldv, w, partials, st, s);
     else

@@ -72,12 +72,24 @@ constexpr int FULL = 4;         // cycle_stop value: m steps done
 // device-scope fence (an L2 write-back on this chip) is issued per block.
 
 // Fixed-order sum of n partials by the 256 threads of one block (valid in
-// thread 0 only).
+// thread 0 only).  Thread t adds p[t], p[t + 256], ... in order; the loads of
+// eight consecutive terms are issued together (index clamped, term masked).
 template <typename T>
 __device__ __forceinline__ T sum_partials(const T *p, int64_t n, T *lds4) {
+    constexpr int U = 8;
     T s = 0;
-    for (int64_t i = threadIdx.x; i < n; i += 256)
-        s += __builtin_nontemporal_load(&p[i]);
+    for (int64_t i0 = threadIdx.x; i0 < n; i0 += U * 256) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * 256;
+            v[u] = __builtin_nontemporal_load(&p[i < n ? i : n - 1]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (i0 + u * 256 < n)
+                s += v[u];
+    }
     return block_sum(s, lds4);
 }
 

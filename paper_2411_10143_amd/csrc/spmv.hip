@@ -172,12 +172,30 @@ __global__ __launch_bounds__(256) void spmv_ell(int n, int64_t G, int K, int64_t
     for (int64_t g = b; g < groups; g += G) {
         const int64_t row = g * 256 + threadIdx.x;
         if (row < n) {
+            // four slots per step: their column and value loads, then their x
+            // gathers, are each in flight together.  Padding (column -1) only
+            // trails a row, so masking it equals stopping at the first one;
+            // x[0] stands in for a masked gather (K > 0 implies ncols > 0).
+            constexpr int S = 4;
             T sum = 0;
-            for (int s = 0; s < K; ++s) {
-                const int c = ld_stream(&ecol[s * pitch + row]);
-                if (c < 0)
+            for (int s0 = 0; s0 < K; s0 += S) {
+                int c[S];
+                T v[S], xv[S];
+#pragma unroll
+                for (int u = 0; u < S; ++u) {
+                    const int64_t s = min(s0 + u, K - 1);
+                    c[u] = s0 + u < K ? ld_stream(&ecol[s * pitch + row]) : -1;
+                    v[u] = ld_stream(&evl[s * pitch + row]);
+                }
+#pragma unroll
+                for (int u = 0; u < S; ++u)
+                    xv[u] = x[c[u] >= 0 ? c[u] : 0];
+#pragma unroll
+                for (int u = 0; u < S; ++u)
+                    if (c[u] >= 0)
+                        sum += v[u] * xv[u];
+                if (c[S - 1] < 0)
                     break;
-                sum += ld_stream(&evl[s * pitch + row]) * x[c];
             }
             T out = alpha * sum;
             if (BETA)

@@ -30,7 +30,7 @@ ck_status fail(ck_status st, const char *fmt, ...) {
 ck_status launch_validate(int64_t n, int64_t ncols, int64_t nnz, const int *rp, const int *col,
                           unsigned *bad, hipStream_t s);
 int64_t features_scratch_bytes(int64_t n, int64_t ncols);
-ck_status launch_features(const ck_matrix &M, void *scratch, hipStream_t s);
+ck_status launch_features(const ck_matrix &M, void *scratch, bool symmetry, hipStream_t s);
 void features_from_acc(const void *acc_host, const ck_matrix &M, int64_t *out28);
 int64_t features_acc_offset(int64_t n, int64_t ncols);
 size_t features_acc_size();
@@ -73,12 +73,15 @@ static void release(ck_matrix *M) {
 }
 
 // Exact integer features (GPU) plus host-derived floating-point features.
-ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s) {
+// `symmetry` = false skips the transposed-entry search (is_symmetric is then
+// reported as 0): the cascade does not use it, so a solve's own feature pass
+// leaves it out.
+ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s, bool symmetry) {
     std::memset(&F, 0, sizeof F);
     const int64_t bytes = features_scratch_bytes(M.n, M.ncols);
     void *scratch = nullptr;
     CK_HIP(hipMallocAsync(&scratch, (size_t)bytes, s));
-    ck_status st = launch_features(M, scratch, s);
+    ck_status st = launch_features(M, scratch, symmetry, s);
     char acc[512];
     if (st == CK_OK) {
         const hipError_t e = hipMemcpyAsync(acc, (char *)scratch + features_acc_offset(M.n, M.ncols),
@@ -94,6 +97,8 @@ ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s) {
                     hipGetErrorString(es != hipSuccess ? es : ef));
     int64_t ints[28];
     features_from_acc(acc, M, ints);
+    if (!symmetry)
+        ints[27] = 0;
     std::memcpy(&F, ints, sizeof ints);
     derive_features(F);
     M.max_row = F.max_r;
@@ -297,7 +302,7 @@ void spmv_destroy(ck_handle h) { release(h); }
 ck_status spmv_features(ck_handle h, ck_features *out, hipStream_t s) {
     if (!h || !out)
         return fail(CK_E_INVALID, "NULL argument");
-    return compute_features(*h, *out, s);
+    return compute_features(*h, *out, s, true);
 }
 
 ck_status ck_select_stages(const ck_features *f, const char *model_path, int32_t stage[3]) {

@@ -39,6 +39,15 @@ struct BStat {
     double relres;
 };
 
+// Single-workgroup FP64 CG (one launch per solve) for at most kWgCgMaxN rows.
+constexpr int kWgCgMaxN = 4096;
+struct WgCgOut {
+    int status, iter, restarts, pad;
+    double relres;   // true relative residual at exit
+};
+ck_status launch_cg_wg(int n, const int *rp, const int *col, const double *val, const double *b,
+                       double *x, double tol, int max_iter, WgCgOut *out, hipStream_t s);
+
 // elements (of the inner type) of a slot's `work`
 int64_t bslot_work_elems(int kind, int64_t n, int m);
 // wide = 1024 threads per slot (single-system path), else 256

@@ -342,7 +342,7 @@ int64_t features_scratch_bytes(int64_t n, int64_t ncols) {
     return ((n + ncols + 255) / 256) * 256 + 512;
 }
 
-ck_status launch_features(const ck_matrix &M, void *scratch, hipStream_t s) {
+ck_status launch_features(const ck_matrix &M, void *scratch, bool symmetry, hipStream_t s) {
     const int64_t nd = M.n + M.ncols - 1;
     unsigned char *flags = (unsigned char *)scratch;
     FeatAcc *acc = (FeatAcc *)((char *)scratch + ((M.n + M.ncols + 255) / 256) * 256);
@@ -355,7 +355,7 @@ ck_status launch_features(const ck_matrix &M, void *scratch, hipStream_t s) {
         hipLaunchKernelGGL(feat_rows, dim3(std::min<int64_t>(ceil_div(M.n, 256), 2048)), dim3(256),
                            0, s, M.n, M.rp, M.col, acc);
         const int64_t G = ceil_div(M.n, 256 / 8);
-        if (M.n == M.ncols)
+        if (symmetry && M.n == M.ncols)
             hipLaunchKernelGGL((feat_nnz<true>), dim3(G), dim3(256), 0, s, M.n, M.rp, M.col,
                                M.val, flags, acc);
         else

@@ -30,7 +30,7 @@
 #include "solvers.hpp"
 
 namespace ck {
-ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s);
+ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s, bool symmetry);
 ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s);
 }  // namespace ck
 
@@ -179,7 +179,7 @@ ck_status ensure_resident(ck_server &S, MatEntry &e, int64_t extra) {
     if (!e.predicted) {
         S.st.prediction_cache_misses += 1;
         ck_features F;
-        CK_TRY(compute_features(*e.h, F, S.stream));
+        CK_TRY(compute_features(*e.h, F, S.stream, true));
         e.symmetric = F.is_symmetric != 0;
         if (spmv_select(&F, nullptr, &e.cfg) != CK_OK)
             e.cfg = default_config(e.n, e.nnz);

@@ -1,0 +1,227 @@
+// Single-workgroup FP64 conjugate gradient for small systems (n <= 4096).
+//
+// A system this small cannot fill the GPU, and a launch per CG step would
+// make launch latency the bound.  One 1024-thread workgroup runs the whole
+// solve in one launch: thread t owns rows t, t + 1024, ... (R <= 4 of them);
+// x, r, p and q of its rows live in registers, p also in LDS (the product
+// gathers it from there), and only the matrix (L2-resident after the first
+// step) and, at the rare residual steps, b are read from memory.  The product
+// sums each row with one lane in ascending entry order; the loads of all R
+// rows' next entries are issued together.  Dot products reduce in a fixed
+// order (wave butterfly, then the 16 wave sums in order), so the result is
+// deterministic.  (Eight rows per thread would spill registers.)
+//
+// The iteration is the same Hestenes-Stiefel CG as the multi-kernel path:
+// r = b - A x, p = r; then q = A p, alpha = rho / p.q, x += alpha p,
+// r -= alpha q, stop when ||r|| / ||b|| <= tol; at a stop the true residual
+// b - A x is recomputed and CG restarts from the current x (at most three
+// times) if it is above tol.
+#include "batched.hpp"
+
+namespace {
+
+constexpr int kWgThreads = 1024;
+constexpr int kWgWaves = kWgThreads / 64;
+
+// sum over the workgroup, returned to every thread; `red` holds kWgWaves
+// doubles; two barriers so that the buffer may be reused right after
+__device__ __forceinline__ double wg_sum_1024(double v, double *red) {
+    v = ck::wave_sum(v);
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0;
+#pragma unroll
+    for (int w = 0; w < kWgWaves; ++w)
+        s += red[w];
+    __syncthreads();
+    return s;
+}
+
+// q[u] = (A v)[row u of this thread], v in LDS
+template <int R>
+__device__ __forceinline__ void wg_matvec(const int (&kb)[R], const int (&ke)[R], int trips,
+                                          const int *__restrict__ col,
+                                          const double *__restrict__ val, const double *v,
+                                          double (&q)[R]) {
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+        q[u] = 0;
+    for (int t = 0; t < trips; ++t) {
+        int cc[R];
+        double vv[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int k = kb[u] + t;
+            const int kk = k < ke[u] ? k : 0;   // entry 0 exists when trips > 0
+            cc[u] = col[kk];
+            vv[u] = val[kk];
+        }
+        __builtin_amdgcn_sched_barrier(0);   // every row's loads in flight together
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+            if (kb[u] + t < ke[u])
+                q[u] += vv[u] * v[cc[u]];
+    }
+}
+
+}  // namespace
+
+template <int R>
+__global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict__ rp,
+                                                    const int *__restrict__ col,
+                                                    const double *__restrict__ val,
+                                                    const double *__restrict__ b,
+                                                    double *__restrict__ x, double tol,
+                                                    int max_iter, ck::WgCgOut *out) {
+    __shared__ double v[kWgThreads * R];   // p (or x while forming the residual)
+    __shared__ double red[kWgWaves];
+    const int t = threadIdx.x;
+    int kb[R], ke[R];
+    double xr[R], rr[R], pr[R], q[R];
+    int trips = 0;
+    double bb = 0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const int i = t + u * kWgThreads;
+        const bool in = i < n;
+        kb[u] = in ? rp[i] : 0;
+        ke[u] = in ? rp[i + 1] : 0;
+        const double bi = in ? b[i] : 0.0;
+        xr[u] = in ? x[i] : 0.0;
+        trips = max(trips, ke[u] - kb[u]);
+        bb += bi * bi;
+    }
+    const double bnorm = sqrt(wg_sum_1024(bb, red));
+    int status = ck::BUDGET, iters = 0, restarts = 0;
+    double relres = 0;
+    if (bnorm == 0.0) {
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+            xr[u] = 0;
+        status = ck::CONVERGED;
+    } else {
+        for (restarts = 0; restarts <= 3; ++restarts) {
+            // r = b - A x
+#pragma unroll
+            for (int u = 0; u < R; ++u)
+                if (t + u * kWgThreads < n)
+                    v[t + u * kWgThreads] = xr[u];
+            __syncthreads();
+            wg_matvec<R>(kb, ke, trips, col, val, v, q);
+            double rho = 0;
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                const int i = t + u * kWgThreads;
+                rr[u] = (i < n ? b[i] : 0.0) - q[u];
+                pr[u] = rr[u];
+                rho += rr[u] * rr[u];
+            }
+            rho = wg_sum_1024(rho, red);   // its barriers also retire the reads of v
+            relres = sqrt(rho) / bnorm;
+            if (relres <= tol) {
+                status = ck::CONVERGED;
+                break;
+            }
+            int state = ck::RUN;
+            while (state == ck::RUN) {
+                if (iters >= max_iter) {
+                    state = ck::BUDGET;
+                    break;
+                }
+#pragma unroll
+                for (int u = 0; u < R; ++u)
+                    if (t + u * kWgThreads < n)
+                        v[t + u * kWgThreads] = pr[u];
+                __syncthreads();
+                wg_matvec<R>(kb, ke, trips, col, val, v, q);
+                double pq = 0;
+#pragma unroll
+                for (int u = 0; u < R; ++u)
+                    pq += pr[u] * q[u];
+                const double sigma = wg_sum_1024(pq, red);
+                if (!(sigma > 0.0)) {
+                    state = ck::BREAKDOWN;
+                    break;
+                }
+                const double alpha = rho / sigma;
+                double rn = 0;
+#pragma unroll
+                for (int u = 0; u < R; ++u) {
+                    xr[u] += alpha * pr[u];
+                    rr[u] -= alpha * q[u];
+                    rn += rr[u] * rr[u];
+                }
+                const double rho_new = wg_sum_1024(rn, red);
+                ++iters;
+                if (sqrt(rho_new) / bnorm <= tol) {
+                    state = ck::CONVERGED;
+                    break;
+                }
+                const double beta = rho_new / rho;
+#pragma unroll
+                for (int u = 0; u < R; ++u)
+                    pr[u] = rr[u] + beta * pr[u];
+                rho = rho_new;
+            }
+            if (state == ck::BREAKDOWN) {
+                status = ck::BREAKDOWN;
+                break;
+            }
+            // true residual of the current x
+#pragma unroll
+            for (int u = 0; u < R; ++u)
+                if (t + u * kWgThreads < n)
+                    v[t + u * kWgThreads] = xr[u];
+            __syncthreads();
+            wg_matvec<R>(kb, ke, trips, col, val, v, q);
+            double tr = 0;
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                const int i = t + u * kWgThreads;
+                const double d = (i < n ? b[i] : 0.0) - q[u];
+                tr += d * d;
+            }
+            relres = sqrt(wg_sum_1024(tr, red)) / bnorm;
+            if (relres <= tol) {
+                status = ck::CONVERGED;
+                break;
+            }
+            if (state == ck::BUDGET) {
+                status = ck::BUDGET;
+                break;
+            }
+        }
+        if (restarts > 3)
+            restarts = 3;
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+        if (t + u * kWgThreads < n)
+            x[t + u * kWgThreads] = xr[u];
+    if (t == 0) {
+        out->status = status;
+        out->iter = iters;
+        out->restarts = restarts;
+        out->relres = relres;
+    }
+}
+
+namespace ck {
+
+ck_status launch_cg_wg(int n, const int *rp, const int *col, const double *val, const double *b,
+                       double *x, double tol, int max_iter, WgCgOut *out, hipStream_t s) {
+    if (n < 1 || n > kWgCgMaxN)
+        return fail(CK_E_INVALID, "single-workgroup CG takes 1..%d rows, got %d", kWgCgMaxN, n);
+    const dim3 grid(1), block(kWgThreads);
+    if (n <= kWgThreads)
+        hipLaunchKernelGGL((cg_wg<1>), grid, block, 0, s, n, rp, col, val, b, x, tol, max_iter, out);
+    else if (n <= 2 * kWgThreads)
+        hipLaunchKernelGGL((cg_wg<2>), grid, block, 0, s, n, rp, col, val, b, x, tol, max_iter, out);
+    else
+        hipLaunchKernelGGL((cg_wg<4>), grid, block, 0, s, n, rp, col, val, b, x, tol, max_iter, out);
+    CK_HIP(hipGetLastError());
+    return CK_OK;
+}
+
+}  // namespace ck

@@ -22,7 +22,7 @@
 
 namespace ck {
 
-ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s);
+ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s, bool symmetry);
 ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s);
 
 namespace {
@@ -155,7 +155,7 @@ class AsyncExec {
         (void)hipSetDevice(M_.device);
         auto t0 = Clock::now();
         ck_features F;
-        if (compute_features(M_, F, side_) != CK_OK || cancel_.load()) {
+        if (compute_features(M_, F, side_, false) != CK_OK || cancel_.load()) {
             skip_rest(0);
             return;
         }
@@ -556,6 +556,27 @@ enum class Solver { CG, GMRES };
 // more than the step itself.
 constexpr int64_t kSmallN = 16384;
 
+// FP64 CG of a system of at most kWgCgMaxN rows in one single-workgroup launch
+ck_status wg_cg_solve(SolveCtx &c, const double *b, double *x) {
+    Workspace ws(c.s);
+    WgCgOut *out;
+    CK_TRY(ws.get(&out, 1));
+    const int max_iter = c.o.max_iter > 0 ? c.o.max_iter : 100000;
+    CK_TRY(launch_cg_wg((int)c.M.n, c.M.rp, c.M.col, c.M.val, b, x, c.o.tol, max_iter, out, c.s));
+    WgCgOut h{};
+    CK_HIP(hipMemcpyAsync(&h, out, sizeof h, hipMemcpyDeviceToHost, c.s));
+    CK_HIP(hipStreamSynchronize(c.s));
+    c.res.iterations = h.iter;
+    c.res.outer_steps = h.restarts + 1;
+    c.res.true_relres = h.relres;
+    if (h.status == CONVERGED)
+        return CK_OK;
+    if (h.status == BREAKDOWN)
+        return fail(CK_E_BREAKDOWN, "breakdown (p.Ap <= 0)");
+    return fail(CK_E_NOT_CONVERGED, "iteration budget spent at relative residual %.3e",
+                h.relres);
+}
+
 ck_status small_solve(SolveCtx &c, const double *b, double *x, bool cg, int m) {
     ck_matrix &M = c.M;
     const bool fp32 = c.o.precision == CK_PREC_MIXED;
@@ -640,6 +661,16 @@ ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *
         return CK_OK;
     }
     const int m = opts->restart > 0 ? opts->restart : 30;
+    if (M.n <= kWgCgMaxN && which == Solver::CG && opts->precision == CK_PREC_FP64 &&
+        !opts->async && !opts->use_config) {
+        // the whole solve in one single-workgroup launch; its product takes
+        // one lane per row
+        const ck_status st = wg_cg_solve(c, b, x);
+        res->final_config = ck_config{CK_FMT_CSR, CK_ALG_VECTOR, 1, 0};
+        res->status = st;
+        res->t_total_us = us_since(t0);
+        return st;
+    }
     const bool vector_cfg = c.cfg.format == CK_FMT_CSR && c.cfg.algorithm == CK_ALG_VECTOR;
     if (M.n <= kSmallN && !opts->async && vector_cfg && (which == Solver::CG || m <= kBMaxM)) {
         const ck_status st = small_solve(c, b, x, which == Solver::CG, m);

@@ -56,23 +56,38 @@ class ServingWorkload:
             h.close()
         torch.cuda.synchronize()
 
-    def run(self, arrivals_s=None, which=None, timeout_s=1800.0):
+    def run(self, arrivals_s=None, which=None, timeout_s=1800.0, progress=None, every_s=30.0):
         """Submit requests (all of `which`, default every one) at the given
-        arrival offsets (seconds, None = all at once); returns completions."""
+        arrival offsets (seconds, None = all at once); returns completions.
+        `progress(text)` is called about every `every_s` seconds."""
         idx = list(range(len(self.mid))) if which is None else list(which)
         arr = np.zeros(len(idx)) if arrivals_s is None else np.asarray(arrivals_s)
         done = []
         t0 = time.perf_counter()
+        last = [t0]
+
+        def tick(submitted):
+            now = time.perf_counter()
+            if progress and now - last[0] >= every_s:
+                last[0] = now
+                progress(f"{now - t0:.0f}s: {submitted} submitted, {len(done)} collected")
+
         for k, t in enumerate(idx):
             while True:
                 wait = t0 + arr[k] - time.perf_counter()
                 if wait <= 0:
                     break
                 done += ck.server_poll(self.srv)
+                tick(k)
                 time.sleep(min(wait, 2e-4))
             ck.server_submit(self.srv, int(self.mid[t]), self.b[t], self.x[t], t)
-        ck.server_drain(self.srv, timeout_s)
-        done += ck.server_poll(self.srv, 1 << 16)
+        end = time.perf_counter() + timeout_s
+        while len(done) < len(idx):
+            done += ck.server_poll(self.srv, 1 << 16)
+            tick(len(idx))
+            if time.perf_counter() > end:
+                ck.server_drain(self.srv, 0.0)   # raises: requests still open
+            time.sleep(1e-3)
         return done
 
     def stats(self):

@@ -12,8 +12,9 @@ decision tree per stage and export the trees as the library's model file.
   fit     : a CART tree per stage (scikit-learn), exported as node tables.
 
 The corpus is synthetic (stencil, power-law, block-diagonal and uniform-random
-families, disjoint seeds from the 48 held-out evaluation matrices), timed on
-this GPU.
+families, disjoint seeds from the 48 held-out evaluation matrices, plus
+Chung-Lu graph Laplacians, whose hub columns none of those families has),
+timed on this GPU.
 
   python -m paper_2411_10143_amd.train collect --out data.csv [--count 200]
   python -m paper_2411_10143_amd.train fit --data data.csv --model cascade_model.txt

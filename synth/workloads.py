@@ -2,7 +2,9 @@
 
 * ``lap2d_64``           : 2D 5-point Laplacian, 64 x 64 (n=4096), CG, tol 1e-10.
 * ``spmv_set``           : 48 SpMV matrices, 4 families x 12 sizes (n 1e4..2e6).
-* ``training_set``       : disjoint-seed matrices from the same families.
+* ``training_set``       : disjoint-seed matrices from the same families, plus
+                           Chung-Lu graph Laplacians (hub rows *and* hub
+                           columns, which no set family has).
 * ``poisson3d_128``      : 3D 7-point Poisson 128^3, CG, tol 1e-10.
 * ``graph_laplacian_1m`` : Chung-Lu graph Laplacian + 1e-2 I, n = 2^20.
 * ``convdiff_1024``      : 2D convection-diffusion 1024^2, Pe 10, GMRES(30).
@@ -17,6 +19,8 @@ import numpy as np
 from . import matrices as M
 
 FAMILIES = ("banded", "powerlaw", "blockdiag", "uniform")
+TRAIN_FAMILIES = FAMILIES + ("graph",)
+GRAPH_MAX_N = 600_000        # keeps a training graph's generation to seconds
 BANDED_R = (5, 7, 9, 13, 19, 27, 5, 7, 9, 13, 19, 27)
 
 
@@ -40,6 +44,10 @@ def family_matrix(family: str, k: int, n: int, seed: int) -> M.CSR:
         return M.block_diagonal(n, seed)
     if family == "uniform":
         return M.uniform_random(n, seed)
+    if family == "graph":
+        return M.graph_laplacian_chung_lu(n, seed, mean_degree=(4, 8, 16, 32)[k % 4],
+                                          zipf_s=(1.8, 2.0, 2.2)[k % 3],
+                                          wmax=min(10_000, max(n // 4, 16)))
     raise ValueError(family)
 
 
@@ -63,12 +71,15 @@ def spmv_set_matrix(spec) -> M.CSR:
 
 
 def training_specs(count: int = 240, seed: int = 9000, lo: float = 1e4, hi: float = 2e6):
-    """Disjoint-seed training matrices: family cycles, n log-uniform in [lo, hi]."""
+    """Disjoint-seed training matrices: the families cycle, n log-uniform in
+    [lo, hi] (graphs at most GRAPH_MAX_N rows)."""
     rng = np.random.default_rng(seed)
     out = []
     for t in range(count):
-        fam = FAMILIES[t % 4]
+        fam = TRAIN_FAMILIES[t % len(TRAIN_FAMILIES)]
         n = int(round(10 ** rng.uniform(math.log10(lo), math.log10(hi))))
+        if fam == "graph":
+            n = min(n, GRAPH_MAX_N)
         k = int(rng.integers(0, 12))
         out.append((f"train{t}_{fam}_n{n}", fam, k, n, seed + 1 + t))
     return out

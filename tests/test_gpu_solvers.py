@@ -46,6 +46,54 @@ def test_cg_lap2d_64_default_config(ck, orc):
     Mx.close()
 
 
+SMALL_SPD = {
+    "lap1d_1": lambda: M.laplacian_1d(1),
+    "lap1d_100": lambda: M.laplacian_1d(100),
+    "lap2d_32": lambda: M.laplacian_2d(32),
+    "lap1d_1025": lambda: M.laplacian_1d(1025),
+    "graph_3001": lambda: M.graph_laplacian_chung_lu(3001, 17, wmax=700),
+    "lap3d_16": lambda: M.laplacian_3d(16),
+}
+
+
+@pytest.mark.parametrize("name", list(SMALL_SPD))
+def test_cg_single_workgroup_path(ck, orc, name):
+    """FP64 CG of at most 4096 rows with no forced configuration runs in one
+    single-workgroup launch (one to four rows per thread)."""
+    A = SMALL_SPD[name]()
+    assert A.n <= 4096
+    xs, b = problem(orc, A, 8)
+    x0 = M.vector(A.n, 9) * 0.1
+    say(f"cg single workgroup {name} n={A.n}")
+    Mx = ck.Matrix.from_csr(A)
+    x, r = run(ck, ck.cg_solve, Mx, b, x0=x0, tol=1e-10)
+    ref = orc.cg(A, b, x0=x0, tol=1e-10)
+    assert r["status"] == ck.CK_OK, r
+    assert r["final_config"] == 0            # CSR-vector, one lane per row
+    rel = orc.relres(A, b, x)
+    assert rel <= 1e-10 and abs(rel - r["true_relres"]) <= 1e-3 * rel + 1e-300
+    assert abs(r["iterations"] - ref["iters"]) <= 3, (r["iterations"], ref["iters"])
+    # budget: the iterate after k steps is the oracle's after k steps
+    k = max(1, min(7, ref["iters"] - 1))
+    if ref["iters"] > 1:
+        x, r = run(ck, ck.cg_solve, Mx, b, x0=x0, tol=1e-14, max_iter=k)
+        assert r["status"] == ck.CK_E_NOT_CONVERGED and r["iterations"] == k
+        refk = orc.cg(A, b, x0=x0, tol=1e-14, maxit=k)
+        assert np.allclose(x, refk["x"], rtol=1e-9, atol=1e-12)
+    Mx.close()
+
+
+def test_cg_above_single_workgroup_limit(ck, orc):
+    A = M.laplacian_1d(4097)
+    xs, b = problem(orc, A, 10)
+    say("cg n=4097 (multi-kernel path)")
+    Mx = ck.Matrix.from_csr(A)
+    x, r = run(ck, ck.cg_solve, Mx, b, tol=1e-10)
+    assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10
+    assert r["final_config"] == ck.config_id(ck.default_config(Mx.handle))
+    Mx.close()
+
+
 @pytest.mark.parametrize("cid", range(12))
 def test_cg_every_config(ck, orc, cid):
     A = M.laplacian_2d(40)

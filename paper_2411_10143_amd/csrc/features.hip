@@ -145,6 +145,13 @@ __device__ __forceinline__ Run run_join(const Run &A, const Run &B) {
     return R;
 }
 
+// Diagonal flags: a thread remembers the last kDiagMemo diagonals it set, so
+// a banded matrix (whose k-th entry of every row lies on the same diagonal)
+// touches its few flag bytes once per thread instead of once per entry; every
+// other entry reads its flag before setting it.  Without this, all entries of
+// a stencil matrix hammer the same few cache lines.
+constexpr int kDiagMemo = 4;
+
 template <bool SYM>
 __global__ __launch_bounds__(256) void feat_nnz(int64_t n, const int *__restrict__ rp,
                                                 const int *__restrict__ col,
@@ -152,80 +159,109 @@ __global__ __launch_bounds__(256) void feat_nnz(int64_t n, const int *__restrict
                                                 unsigned char *__restrict__ diag_flag,
                                                 FeatAcc *acc) {
     constexpr int L = 8;
+    __shared__ unsigned long long part[3][4];
     const int lane = threadIdx.x & (L - 1);
-    const int64_t i = (int64_t)blockIdx.x * (256 / L) + threadIdx.x / L;
+    const int base = (threadIdx.x & 63) & ~(L - 1);
     unsigned long long dcount = 0, asym = 0, cl = 0;
-    Run mine{0, 0, 0, 0, 0, 0};
+    int64_t memo[kDiagMemo];
+#pragma unroll
+    for (int m = 0; m < kDiagMemo; ++m)
+        memo[m] = -1;
+    int slot = 0;
     // once any block has found an unmatched entry the answer is fixed, so
     // later blocks skip the transposed-entry searches
     const bool search = SYM && __builtin_nontemporal_load(&acc->asym) == 0;
-    if (i < n) {
-        const int k0 = rp[i], k1 = rp[i + 1];
-        const int r = k1 - k0;
-        const int chunk = (r + L - 1) / L;
-        const int a = k0 + lane * chunk;
-        const int e = min(k1, a + chunk);
-        for (int k = a; k < e; ++k) {
-            const int c = col[k];
-            if (k == a) {
-                mine = Run{1, 1, 1, 1, c, c};
-            } else {
-                const bool cont = c == mine.last + 1;
-                mine.suf = cont ? mine.suf + 1 : 1;
-                if (cont && mine.pre == mine.len)
-                    mine.pre += 1;
-                mine.len += 1;
-                mine.best = max(mine.best, mine.suf);
-                mine.last = c;
-            }
-            // test before setting: most entries land on an already-set diagonal,
-            // and a read costs far less than a partial-line byte write
-            unsigned char *fl = &diag_flag[(int64_t)c - i + (n - 1)];
-            if (*fl == 0)
-                *fl = 1;
-            if (c == i)
-                dcount += 1;
-            if (search && asym == 0) {
-                // transposed entry (c, i) must be stored with the same value
-                int lo = rp[c], hi = rp[c + 1];
-                while (lo < hi) {
-                    const int mid = (lo + hi) >> 1;
-                    if (col[mid] < (int)i)
-                        lo = mid + 1;
-                    else
-                        hi = mid;
+    const int64_t groups = (n + 256 / L - 1) / (256 / L);
+    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
+        const int64_t i = g * (256 / L) + threadIdx.x / L;
+        Run mine{0, 0, 0, 0, 0, 0};
+        if (i < n) {
+            const int k0 = rp[i], k1 = rp[i + 1];
+            const int r = k1 - k0;
+            const int chunk = (r + L - 1) / L;
+            const int a = k0 + lane * chunk;
+            const int e = min(k1, a + chunk);
+            for (int k = a; k < e; ++k) {
+                const int c = col[k];
+                if (k == a) {
+                    mine = Run{1, 1, 1, 1, c, c};
+                } else {
+                    const bool cont = c == mine.last + 1;
+                    mine.suf = cont ? mine.suf + 1 : 1;
+                    if (cont && mine.pre == mine.len)
+                        mine.pre += 1;
+                    mine.len += 1;
+                    mine.best = max(mine.best, mine.suf);
+                    mine.last = c;
                 }
-                if (lo >= rp[c + 1] || col[lo] != (int)i || val[lo] != val[k])
-                    asym = 1;
+                const int64_t d = (int64_t)c - i + (n - 1);
+                bool seen = false;
+#pragma unroll
+                for (int m = 0; m < kDiagMemo; ++m)
+                    seen |= memo[m] == d;
+                if (!seen) {
+                    if (diag_flag[d] == 0)
+                        diag_flag[d] = 1;
+#pragma unroll
+                    for (int m = 0; m < kDiagMemo; ++m)
+                        if (m == slot)
+                            memo[m] = d;
+                    slot = slot + 1 == kDiagMemo ? 0 : slot + 1;
+                }
+                if (c == i)
+                    dcount += 1;
+                if (search && asym == 0) {
+                    // transposed entry (c, i) must be stored with the same value
+                    int lo = rp[c], hi = rp[c + 1];
+                    while (lo < hi) {
+                        const int mid = (lo + hi) >> 1;
+                        if (col[mid] < (int)i)
+                            lo = mid + 1;
+                        else
+                            hi = mid;
+                    }
+                    if (lo >= rp[c + 1] || col[lo] != (int)i || val[lo] != val[k])
+                        asym = 1;
+                }
             }
         }
-    }
-    // fold the L chunk summaries of a row in lane order (lane 0 of the group)
-    const int base = (threadIdx.x & 63) & ~(L - 1);
-    Run tot = mine;
+        // fold the L chunk summaries of a row in lane order (lane 0 of the group)
+        Run tot = mine;
 #pragma unroll
-    for (int t = 1; t < L; ++t) {
-        Run o;
-        o.len = __shfl(mine.len, base + t, 64);
-        o.pre = __shfl(mine.pre, base + t, 64);
-        o.suf = __shfl(mine.suf, base + t, 64);
-        o.best = __shfl(mine.best, base + t, 64);
-        o.first = __shfl(mine.first, base + t, 64);
-        o.last = __shfl(mine.last, base + t, 64);
-        tot = run_join(tot, o);
+        for (int t = 1; t < L; ++t) {
+            Run o;
+            o.len = __shfl(mine.len, base + t, 64);
+            o.pre = __shfl(mine.pre, base + t, 64);
+            o.suf = __shfl(mine.suf, base + t, 64);
+            o.best = __shfl(mine.best, base + t, 64);
+            o.first = __shfl(mine.first, base + t, 64);
+            o.last = __shfl(mine.last, base + t, 64);
+            tot = run_join(tot, o);
+        }
+        if (lane == 0 && i < n)
+            cl += (unsigned long long)tot.best;
     }
-    if (lane == 0 && i < n)
-        cl = (unsigned long long)tot.best;
+    // one atomic per block and counter
     cl = ck::wave_sum(cl);
     dcount = ck::wave_sum(dcount);
     asym = ck::wave_sum(asym);
+    const int w = threadIdx.x >> 6;
     if ((threadIdx.x & 63) == 0) {
-        if (cl)
-            atomicAdd(&acc->cluster, cl);
-        if (dcount)
-            atomicAdd(&acc->diag_nnz, dcount);
-        if (asym)
-            atomicAdd(&acc->asym, asym);
+        part[0][w] = cl;
+        part[1][w] = dcount;
+        part[2][w] = asym;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t0 = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+        const unsigned long long t1 = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+        const unsigned long long t2 = part[2][0] + part[2][1] + part[2][2] + part[2][3];
+        if (t0)
+            atomicAdd(&acc->cluster, t0);
+        if (t1)
+            atomicAdd(&acc->diag_nnz, t1);
+        if (t2)
+            atomicAdd(&acc->asym, t2);
     }
 }
 
@@ -354,7 +390,7 @@ ck_status launch_features(const ck_matrix &M, void *scratch, bool symmetry, hipS
     if (M.n > 0) {
         hipLaunchKernelGGL(feat_rows, dim3(std::min<int64_t>(ceil_div(M.n, 256), 2048)), dim3(256),
                            0, s, M.n, M.rp, M.col, acc);
-        const int64_t G = ceil_div(M.n, 256 / 8);
+        const int64_t G = std::min<int64_t>(ceil_div(M.n, 256 / 8), 8192);
         if (symmetry && M.n == M.ncols)
             hipLaunchKernelGGL((feat_nnz<true>), dim3(G), dim3(256), 0, s, M.n, M.rp, M.col,
                                M.val, flags, acc);

@@ -76,7 +76,7 @@ def labels(times):
     return fmt, alg, lanes
 
 
-def collect(out_csv, count=200, seed=9000, reps=None):
+def collect(out_csv, count=600, seed=9000, reps=None):
     import torch
 
     import paper_2411_10143_amd as ck
@@ -185,13 +185,13 @@ def main(argv=None):
     sub = p.add_subparsers(dest="cmd", required=True)
     c = sub.add_parser("collect")
     c.add_argument("--out", required=True)
-    c.add_argument("--count", type=int, default=200)
+    c.add_argument("--count", type=int, default=600)
     c.add_argument("--seed", type=int, default=9000)
     c.add_argument("--reps", type=int, default=None)
     fa = sub.add_parser("fit")
     fa.add_argument("--data", required=True, nargs="+")
     fa.add_argument("--model", required=True)
-    fa.add_argument("--max-depth", type=int, default=6)
+    fa.add_argument("--max-depth", type=int, default=10)
     fa.add_argument("--min-leaf", type=int, default=1)
     a = p.parse_args(argv)
     if a.cmd == "collect":

@@ -70,7 +70,7 @@ def spmv_set_matrix(spec) -> M.CSR:
     return A
 
 
-def training_specs(count: int = 240, seed: int = 9000, lo: float = 1e4, hi: float = 2e6):
+def training_specs(count: int = 600, seed: int = 9000, lo: float = 1e4, hi: float = 2e6):
     """Disjoint-seed training matrices: the families cycle, n log-uniform in
     [lo, hi] (graphs at most GRAPH_MAX_N rows)."""
     rng = np.random.default_rng(seed)

@@ -9,7 +9,7 @@ configurations the bench times:
 * ELL and COO conversions byte-exact on the largest member of each family;
 * CG on the 3D Poisson 128^3 and 2^20-row graph Laplacian systems (async
   executor) and GMRES(30) on convection-diffusion 1024^2, FP64 and mixed,
-  judged by the oracle's true FP64 residual.
+  checked by the oracle's true FP64 residual.
 """
 import numpy as np
 import pytest

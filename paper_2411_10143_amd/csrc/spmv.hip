@@ -248,6 +248,14 @@ __device__ __forceinline__ void finish_carries(int *s_crow, T *s_cval, int frow,
     }
 }
 
+// Merge-path CSR.  Workgroup b owns merged items [2048 b, 2048 (b+1)) of the
+// merge of the row ends rp[1..n] with the entries 0..nnz-1.  Two threads find
+// the workgroup's start and end coordinates; the workgroup then stages the
+// row ends it crosses and the products val[j] * x[col[j]] of the entries it
+// covers in LDS with coalesced loads (eight gathers per thread in flight), and
+// every thread walks its eight items from LDS after a local merge-path search.
+// Rows cut by thread boundaries are completed in LDS, rows cut by workgroup
+// boundaries by carry_fixup.
 template <typename T, bool BETA>
 __global__ __launch_bounds__(256) void spmv_merge(int n, int nnz, int64_t G,
                                                   const int *__restrict__ rp,
@@ -257,8 +265,12 @@ __global__ __launch_bounds__(256) void spmv_merge(int n, int nnz, int64_t G,
                                                   T *__restrict__ y, int *__restrict__ crow_g,
                                                   T *__restrict__ cval_g,
                                                   const int *__restrict__ skip) {
+    constexpr int ITEMS = 256 * kMergeIPT;
     __shared__ int s_crow[256];
     __shared__ T s_cval[256];
+    __shared__ int s_rend[ITEMS + 1];   // ends of rows i0 .. i1 (local entry index + j0)
+    __shared__ T s_prod[ITEMS];         // products of entries j0 .. j1-1
+    __shared__ int s_coord[4];
     if (skipped(skip))
         return;
     const int64_t b = ck::xcd_block(G);
@@ -266,30 +278,71 @@ __global__ __launch_bounds__(256) void spmv_merge(int n, int nnz, int64_t G,
         return;
     const int tid = threadIdx.x;
     const int64_t P = (int64_t)n + nnz;
-    const int64_t d0 = (b * 256 + tid) * kMergeIPT;
-    int crow = -1, frow = -1;
-    T cval = 0, fval = 0;
-    if (d0 < P) {
-        const int64_t d1 = min(d0 + kMergeIPT, P);
-        // merge-path search: i = row ends among the first d0 merged items
-        int lo = (int)max<int64_t>(0, d0 - nnz), hi = (int)min<int64_t>(d0, n);
+    const int64_t D0 = b * ITEMS;
+    const int64_t D1 = min(D0 + ITEMS, P);
+    if (tid < 2) {   // merge-path coordinates of D0 (thread 0) and D1 (thread 1)
+        const int64_t d = tid == 0 ? D0 : D1;
+        int lo = (int)max<int64_t>(0, d - nnz), hi = (int)min<int64_t>(d, n);
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if ((int64_t)rp[mid + 1] <= d0 - mid - 1)
+            if ((int64_t)rp[mid + 1] <= d - mid - 1)
                 lo = mid + 1;
             else
                 hi = mid;
         }
-        int i = lo;
-        int j = (int)(d0 - lo);
-        int rend = i < n ? rp[i + 1] : nnz;
+        s_coord[2 * tid] = lo;
+        s_coord[2 * tid + 1] = (int)(d - lo);
+    }
+    __syncthreads();
+    const int i0 = s_coord[0], j0 = s_coord[1], i1 = s_coord[2], j1 = s_coord[3];
+    const int nrows = i1 - i0 + 1;   // rows i0 .. i1 (i1 may be n)
+    const int nents = j1 - j0;
+    for (int t = tid; t < nrows; t += 256)
+        s_rend[t] = i0 + t < n ? rp[i0 + t + 1] : nnz;
+    for (int t0 = 0; t0 < nents; t0 += 256 * kMergeIPT) {
+        int cc[kMergeIPT];
+        T vv[kMergeIPT], xv[kMergeIPT];
+#pragma unroll
+        for (int u = 0; u < kMergeIPT; ++u) {
+            const int t = min(t0 + u * 256 + tid, nents - 1);
+            cc[u] = ld_stream(&col[j0 + t]);
+            vv[u] = ld_stream(&val[j0 + t]);
+        }
+#pragma unroll
+        for (int u = 0; u < kMergeIPT; ++u)
+            xv[u] = x[cc[u]];
+        __builtin_amdgcn_sched_barrier(0);   // all gathers in flight before the first use
+#pragma unroll
+        for (int u = 0; u < kMergeIPT; ++u)
+            if (t0 + u * 256 + tid < nents)
+                s_prod[t0 + u * 256 + tid] = vv[u] * xv[u];
+    }
+    __syncthreads();
+    int crow = -1, frow = -1;
+    T cval = 0, fval = 0;
+    const int dl = tid * kMergeIPT;   // this thread's first local item
+    if (D0 + dl < D1) {
+        const int dle = (int)min<int64_t>(dl + kMergeIPT, D1 - D0);
+        // local merge-path search: a = row ends among the block's first dl items
+        int lo = max(0, dl - nents), hi = min(dl, nrows - 1);
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (s_rend[mid] - j0 <= dl - mid - 1)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        int a = lo;
+        int e = dl - lo;
+        int rend = s_rend[a] - j0;
         T acc = 0;
         bool first = true;
-        for (int64_t d = d0; d < d1; ++d) {
-            if (j < rend) {
-                acc += ld_stream(&val[j]) * x[ld_stream(&col[j])];
-                ++j;
+        for (int d = dl; d < dle; ++d) {
+            if (e < rend) {
+                acc += s_prod[e];
+                ++e;
             } else {
+                const int i = i0 + a;
                 if (first) {
                     frow = i;
                     fval = acc;
@@ -301,11 +354,11 @@ __global__ __launch_bounds__(256) void spmv_merge(int n, int nnz, int64_t G,
                     y[i] = out;
                 }
                 acc = 0;
-                ++i;
-                rend = i < n ? rp[i + 1] : nnz;
+                ++a;
+                rend = s_rend[a] - j0;
             }
         }
-        crow = i < n ? i : -1;
+        crow = i0 + a < n ? i0 + a : -1;
         cval = acc;
     }
     s_crow[tid] = crow;
@@ -327,30 +380,58 @@ __global__ __launch_bounds__(256) void spmv_coo(int n, int nnz, int64_t G,
                                                 T *__restrict__ y, int *__restrict__ crow_g,
                                                 T *__restrict__ cval_g,
                                                 const int *__restrict__ skip) {
+    constexpr int ITEMS = 256 * kCooIPT;
     __shared__ int s_crow[256];
     __shared__ T s_cval[256];
+    __shared__ int s_row[ITEMS + 1];   // row of entries K0 .. K0+cnt (the last: next row or n)
+    __shared__ T s_prod[ITEMS];
     if (skipped(skip))
         return;
     const int64_t b = ck::xcd_block(G);
     if (b < 0)
         return;
     const int tid = threadIdx.x;
-    const int64_t k0 = (b * 256 + tid) * kCooIPT;
+    // stage this workgroup's entries: rows and products, coalesced, with the
+    // eight gathers of a thread in flight together
+    const int64_t K0 = b * ITEMS;
+    const int cnt = (int)min<int64_t>(ITEMS, nnz - K0);
+    {
+        int cc[kCooIPT];
+        T vv[kCooIPT], xv[kCooIPT];
+#pragma unroll
+        for (int u = 0; u < kCooIPT; ++u) {
+            const int t = min(u * 256 + tid, cnt - 1);
+            cc[u] = ld_stream(&col[K0 + t]);
+            vv[u] = ld_stream(&val[K0 + t]);
+        }
+#pragma unroll
+        for (int u = 0; u < kCooIPT; ++u)
+            xv[u] = x[cc[u]];
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < kCooIPT; ++u)
+            if (u * 256 + tid < cnt)
+                s_prod[u * 256 + tid] = vv[u] * xv[u];
+    }
+    for (int t = tid; t <= cnt; t += 256)
+        s_row[t] = K0 + t < nnz ? ld_stream(&row[K0 + t]) : n;
+    __syncthreads();
+    const int k0 = tid * kCooIPT;   // this thread's first local entry
     int crow = -1, frow = -1;
     T cval = 0, fval = 0;
-    if (k0 < nnz) {
-        const int k1 = (int)min<int64_t>(k0 + kCooIPT, nnz);
-        if (k0 == 0) {   // rows before the first stored entry are empty
-            const int r_first = row[0];
+    if (k0 < cnt) {
+        const int k1 = min(k0 + kCooIPT, cnt);
+        if (K0 + k0 == 0) {   // rows before the first stored entry are empty
+            const int r_first = s_row[0];
             for (int r = 0; r < r_first; ++r)
                 y[r] = BETA ? beta * y[r] : T(0);
         }
-        int cur = row[k0];
+        int cur = s_row[k0];
         T acc = 0;
         bool first = true;
-        for (int k = (int)k0; k < k1; ++k) {
-            acc += ld_stream(&val[k]) * x[ld_stream(&col[k])];
-            const int nxt = (k + 1 < nnz) ? row[k + 1] : n;
+        for (int k = k0; k < k1; ++k) {
+            acc += s_prod[k];
+            const int nxt = s_row[k + 1];
             if (nxt != cur) {
                 if (first) {
                     frow = cur;
@@ -368,9 +449,8 @@ __global__ __launch_bounds__(256) void spmv_coo(int n, int nnz, int64_t G,
                 cur = nxt;
             }
         }
-        const int nxt = (k1 < nnz) ? row[k1] : n;
-        if (nxt == row[k1 - 1]) {
-            crow = row[k1 - 1];
+        if (s_row[k1] == s_row[k1 - 1]) {   // the thread ends inside a row
+            crow = s_row[k1 - 1];
             cval = acc;
         }
     }

@@ -191,7 +191,7 @@ def main(argv=None):
     fa = sub.add_parser("fit")
     fa.add_argument("--data", required=True, nargs="+")
     fa.add_argument("--model", required=True)
-    fa.add_argument("--max-depth", type=int, default=10)
+    fa.add_argument("--max-depth", type=int, default=6)
     fa.add_argument("--min-leaf", type=int, default=1)
     a = p.parse_args(argv)
     if a.cmd == "collect":

@@ -5,8 +5,9 @@
 // over the basis:
 //   pass 1: partials of V_j^T w                        -> finish: h1
 //   pass 2: w' = w - V_j h1, and in the same sweep partials of V_j^T w' (h2)
-//           and of ||w'||^2                            -> finish: h2, ||w'||^2
-//   givens: h_{j+1,j} = sqrt(||w'||^2 - ||h2||^2) (Pythagoras: w' - V_j h2 is
+//           and of ||w'||^2
+//   givens: one workgroup sums the pass-2 partials (h2, ||w'||^2), then
+//           h_{j+1,j} = sqrt(||w'||^2 - ||h2||^2) (Pythagoras: w' - V_j h2 is
 //           w' minus its projection on the orthonormal V_j), column j of the
 //           Hessenberg matrix (h1 + h2), previous Givens rotations, rotation
 //           j, residual estimate |g_{j+1}|, cycle stop decision
@@ -157,27 +158,52 @@ __global__ __launch_bounds__(256) void gm_pass3(int64_t n, int64_t G, int ncols,
     }
 }
 
-// h_{j+1,j}, Hessenberg column j, previous rotations, new rotation, estimate.
-// h2[j+1] holds ||w'||^2 from the pass-2 finish.  The values the rotation
-// chain needs are first loaded in parallel into LDS; one thread then runs the
-// chain without a global-memory round trip per rotation.
+// Pass-2 finish and Givens step in one 1024-thread workgroup:
+//  1. wave w sums the G block partials of columns w, w + 16, ... (h2[c] for
+//     c <= j, and ||w'||^2 as column j + 1), lanes striding the blocks, then a
+//     wave butterfly (fixed order);
+//  2. h_{j+1,j} = sqrt(||w'||^2 - ||h2||^2), Hessenberg column j (h1 + h2),
+//     previous rotations, new rotation, residual estimate -- one thread, from
+//     LDS, with no global-memory round trip per rotation.
 template <typename T>
-__global__ __launch_bounds__(64) void gm_finish_givens(GmDev<T> *st) {
-    __shared__ T col[ck::kMaxRestart], h2[ck::kMaxRestart], cs[ck::kMaxRestart],
+__global__ __launch_bounds__(1024) void gm_finish_givens(int64_t G, const T *__restrict__ partials,
+                                                         GmDev<T> *st) {
+    constexpr int U = 8;
+    __shared__ T col[ck::kMaxRestart], h2[ck::kMaxRestart + 1], cs[ck::kMaxRestart],
         sn[ck::kMaxRestart];
     if (st->halt)
         return;
     const int m = st->m;
     const int j = st->j;
-    for (int c = threadIdx.x; c <= j; c += 64) {
-        const T b = st->h2[c];
-        col[c] = st->h1[c] + b;
-        h2[c] = b;
-        if (c < j) {
-            cs[c] = st->cs[c];
-            sn[c] = st->sn[c];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int c = w; c <= j + 1; c += 16) {
+        const T *pc = partials + (int64_t)c * G;
+        T acc = 0;
+        for (int64_t b0 = lane; b0 < G; b0 += 64 * U) {
+            T v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t b = b0 + 64 * u;
+                v[u] = __builtin_nontemporal_load(&pc[b < G ? b : G - 1]);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (b0 + 64 * u < G)
+                    acc += v[u];
+        }
+        acc = ck::wave_sum(acc);
+        if (lane == 0) {
+            h2[c] = acc;
+            st->h2[c] = acc;   // pass 3 subtracts V h2
         }
     }
+    for (int c = threadIdx.x; c < j; c += 1024) {
+        cs[c] = st->cs[c];
+        sn[c] = st->sn[c];
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c <= j; c += 1024)
+        col[c] = st->h1[c] + h2[c];
     __syncthreads();
     if (threadIdx.x != 0)
         return;
@@ -185,7 +211,7 @@ __global__ __launch_bounds__(64) void gm_finish_givens(GmDev<T> *st) {
     T proj = 0;
     for (int c = 0; c <= j; ++c)
         proj += h2[c] * h2[c];
-    const T nrm2 = st->h2[j + 1] - proj;
+    const T nrm2 = h2[j + 1] - proj;
     const T hn = nrm2 > T(0) ? sqrt(nrm2) : T(0);
     // previous rotations applied to (h_0j, ..., h_jj, hn); `a` carries entry i
     T a = col[0];
@@ -367,9 +393,7 @@ static void arnoldi_nc(int64_t n, int64_t G, int ncols, T *V, int64_t ldv, T *w,
     hipLaunchKernelGGL((gm_finish_cols<T>), dim3(ncols), dim3(256), 0, s, G, partials, 1, st);
     hipLaunchKernelGGL((gm_pass2<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w,
                        partials, st);
-    hipLaunchKernelGGL((gm_finish_cols<T>), dim3(ncols + 1), dim3(256), 0, s, G, partials, 2,
-                       st);
-    hipLaunchKernelGGL((gm_finish_givens<T>), dim3(1), dim3(64), 0, s, st);
+    hipLaunchKernelGGL((gm_finish_givens<T>), dim3(1), dim3(1024), 0, s, G, partials, st);
     hipLaunchKernelGGL((gm_pass3<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w, st);
 }
 

@@ -23,22 +23,28 @@ namespace {
 constexpr int kWgThreads = 1024;
 constexpr int kWgWaves = kWgThreads / 64;
 
-// sum over the workgroup, returned to every thread; `red` holds kWgWaves
-// doubles; two barriers so that the buffer may be reused right after
-__device__ __forceinline__ double wg_sum_1024(double v, double *red) {
+// sum over the workgroup, returned to every thread (fixed order).  Successive
+// calls alternate between the two halves of `red` (2 x kWgWaves doubles), so
+// one barrier per call suffices: a half is rewritten only two calls later,
+// after every thread has passed the barrier of the call in between, and so
+// has finished reading it.
+__device__ __forceinline__ double wg_sum_1024(double v, double *red, int &parity) {
+    double *buf = red + parity * kWgWaves;
+    parity ^= 1;
     v = ck::wave_sum(v);
     if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = v;
+        buf[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = 0;
 #pragma unroll
     for (int w = 0; w < kWgWaves; ++w)
-        s += red[w];
-    __syncthreads();
+        s += buf[w];
     return s;
 }
 
-// q[u] = (A v)[row u of this thread], v in LDS
+// q[u] = (A v)[row u of this thread], v in LDS.  The column and value loads
+// of step t + 1 are issued before the gathers and products of step t, so one
+// memory round trip overlaps the next.
 template <int R>
 __device__ __forceinline__ void wg_matvec(const int (&kb)[R], const int (&ke)[R], int trips,
                                           const int *__restrict__ col,
@@ -47,21 +53,36 @@ __device__ __forceinline__ void wg_matvec(const int (&kb)[R], const int (&ke)[R]
 #pragma unroll
     for (int u = 0; u < R; ++u)
         q[u] = 0;
+    if (trips == 0)
+        return;
+    int cc[R];
+    double vv[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const int kk = kb[u] < ke[u] ? kb[u] : 0;   // entry 0 exists when trips > 0
+        cc[u] = col[kk];
+        vv[u] = val[kk];
+    }
     for (int t = 0; t < trips; ++t) {
-        int cc[R];
-        double vv[R];
+        int cn[R];
+        double vn[R];
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-            const int k = kb[u] + t;
-            const int kk = k < ke[u] ? k : 0;   // entry 0 exists when trips > 0
-            cc[u] = col[kk];
-            vv[u] = val[kk];
+            const int k = kb[u] + t + 1;
+            const int kk = k < ke[u] ? k : 0;
+            cn[u] = col[kk];
+            vn[u] = val[kk];
         }
-        __builtin_amdgcn_sched_barrier(0);   // every row's loads in flight together
+        __builtin_amdgcn_sched_barrier(0);   // next step's loads in flight first
 #pragma unroll
         for (int u = 0; u < R; ++u)
             if (kb[u] + t < ke[u])
                 q[u] += vv[u] * v[cc[u]];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            cc[u] = cn[u];
+            vv[u] = vn[u];
+        }
     }
 }
 
@@ -75,7 +96,8 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
                                                     double *__restrict__ x, double tol,
                                                     int max_iter, ck::WgCgOut *out) {
     __shared__ double v[kWgThreads * R];   // p (or x while forming the residual)
-    __shared__ double red[kWgWaves];
+    __shared__ double red[2 * kWgWaves];
+    int parity = 0;
     const int t = threadIdx.x;
     int kb[R], ke[R];
     double xr[R], rr[R], pr[R], q[R];
@@ -92,7 +114,7 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
         trips = max(trips, ke[u] - kb[u]);
         bb += bi * bi;
     }
-    const double bnorm = sqrt(wg_sum_1024(bb, red));
+    const double bnorm = sqrt(wg_sum_1024(bb, red, parity));
     int status = ck::BUDGET, iters = 0, restarts = 0;
     double relres = 0;
     if (bnorm == 0.0) {
@@ -117,7 +139,7 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
                 pr[u] = rr[u];
                 rho += rr[u] * rr[u];
             }
-            rho = wg_sum_1024(rho, red);   // its barriers also retire the reads of v
+            rho = wg_sum_1024(rho, red, parity);   // its barrier also retires the reads of v
             relres = sqrt(rho) / bnorm;
             if (relres <= tol) {
                 status = ck::CONVERGED;
@@ -139,7 +161,7 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
 #pragma unroll
                 for (int u = 0; u < R; ++u)
                     pq += pr[u] * q[u];
-                const double sigma = wg_sum_1024(pq, red);
+                const double sigma = wg_sum_1024(pq, red, parity);
                 if (!(sigma > 0.0)) {
                     state = ck::BREAKDOWN;
                     break;
@@ -152,7 +174,7 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
                     rr[u] -= alpha * q[u];
                     rn += rr[u] * rr[u];
                 }
-                const double rho_new = wg_sum_1024(rn, red);
+                const double rho_new = wg_sum_1024(rn, red, parity);
                 ++iters;
                 if (sqrt(rho_new) / bnorm <= tol) {
                     state = ck::CONVERGED;
@@ -182,7 +204,7 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
                 const double d = (i < n ? b[i] : 0.0) - q[u];
                 tr += d * d;
             }
-            relres = sqrt(wg_sum_1024(tr, red)) / bnorm;
+            relres = sqrt(wg_sum_1024(tr, red, parity)) / bnorm;
             if (relres <= tol) {
                 status = ck::CONVERGED;
                 break;

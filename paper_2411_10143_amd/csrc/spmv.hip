@@ -134,8 +134,26 @@ __global__ __launch_bounds__(256) void spmv_csr_scalar(int n, int64_t G,
         T acc = 0;
         for (int base = k0; base < k1; base += kScalarCap) {
             const int cnt = min(kScalarCap, k1 - base);
-            for (int t = tid; t < cnt; t += 256)
-                prod[t] = ld_stream(&val[base + t]) * x[ld_stream(&col[base + t])];
+            // eight products per thread per step, their loads and gathers in
+            // flight together (index clamped, store masked)
+            for (int t0 = 0; t0 < cnt; t0 += 8 * 256) {
+                int cc[8];
+                T vv[8], xv[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int t = min(t0 + u * 256 + tid, cnt - 1);
+                    cc[u] = ld_stream(&col[base + t]);
+                    vv[u] = ld_stream(&val[base + t]);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    xv[u] = x[cc[u]];
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    if (t0 + u * 256 + tid < cnt)
+                        prod[t0 + u * 256 + tid] = vv[u] * xv[u];
+            }
             __syncthreads();
             const int lo = max(my_lo, base), hi = min(my_hi, base + cnt);
             for (int k = lo; k < hi; ++k)

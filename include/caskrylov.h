@@ -199,7 +199,12 @@ ck_status spmv_apply_f32(ck_handle h, const ck_config *cfg, float alpha, const f
  * b - A x, restarting from the current x (at most 3 times) if needed.
  * p.Ap <= 0 gives CK_E_BREAKDOWN.  opts->async = 1 runs the asynchronous
  * executor (Section III-C-2).  MIXED precision: FP64 refinement around FP32
- * CG segments.  Blocks until the result is final; d_x then holds x. */
+ * CG segments.  Blocks until the result is final; d_x then holds x.
+ * Small systems run in one launch: FP64 solves of at most 4096 rows with
+ * neither async nor use_config run on a single 1024-thread workgroup whose
+ * product takes one lane per row (final_config reports CSR-vector with 1
+ * lane); other systems of at most 16384 rows with a CSR-vector configuration
+ * and no async run on the request loop's batched kernel. */
 ck_status cg_solve(ck_handle h, const double *d_b, double *d_x, const ck_solve_opts *opts,
                    ck_solve_result *res, hipStream_t s);
 
@@ -207,7 +212,9 @@ ck_status cg_solve(ck_handle h, const double *d_b, double *d_x, const ck_solve_o
  * solver of the paper's evaluation, Section IV).  Each cycle starts from the
  * true residual; Arnoldi uses classical Gram-Schmidt applied twice; the
  * Givens least-squares update runs on the device.  MIXED precision: each
- * FP64 refinement step runs one FP32 GMRES(m) cycle on r/||r||. */
+ * FP64 refinement step runs one FP32 GMRES(m) cycle on r/||r||.  Systems of
+ * at most 16384 rows with a CSR-vector configuration, m <= 32 and no async
+ * run in one launch of the request loop's batched kernel. */
 ck_status gmres_solve(ck_handle h, const double *d_b, double *d_x, const ck_solve_opts *opts,
                       ck_solve_result *res, hipStream_t s);
 

@@ -120,6 +120,9 @@ class AsyncExec {
         }
     }
 
+    // true while a stage decision has not been applied yet
+    bool pending() const { return !(applied_[0] && applied_[1] && applied_[2]); }
+
     void finish() {
         cancel_.store(true);
         if (worker_.joinable())
@@ -304,10 +307,14 @@ ck_status cg_core(SolveCtx &c, T *x, T *r, T *p, T *q, T *partials, CgDev<T> *de
     CK_TRY(launch_cg_start<T>(c.M.n, r, p, partials, dev, c.s));
     const int every = std::max(1, c.o.check_every > 0 ? c.o.check_every : 8);
     const int *state_ptr = &dev->state;
-    int slot = 0, polls = 0;
+    int slot = 0, polls = 0, since_poll = 0;
     int issued = 0;
     const int budget = max_iter - iter_total;
     while (true) {
+        // the host runs up to two polls ahead of the device; while a cascade
+        // decision may still arrive, poll every other iteration so that a
+        // decision reaches the device within a few iterations
+        const int every_now = (c.exec && c.exec->pending()) ? std::min(every, 2) : every;
         c.poll(iter_total + issued);
         const bool fused = spmv_fuses_dot(c.cfg);
         if (fused) {
@@ -319,7 +326,8 @@ ck_status cg_core(SolveCtx &c, T *x, T *r, T *p, T *q, T *partials, CgDev<T> *de
         }
         CK_TRY(launch_cg_update<T>(c.M.n, x, r, p, q, partials, dev, c.s));
         ++issued;
-        if (issued % every == 0 || issued >= budget) {
+        if (++since_poll >= every_now || issued >= budget) {
+            since_poll = 0;
             // stage this poll, then read the previous one
             CK_HIP(hipMemcpyAsync(pin.buf + 64 * slot, &dev->state, 2 * sizeof(int),
                                   hipMemcpyDeviceToHost, c.s));

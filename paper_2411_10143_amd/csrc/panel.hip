@@ -192,14 +192,6 @@ int panel_count_for(int64_t ncols, int value_bytes) {
     return (int)(8 * q);
 }
 
-int panel_lanes_for(int64_t n, int64_t nnz, int P) {
-    const int64_t mean = n > 0 ? nnz / (n * P) : 0;
-    int L = 1;
-    while ((int64_t)L * 2 <= mean && L < 64)
-        L *= 2;
-    return L;
-}
-
 int64_t panel_scan_tmp_elems(int64_t N) {
     const int64_t b1 = ceil_div(N + 1, 2048);
     const int64_t b2 = ceil_div(b1, 2048);

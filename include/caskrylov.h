@@ -149,9 +149,12 @@ ck_status spmv_features(ck_handle h, ck_features *out, hipStream_t s);
 
 /* spmv_select -- host-only cascaded inference (Section III-C-1): stage 1
  * format, stage 2 CSR algorithm (only if CSR; scalar, vector, merge or
- * panel), stage 3 lanes (only if CSR-vector).  model_path: a cascade model file, or NULL for the model
- * shipped next to the library.  A stage that does not run keeps the default
- * configuration's value for its field.  *out->stages_done = stages run. */
+ * panel), stage 3 lanes (only if CSR-vector).  model_path: a cascade model
+ * file, or NULL for the default model: the file named by the environment
+ * variable CK_CASCADE_MODEL if set, else cascade_model.txt next to the
+ * library (the async executor and the request loop use the default model).
+ * A stage that does not run keeps the default configuration's value for its
+ * field.  *out->stages_done = stages run. */
 ck_status spmv_select(const ck_features *f, const char *model_path, ck_config *out);
 
 /* ck_select_stages -- the same inference, reporting each stage's raw class:

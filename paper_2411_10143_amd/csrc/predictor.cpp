@@ -108,6 +108,9 @@ bool parse_model(const std::string &path, Cascade &out, std::string &err) {
 }
 
 std::string default_model_path() {
+    const char *env = std::getenv("CK_CASCADE_MODEL");
+    if (env && *env)
+        return std::string(env);
     Dl_info info;
     if (dladdr((void *)&default_model_path, &info) && info.dli_fname) {
         std::string p(info.dli_fname);

@@ -107,7 +107,7 @@ class AsyncExec {
                 applied_[t] = true;
                 continue;
             }
-            if (t == 0 && conv_needed_.load(std::memory_order_acquire)) {
+            if (conv_needed_[t].load(std::memory_order_acquire)) {
                 const hipError_t e = hipEventQuery(conv_done_);
                 if (e == hipErrorNotReady)
                     return;
@@ -188,7 +188,7 @@ class AsyncExec {
                 return;
             }
             (void)hipEventRecord(conv_done_, side_);
-            conv_needed_.store(true, std::memory_order_release);
+            conv_needed_[0].store(true, std::memory_order_release);
             publish(0, c);
             skip_rest(1);
             (void)hipEventSynchronize(conv_done_);
@@ -204,6 +204,26 @@ class AsyncExec {
         const int alg = C->tree[1].eval(in);
         t_infer += us_since(t1);
         c = stage_config(1, alg, c);
+        if (alg == CK_ALG_PANEL) {
+            // the panel-major copy must exist before the switch
+            if (cancel_.load()) {
+                skip_rest(1);
+                return;
+            }
+            auto t2 = Clock::now();
+            if (convert_format(M_, c, side_) != CK_OK) {
+                conversion_failed = 1;
+                skip_rest(1);
+                return;
+            }
+            (void)hipEventRecord(conv_done_, side_);
+            conv_needed_[1].store(true, std::memory_order_release);
+            publish(1, c);
+            skip_rest(2);
+            (void)hipEventSynchronize(conv_done_);
+            t_convert = us_since(t2);
+            return;
+        }
         publish(1, c);
         if (alg != CK_ALG_VECTOR) {
             skip_rest(2);
@@ -222,7 +242,7 @@ class AsyncExec {
     hipEvent_t conv_done_ = nullptr;
     std::thread worker_;
     std::atomic<bool> cancel_{false};
-    std::atomic<bool> conv_needed_{false};
+    std::atomic<bool> conv_needed_[3] = {false, false, false};   // stage waits for conv_done_
     std::atomic<int> published_[3];
     ck_config decoded_[3];
     bool applied_[3];

@@ -132,6 +132,27 @@ def test_cg_async_executor(ck, orc):
     Mx.close()
 
 
+@pytest.mark.parametrize("solver", ["cg", "gmres"])
+def test_async_switch_to_panel_converts_first(ck, orc, tmp_path, solver, monkeypatch):
+    """A stage-2 decision for CSR-panel is applied only after the panel-major
+    copy exists (a model whose trees are single leaves forces the decision)."""
+    from helpers import write_model
+    leaf = lambda c: dict(feature=[-1], threshold=[0.0], left=[-1], right=[-1], cls=[c])
+    path = str(tmp_path / "panel_model.txt")
+    write_model(path, [leaf(0), leaf(3), leaf(0)])     # CSR, then CSR-panel
+    monkeypatch.setenv("CK_CASCADE_MODEL", path)
+    A = M.laplacian_3d(40) if solver == "cg" else M.convection_diffusion_2d(200, 10.0)
+    xs, b = problem(orc, A, 12)
+    say(f"async {solver} forced to csr-panel n={A.n}")
+    Mx = ck.Matrix.from_csr(A)
+    fn = ck.cg_solve if solver == "cg" else ck.gmres_solve
+    x, r = run(ck, fn, Mx, b, tol=1e-10, async_=True)
+    assert r["status"] == ck.CK_OK, r
+    assert orc.relres(A, b, x) <= 1e-10
+    assert r["switch_iter"][1] >= 0 and r["final_config"] == 11, r
+    Mx.close()
+
+
 def test_cg_breakdown_budget_zero_rhs(ck, orc):
     import torch
     say("cg breakdown")

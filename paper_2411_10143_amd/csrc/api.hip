@@ -67,6 +67,7 @@ static void release(ck_matrix *M) {
     (void)hipFree(M->panel_col);
     (void)hipFree(M->panel_val);
     (void)hipFree(M->panel_val32);
+    (void)hipFree(M->merge_part);
     for (auto &kv : M->carry)
         (void)hipFree(kv.second);
     delete M;
@@ -109,9 +110,19 @@ ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s, bool sym
 ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
     if (!config_valid(c))
         return fail(CK_E_INVALID, "invalid SpMV configuration");
-    if (c.format == CK_FMT_CSR && c.algorithm != CK_ALG_PANEL)
+    if (c.format == CK_FMT_CSR && c.algorithm != CK_ALG_PANEL && c.algorithm != CK_ALG_MERGE)
         return CK_OK;
     std::lock_guard<std::mutex> lk(M.mu);
+    if (c.format == CK_FMT_CSR && c.algorithm == CK_ALG_MERGE) {
+        // the merge-path partition of the matrix, searched once instead of by
+        // every workgroup of every product
+        if (M.has_merge_part.load())
+            return CK_OK;
+        CK_TRY(dev_alloc(&M.merge_part, merge_part_entries(M)));
+        CK_TRY(launch_merge_partition(M, M.merge_part, s));
+        M.has_merge_part.store(true);
+        return CK_OK;
+    }
     if (c.format == CK_FMT_CSR) {   // CSR-panel
         if (M.has_panel.load())
             return CK_OK;

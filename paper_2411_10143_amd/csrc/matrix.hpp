@@ -35,6 +35,10 @@ struct ck_matrix {
     double *panel_val = nullptr;
     float *panel_val32 = nullptr;
     std::atomic<bool> has_panel{false};
+    // merge-path partition (after conversion to CSR-merge): merge_part[q] =
+    // rows whose end lies among the first min(2048 q, n + nnz) merged items
+    int32_t *merge_part = nullptr;
+    std::atomic<bool> has_merge_part{false};
     int64_t max_row = -1;             // longest row, once known
     ck_config active{};
     std::mutex mu;                    // guards conversions, `active` and `carry`
@@ -72,6 +76,9 @@ bool spmv_fuses_dot(const ck_config &c);
 int64_t spmv_dot_blocks(const ck_matrix &M, const ck_config &c);
 // Bytes of carry workspace a launch needs (0 if none).
 int64_t spmv_carry_bytes(const ck_matrix &M, const ck_config &c, bool fp32);
+// Merge-path partition: entries of merge_part, and its launch (stream-ordered).
+int64_t merge_part_entries(const ck_matrix &M);
+ck_status launch_merge_partition(const ck_matrix &M, int32_t *part, hipStream_t s);
 
 template <typename T>
 ck_status launch_spmv(const ck_matrix &M, const ck_config &c, const SpmvArgs<T> &a,

@@ -204,8 +204,8 @@ class AsyncExec {
         const int alg = C->tree[1].eval(in);
         t_infer += us_since(t1);
         c = stage_config(1, alg, c);
-        if (alg == CK_ALG_PANEL) {
-            // the panel-major copy must exist before the switch
+        if (alg == CK_ALG_PANEL || alg == CK_ALG_MERGE) {
+            // the panel-major copy / merge-path partition must exist first
             if (cancel_.load()) {
                 skip_rest(1);
                 return;

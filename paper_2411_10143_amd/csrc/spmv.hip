@@ -266,9 +266,30 @@ __device__ __forceinline__ void finish_carries(int *s_crow, T *s_cval, int frow,
     }
 }
 
+// part[q] = merge-path row coordinate of item min(2048 q, n + nnz): the
+// number of row ends among those first items (binary search on the row ends).
+__global__ __launch_bounds__(256) void merge_partition(int n, int nnz, int64_t Q,
+                                                       const int *__restrict__ rp,
+                                                       int *__restrict__ part) {
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= Q)
+        return;
+    const int64_t d = min<int64_t>(q * 256 * kMergeIPT, (int64_t)n + nnz);
+    int lo = (int)max<int64_t>(0, d - nnz), hi = (int)min<int64_t>(d, n);
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if ((int64_t)rp[mid + 1] <= d - mid - 1)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    part[q] = lo;
+}
+
 // Merge-path CSR.  Workgroup b owns merged items [2048 b, 2048 (b+1)) of the
-// merge of the row ends rp[1..n] with the entries 0..nnz-1.  Two threads find
-// the workgroup's start and end coordinates; the workgroup then stages the
+// merge of the row ends rp[1..n] with the entries 0..nnz-1.  Its start and
+// end coordinates come from the matrix's cached partition (built by the
+// conversion to CSR-merge), else two threads search them; it then stages the
 // row ends it crosses and the products val[j] * x[col[j]] of the entries it
 // covers in LDS with coalesced loads (eight gathers per thread in flight), and
 // every thread walks its eight items from LDS after a local merge-path search.
@@ -282,6 +303,7 @@ __global__ __launch_bounds__(256) void spmv_merge(int n, int nnz, int64_t G,
                                                   const T *__restrict__ x, T beta,
                                                   T *__restrict__ y, int *__restrict__ crow_g,
                                                   T *__restrict__ cval_g,
+                                                  const int *__restrict__ part,
                                                   const int *__restrict__ skip) {
     constexpr int ITEMS = 256 * kMergeIPT;
     __shared__ int s_crow[256];
@@ -300,16 +322,22 @@ __global__ __launch_bounds__(256) void spmv_merge(int n, int nnz, int64_t G,
     const int64_t D1 = min(D0 + ITEMS, P);
     if (tid < 2) {   // merge-path coordinates of D0 (thread 0) and D1 (thread 1)
         const int64_t d = tid == 0 ? D0 : D1;
-        int lo = (int)max<int64_t>(0, d - nnz), hi = (int)min<int64_t>(d, n);
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if ((int64_t)rp[mid + 1] <= d - mid - 1)
-                lo = mid + 1;
-            else
-                hi = mid;
+        int i;
+        if (part != nullptr) {   // the matrix's cached partition
+            i = part[b + tid];
+        } else {
+            int lo = (int)max<int64_t>(0, d - nnz), hi = (int)min<int64_t>(d, n);
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if ((int64_t)rp[mid + 1] <= d - mid - 1)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            i = lo;
         }
-        s_coord[2 * tid] = lo;
-        s_coord[2 * tid + 1] = (int)(d - lo);
+        s_coord[2 * tid] = i;
+        s_coord[2 * tid + 1] = (int)(d - i);
     }
     __syncthreads();
     const int i0 = s_coord[0], j0 = s_coord[1], i1 = s_coord[2], j1 = s_coord[3];
@@ -563,6 +591,18 @@ int64_t spmv_carry_bytes(const ck_matrix &M, const ck_config &c, bool fp32) {
     return ((G * (int64_t)sizeof(int) + 255) / 256) * 256 + G * (fp32 ? 4 : 8) + 256;
 }
 
+int64_t merge_part_entries(const ck_matrix &M) {
+    return ceil_div(M.n + M.nnz, 256 * kMergeIPT) + 1;
+}
+
+ck_status launch_merge_partition(const ck_matrix &M, int32_t *part, hipStream_t s) {
+    const int64_t Q = merge_part_entries(M);
+    hipLaunchKernelGGL(merge_partition, dim3(ceil_div(Q, 256)), dim3(256), 0, s, (int)M.n,
+                       (int)M.nnz, Q, M.rp, part);
+    CK_HIP(hipGetLastError());
+    return CK_OK;
+}
+
 ck_config default_config(int64_t n, int64_t nnz) {
     const int64_t mean = n > 0 ? nnz / n : 0;   // floor(nnz/n) has the same floor(log2)
     int L = 1;
@@ -671,7 +711,8 @@ static ck_status dispatch_carry(const ck_matrix &M, const ck_config &c, const Sp
     else
         hipLaunchKernelGGL((spmv_merge<T, BETA>), dim3(xcd_grid(G)), dim3(256), 0, s, (int)M.n,
                            (int)M.nnz, G, M.rp, M.col, values<T>(M), a.alpha, a.x, a.beta, a.y,
-                           crow, cval, a.skip);
+                           crow, cval, M.has_merge_part.load() ? M.merge_part : nullptr,
+                           a.skip);
     hipLaunchKernelGGL((carry_fixup<T>), dim3(ceil_div(G, 256)), dim3(256), 0, s, G, crow, cval,
                        a.alpha, a.y, a.skip);
     if (own)

@@ -224,6 +224,28 @@ def test_cascade_decisions_match_oracle(ck, orc, tmp_path):
         assert ck.select_stages(F, path) == orc.cascade(fitted, f15)
 
 
+def test_merge_with_and_without_cached_partition(ck, orc):
+    """CSR-merge gives the same bits whether its workgroups read the matrix's
+    cached partition (after conversion) or search their bounds themselves."""
+    import torch
+    for name in ["int_ragged", "powerlaw", "uniform", "single_row"]:
+        A = case(name)
+        say(f"merge partition {name}")
+        x = np.random.default_rng(3).uniform(-1, 1, A.ncols)
+        dx = torch.from_numpy(x).cuda()
+        cfg = ck.config_from_id(8)
+        Mx = ck.Matrix.from_csr(A)
+        y1 = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+        ck.spmv_apply(Mx.handle, dx, y1, 1.0, 0.0, cfg)        # no conversion yet: searches
+        ck.spmv_convert(Mx.handle, cfg)
+        y2 = torch.zeros_like(y1)
+        ck.spmv_apply(Mx.handle, dx, y2, 1.0, 0.0, cfg)        # cached partition
+        assert torch.equal(y1, y2), name
+        ref = orc.spmv(A, x)
+        assert np.all(np.abs(y2.cpu().numpy() - ref) <= spmv_bound(orc, A, x, 1.0, 0.0, None, U64))
+        Mx.close()
+
+
 def test_dot_deterministic_and_accurate(ck):
     import torch
     for n in [0, 1, 1000, 1 << 20, 3_000_001]:

@@ -76,6 +76,14 @@ def _declare(L):
     L.orc_csr_to_ell.restype = C.c_int
     L.orc_csr_to_coo_rows.argtypes = [_i64, _pi32, _pi32]
     L.orc_csr_to_coo_rows.restype = None
+    L.orc_dia_shape.argtypes = [_i64, _i64, _pi32, _pi32, _pi64, _pi64, _pi32]
+    L.orc_dia_shape.restype = C.c_int
+    L.orc_csr_to_dia.argtypes = [_i64, _pi32, _pi32, _pd, _i64, _i64, _pi32, _pd]
+    L.orc_csr_to_dia.restype = C.c_int
+    L.orc_hyb_width.argtypes = [_i64, _pi32]
+    L.orc_hyb_width.restype = C.c_int64
+    L.orc_hyb_tail_rows.argtypes = [_i64, _pi32, _i64, _pi32]
+    L.orc_hyb_tail_rows.restype = C.c_int64
     L.orc_tree_eval.argtypes = [_pi32, _pd, _pi32, _pi32, _pi32, _pd]
     L.orc_tree_eval.restype = C.c_int32
     L.orc_cascade.argtypes = ([_pi32, _pd, _pi32, _pi32, _pi32] * 3) + [_pd, _pi32]
@@ -183,6 +191,53 @@ def to_coo_rows(A):
     row = np.empty(int(rp[-1]), dtype=np.int32)
     lib().orc_csr_to_coo_rows(A.n, _p(rp, C.c_int32), _p(row, C.c_int32))
     return row
+
+
+def dia_shape(A):
+    """Returns (status, ndiag, pitch, offsets int32[ndiag])."""
+    rp, col, _ = _csr(A)
+    nd = C.c_int64()
+    pitch = C.c_int64()
+    lib().orc_dia_shape(A.n, A.ncols, _p(rp, C.c_int32), _p(col, C.c_int32), C.byref(nd),
+                        C.byref(pitch), None)
+    off = np.empty(max(nd.value, 1), dtype=np.int32)
+    st = lib().orc_dia_shape(A.n, A.ncols, _p(rp, C.c_int32), _p(col, C.c_int32), C.byref(nd),
+                             C.byref(pitch), _p(off, C.c_int32))
+    return st, nd.value, pitch.value, off[:nd.value]
+
+
+def to_dia(A):
+    """Returns (status, ndiag, pitch, offsets int32[ndiag], values float64[ndiag*pitch])."""
+    st, nd, pitch, off = dia_shape(A)
+    if st != OK:
+        return st, nd, pitch, off, None
+    rp, col, val = _csr(A)
+    dv = np.empty(nd * pitch, dtype=np.float64)
+    off = np.ascontiguousarray(off, dtype=np.int32)
+    lib().orc_csr_to_dia(A.n, _p(rp, C.c_int32), _p(col, C.c_int32), _p(val, C.c_double), nd,
+                         pitch, _p(off, C.c_int32), _p(dv, C.c_double))
+    return st, nd, pitch, off, dv
+
+
+def hyb_width(A):
+    rp = np.ascontiguousarray(A.rp, dtype=np.int32)
+    return int(lib().orc_hyb_width(A.n, _p(rp, C.c_int32)))
+
+
+def to_hyb(A):
+    """Returns (K, pitch, ell_col int32[K*pitch], ell_val float64[K*pitch],
+    tail_rows int32[nt]): the ELL part of width K and the rows longer than K."""
+    rp, col, val = _csr(A)
+    K = hyb_width(A)
+    pitch = (A.n + 63) // 64 * 64
+    ec = np.empty(K * pitch, dtype=np.int32)
+    ev = np.empty(K * pitch, dtype=np.float64)
+    lib().orc_csr_to_ell(A.n, _p(rp, C.c_int32), _p(col, C.c_int32), _p(val, C.c_double),
+                         K, pitch, _p(ec, C.c_int32), _p(ev, C.c_double))
+    nt = int(lib().orc_hyb_tail_rows(A.n, _p(rp, C.c_int32), K, None))
+    tr = np.empty(max(nt, 1), dtype=np.int32)
+    lib().orc_hyb_tail_rows(A.n, _p(rp, C.c_int32), K, _p(tr, C.c_int32))
+    return K, pitch, ec, ev, tr[:nt]
 
 
 def _tree_arrays(tree):

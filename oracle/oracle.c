@@ -20,9 +20,13 @@
  *                       histogram, the main-diagonal count and a symmetry flag.
  *   orc_features_derive the floating-point features of the same table,
  *                       derived only from those integers.
- *   orc_ell_shape,      CSR -> ELL and CSR -> COO conversion, the formats of
- *   orc_csr_to_ell,     the configuration space (Section III-B-2) and the
+ *   orc_ell_shape,      CSR -> ELL, COO, DIA and HYB conversion, the formats
+ *   orc_csr_to_ell,     of the configuration space (Section III-B-2) and the
  *   orc_csr_to_coo_rows conversion step of the online phase (Section III-C-1).
+ *   orc_dia_shape,
+ *   orc_csr_to_dia,
+ *   orc_hyb_width,
+ *   orc_hyb_tail_rows
  *   orc_tree_eval,      decision-tree inference and the three-stage cascade
  *   orc_cascade         (Section III-C-1, the cascaded-prediction figure).
  *   orc_cg              conjugate gradient (Hestenes-Stiefel form; Saad,
@@ -297,6 +301,90 @@ void orc_csr_to_coo_rows(int64_t n, const int32_t *rp, int32_t *row)
     for (int64_t i = 0; i < n; ++i)
         for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
             row[k] = (int32_t)i;
+}
+
+/* DIA shape (DIA is one of the formats of the configuration space, Section
+ * III-B-2): the stored diagonals are the distinct values of col - row over
+ * the stored entries, in ascending order; pitch = n rounded up to a multiple
+ * of 64.  Refused (ORC_UNSUPPORTED) when ndiag*pitch > 8*nnz, the same fill
+ * limit as ELL.  off may be NULL (shape only); otherwise it receives the
+ * ndiag offsets. */
+int orc_dia_shape(int64_t n, int64_t ncols, const int32_t *rp, const int32_t *col,
+                  int64_t *ndiag, int64_t *pitch, int32_t *off)
+{
+    /* seen[d + n - 1] marks offset d, d in [-(n-1), ncols-1] */
+    int64_t span = n + ncols - 1;
+    unsigned char *seen = (unsigned char *)calloc(span > 0 ? (size_t)span : 1, 1);
+    int64_t count = 0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
+            seen[(int64_t)col[k] - i + n - 1] = 1;
+    for (int64_t t = 0; t < span; ++t)
+        if (seen[t]) {
+            if (off)
+                off[count] = (int32_t)(t - (n - 1));
+            ++count;
+        }
+    free(seen);
+    *ndiag = count;
+    *pitch = ((n + 63) / 64) * 64;
+    if (count * (*pitch) > 8 * (int64_t)rp[n])
+        return ORC_UNSUPPORTED;
+    return ORC_OK;
+}
+
+/* DIA values: diagonal d of row i lives at d*pitch + i and holds a(i, i +
+ * off[d]) when that entry is stored; every other slot (absent entries,
+ * columns outside [0, ncols), rows n..pitch-1) holds +0.0. */
+int orc_csr_to_dia(int64_t n, const int32_t *rp, const int32_t *col, const double *val,
+                   int64_t ndiag, int64_t pitch, const int32_t *off, double *dia_val)
+{
+    for (int64_t t = 0; t < ndiag * pitch; ++t)
+        dia_val[t] = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = rp[i]; k < rp[i + 1]; ++k) {
+            int64_t d = 0;            /* find col - row among the offsets */
+            while (off[d] != (int64_t)col[k] - i)
+                ++d;
+            dia_val[d * pitch + i] = val[k];
+        }
+    return ORC_OK;
+}
+
+/* HYB width (HYB, ELL plus a remainder, is one of the formats of the
+ * configuration space, Section III-B-2; the width rule is Bell and
+ * Garland's): K = the largest k >= 0 such that at least a third of the rows
+ * have k or more entries, i.e. 3 * #{i : r_i >= k} >= n.  n = 0 gives 0. */
+int64_t orc_hyb_width(int64_t n, const int32_t *rp)
+{
+    int64_t K = 0;
+    for (int64_t k = 1;; ++k) {
+        int64_t rows = 0;
+        for (int64_t i = 0; i < n; ++i)
+            if (rp[i + 1] - rp[i] >= k)
+                ++rows;
+        if (rows == 0 || 3 * rows < n)
+            break;
+        K = k;
+    }
+    return K;
+}
+
+/* HYB layout: the ELL part is the ELL layout of width K (each row's first
+ * min(r_i, K) entries; orc_csr_to_ell with that K), and the remainder is
+ * the list of rows longer than K in ascending order (their entries K..r_i-1
+ * stay in the CSR arrays).  Returns the number of such rows; tail_rows may
+ * be NULL to count only. */
+int64_t orc_hyb_tail_rows(int64_t n, const int32_t *rp, int64_t K, int32_t *tail_rows)
+{
+    int64_t t = 0;
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] - rp[i] > K) {
+            if (tail_rows)
+                tail_rows[t] = (int32_t)i;
+            ++t;
+        }
+    return t;
 }
 
 /* ------------------------------------------------------------------------ */

@@ -12,7 +12,8 @@ from helpers import ROOT
 
 SRC = os.path.join(ROOT, "oracle", "oracle.c")
 PIN_TESTS = ["tests/test_oracle_spmv.py", "tests/test_oracle_features.py",
-             "tests/test_oracle_convert_tree.py", "tests/test_oracle_krylov.py"]
+             "tests/test_oracle_convert_tree.py", "tests/test_oracle_krylov.py",
+             "tests/test_oracle_dia_hyb.py"]
 
 MUTANTS = {
     "spmv_beta_sign": ("y[i] = alpha * s + beta * y[i];", "y[i] = alpha * s - beta * y[i];"),
@@ -27,6 +28,11 @@ MUTANTS = {
     "hist_bin_bound": ("while (bin < 15 && r >= ((int64_t)1 << bin))",
                        "while (bin < 15 && r > ((int64_t)1 << bin))"),
     "ell_pitch": ("*pitch = (n + 63) / 64 * 64;", "*pitch = (n + 31) / 32 * 32;"),
+    "dia_fill_limit": ("if (count * (*pitch) > 8 * (int64_t)rp[n])",
+                       "if (count * (*pitch) >= 8 * (int64_t)rp[n])"),
+    "dia_padding_sign": ("dia_val[t] = 0.0;", "dia_val[t] = -0.0;"),
+    "hyb_third_rule": ("if (rows == 0 || 3 * rows < n)", "if (rows == 0 || 3 * rows <= n)"),
+    "hyb_tail_bound": ("if (rp[i + 1] - rp[i] > K) {", "if (rp[i + 1] - rp[i] >= K) {"),
     "tree_strict_compare": ("if (v <= thr[t])", "if (v < thr[t])"),
     "cascade_gate": ("if (out[1] == 1)", "if (out[1] == 0)"),
     "cg_beta_inverted": ("double beta = rho_new / rho;", "double beta = rho / rho_new;"),

@@ -53,7 +53,9 @@ typedef enum {
 typedef struct ck_matrix *ck_handle;
 
 /* ---- SpMV configuration space (Section III-B-2, configuration figure) ----
- * format    : CK_FMT_CSR, CK_FMT_ELL or CK_FMT_COO
+ * format    : CK_FMT_CSR, CK_FMT_ELL, CK_FMT_COO, CK_FMT_DIA (diagonals) or
+ *             CK_FMT_HYB (ELL part plus the remainder of long rows); the
+ *             five formats Section III-B-2 names
  * algorithm : for CSR only -- CK_ALG_SCALAR (one lane per row, row block
  *             staged through LDS), CK_ALG_VECTOR (`lanes` lanes per row),
  *             CK_ALG_MERGE (merge-path load balancing), CK_ALG_PANEL (column
@@ -61,12 +63,12 @@ typedef struct ck_matrix *ck_handle;
  *             panel-major copy made by spmv_convert)
  * lanes     : for CSR-vector, 1, 2, 4, 8, 16, 32 or 64 lanes per row
  * stages_done: how many cascade stages produced this configuration (0-3)
- * Twelve configurations in all: 7 CSR-vector lane counts, CSR-scalar,
- * CSR-merge, ELL, COO, CSR-panel.  ck_config_id() numbers them 0..11 in
- * that order. */
-enum { CK_FMT_CSR = 0, CK_FMT_ELL = 1, CK_FMT_COO = 2 };
+ * Fourteen configurations in all: 7 CSR-vector lane counts, CSR-scalar,
+ * CSR-merge, ELL, COO, CSR-panel, DIA, HYB.  ck_config_id() numbers them
+ * 0..13 in that order. */
+enum { CK_FMT_CSR = 0, CK_FMT_ELL = 1, CK_FMT_COO = 2, CK_FMT_DIA = 3, CK_FMT_HYB = 4 };
 enum { CK_ALG_SCALAR = 0, CK_ALG_VECTOR = 1, CK_ALG_MERGE = 2, CK_ALG_PANEL = 3 };
-#define CK_NUM_CONFIGS 12
+#define CK_NUM_CONFIGS 14
 
 typedef struct {
     int32_t format;
@@ -173,8 +175,17 @@ ck_status ck_default_config(ck_handle h, ck_config *out);
  * value +0.0; refused with CK_E_UNSUPPORTED when K*pitch > 8*nnz.  COO: a
  * row-index array (column and value arrays are shared with CSR).  CSR-panel:
  * panel-major copy of the column and value arrays plus per-panel row
- * pointers (P*nrows + 1 int32).  Enqueued
- * on s; the copy is usable by later work on s.  Idempotent. */
+ * pointers (P*nrows + 1 int32).  DIA: the ndiag distinct offsets
+ * col - row of the stored entries (int32, ascending) and ndiag*pitch values,
+ * diagonal k of row i at k*pitch + i, +0.0 where no entry is stored
+ * (pitch = nrows rounded up to 64); refused with CK_E_UNSUPPORTED when
+ * ndiag*pitch > 8*nnz.  HYB: the ELL layout of width K = the largest k with
+ * 3*#{rows of length >= k} >= nrows (Bell and Garland's rule), plus the
+ * ascending list of rows longer than K (their entries K.. stay in the CSR
+ * arrays).  A DIA product multiplies the +0.0 of an absent slot by x like
+ * a stored value, so a non-finite x_j also reaches rows that store nothing
+ * in column j.  Enqueued on s; DIA and HYB block on s once to read a count
+ * back; the copy is usable by later work on s.  Idempotent. */
 ck_status spmv_convert(ck_handle h, const ck_config *cfg, hipStream_t s);
 
 /* ck_set_active / ck_get_active -- the configuration spmv_apply uses when
@@ -227,6 +238,19 @@ ck_status gmres_solve(ck_handle h, const double *d_b, double *d_x, const ck_solv
 ck_status ck_export_ell(ck_handle h, int32_t *d_col, double *d_val, int64_t *K,
                         int64_t *pitch, hipStream_t s);
 
+/* ck_export_dia -- after spmv_convert to DIA: *ndiag and *pitch, and (if
+ * non-NULL) the offsets into d_off int32[ndiag] and the values into d_val
+ * double[ndiag*pitch] (layout as spmv_convert describes). */
+ck_status ck_export_dia(ck_handle h, int32_t *d_off, double *d_val, int64_t *ndiag,
+                        int64_t *pitch, hipStream_t s);
+
+/* ck_export_hyb -- after spmv_convert to HYB: the width *K, *pitch, the
+ * number of long rows *ntail and the lanes per long row of the remainder
+ * pass *lanes, and (if non-NULL) the ELL part into d_col int32[K*pitch] and
+ * d_val double[K*pitch] and the long rows into d_rows int32[ntail]. */
+ck_status ck_export_hyb(ck_handle h, int32_t *d_col, double *d_val, int32_t *d_rows, int64_t *K,
+                        int64_t *pitch, int64_t *ntail, int32_t *lanes, hipStream_t s);
+
 /* ck_export_coo_rows -- copy the COO row array (after spmv_convert to COO)
  * into d_row int32[nnz]. */
 ck_status ck_export_coo_rows(ck_handle h, int32_t *d_row, hipStream_t s);
@@ -236,9 +260,10 @@ ck_status ck_export_coo_rows(ck_handle h, int32_t *d_row, hipStream_t s);
  * the device scalar d_out.  Same inputs give the same bits on every call. */
 ck_status ck_dot(int64_t n, const double *d_x, const double *d_y, double *d_out, hipStream_t s);
 
-/* ck_config_id / ck_config_from_id -- number the 12 configurations 0..11:
+/* ck_config_id / ck_config_from_id -- number the 14 configurations 0..13:
  * CSR-vector lanes 1,2,4,...,64 = 0..6, CSR-scalar = 7, CSR-merge = 8,
- * ELL = 9, COO = 10, CSR-panel = 11.  Invalid input gives -1 / CK_E_INVALID. */
+ * ELL = 9, COO = 10, CSR-panel = 11, DIA = 12, HYB = 13.  Invalid input
+ * gives -1 / CK_E_INVALID. */
 int32_t ck_config_id(const ck_config *cfg);
 ck_status ck_config_from_id(int32_t id, ck_config *out);
 

@@ -17,14 +17,15 @@ CK_OK, CK_E_INVALID, CK_E_NOMEM, CK_E_HIP = 0, -1, -2, -3
 CK_E_NOT_CONVERGED, CK_E_BREAKDOWN, CK_E_UNSUPPORTED, CK_E_CANCELLED = -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "NOT_CONVERGED",
                 -5: "BREAKDOWN", -6: "UNSUPPORTED", -7: "CANCELLED"}
-CK_FMT_CSR, CK_FMT_ELL, CK_FMT_COO = 0, 1, 2
+CK_FMT_CSR, CK_FMT_ELL, CK_FMT_COO, CK_FMT_DIA, CK_FMT_HYB = 0, 1, 2, 3, 4
 CK_ALG_SCALAR, CK_ALG_VECTOR, CK_ALG_MERGE, CK_ALG_PANEL = 0, 1, 2, 3
 CK_PREC_FP64, CK_PREC_MIXED = 0, 1
 CK_KEEP_FP32 = 1
-NUM_CONFIGS = 12
+NUM_CONFIGS = 14
 CONFIG_NAMES = ["csr-vector-1", "csr-vector-2", "csr-vector-4", "csr-vector-8",
                 "csr-vector-16", "csr-vector-32", "csr-vector-64", "csr-scalar", "csr-merge",
-                "ell", "coo", "csr-panel"]
+                "ell", "coo", "csr-panel", "dia", "hyb"]
+ID_ELL, ID_DIA = 9, 12       # the configurations whose conversion can be refused for fill
 
 
 class CkError(RuntimeError):
@@ -134,6 +135,9 @@ SIGNATURES = {
     "gmres_solve": (_i32, [_vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveResult), _vp]),
     "ck_export_ell": (_i32, [_vp, _vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp]),
     "ck_export_coo_rows": (_i32, [_vp, _vp, _vp]),
+    "ck_export_dia": (_i32, [_vp, _vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp]),
+    "ck_export_hyb": (_i32, [_vp, _vp, _vp, _vp, C.POINTER(_i64), C.POINTER(_i64),
+                             C.POINTER(_i64), C.POINTER(_i32), _vp]),
     "ck_dot": (_i32, [_i64, _vp, _vp, _vp, _vp]),
     "ck_config_id": (_i32, [C.POINTER(Config)]),
     "ck_config_from_id": (_i32, [_i32, C.POINTER(Config)]),
@@ -332,6 +336,36 @@ def export_ell(h, stream=None):
     _check(lib().ck_export_ell(h, _ptr(ec), _ptr(ev), C.byref(K), C.byref(pitch),
                                _stream(stream)))
     return K.value, pitch.value, ec, ev
+
+
+def export_dia(h, stream=None):
+    """(ndiag, pitch, offsets int32[ndiag], values float64[ndiag*pitch]) on the device."""
+    import torch
+    nd, pitch = _i64(), _i64()
+    _check(lib().ck_export_dia(h, None, None, C.byref(nd), C.byref(pitch), _stream(stream)))
+    off = torch.empty(nd.value, dtype=torch.int32, device="cuda")
+    dv = torch.empty(nd.value * pitch.value, dtype=torch.float64, device="cuda")
+    _check(lib().ck_export_dia(h, _ptr(off) if nd.value else None,
+                               _ptr(dv) if nd.value else None, C.byref(nd), C.byref(pitch),
+                               _stream(stream)))
+    return nd.value, pitch.value, off, dv
+
+
+def export_hyb(h, stream=None):
+    """(K, pitch, lanes, ell_col int32[K*pitch], ell_val float64[K*pitch],
+    long rows int32[ntail]) on the device."""
+    import torch
+    K, pitch, nt, L = _i64(), _i64(), _i64(), _i32()
+    _check(lib().ck_export_hyb(h, None, None, None, C.byref(K), C.byref(pitch), C.byref(nt),
+                               C.byref(L), _stream(stream)))
+    cnt = K.value * pitch.value
+    ec = torch.empty(cnt, dtype=torch.int32, device="cuda")
+    ev = torch.empty(cnt, dtype=torch.float64, device="cuda")
+    rows = torch.empty(nt.value, dtype=torch.int32, device="cuda")
+    _check(lib().ck_export_hyb(h, _ptr(ec) if cnt else None, _ptr(ev) if cnt else None,
+                               _ptr(rows) if nt.value else None, C.byref(K), C.byref(pitch),
+                               C.byref(nt), C.byref(L), _stream(stream)))
+    return K.value, pitch.value, L.value, ec, ev, rows
 
 
 def export_coo_rows(h, nnz, stream=None):

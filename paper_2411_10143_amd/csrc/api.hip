@@ -6,6 +6,7 @@
 #include <limits>
 
 #include "matrix.hpp"
+#include "diahyb.hpp"
 #include "panel.hpp"
 #include "predictor.hpp"
 #include "solvers.hpp"
@@ -63,6 +64,13 @@ static void release(ck_matrix *M) {
     (void)hipFree(M->ell_val);
     (void)hipFree(M->ell_val32);
     (void)hipFree(M->coo_row);
+    (void)hipFree(M->dia_off);
+    (void)hipFree(M->dia_val);
+    (void)hipFree(M->dia_val32);
+    (void)hipFree(M->hyb_col);
+    (void)hipFree(M->hyb_val);
+    (void)hipFree(M->hyb_val32);
+    (void)hipFree(M->hyb_rows);
     (void)hipFree(M->panel_rp);
     (void)hipFree(M->panel_col);
     (void)hipFree(M->panel_val);
@@ -106,7 +114,8 @@ ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s, bool sym
     return CK_OK;
 }
 
-// Builds the ELL or COO copy a configuration needs (idempotent).
+// Builds the ELL, COO, DIA, HYB or CSR-panel copy (or the merge-path
+// partition) a configuration needs (idempotent).
 ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
     if (!config_valid(c))
         return fail(CK_E_INVALID, "invalid SpMV configuration");
@@ -147,6 +156,42 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
         M.panel_W = W;
         M.panel_L = kPanelLanes;
         M.has_panel.store(true);
+        return CK_OK;
+    }
+    if (c.format == CK_FMT_DIA) {
+        if (M.has_dia.load())
+            return CK_OK;
+        const ck_status st = convert_to_dia(M, s);
+        if (st != CK_OK) {   // refused for fill, or out of memory: leave no partial copy
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(M.dia_off);
+            (void)hipFree(M.dia_val);
+            (void)hipFree(M.dia_val32);
+            M.dia_off = nullptr;
+            M.dia_val = nullptr;
+            M.dia_val32 = nullptr;
+            return st;
+        }
+        M.has_dia.store(true);
+        return CK_OK;
+    }
+    if (c.format == CK_FMT_HYB) {
+        if (M.has_hyb.load())
+            return CK_OK;
+        const ck_status st = convert_to_hyb(M, s);
+        if (st != CK_OK) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(M.hyb_col);
+            (void)hipFree(M.hyb_val);
+            (void)hipFree(M.hyb_val32);
+            (void)hipFree(M.hyb_rows);
+            M.hyb_col = nullptr;
+            M.hyb_val = nullptr;
+            M.hyb_val32 = nullptr;
+            M.hyb_rows = nullptr;
+            return st;
+        }
+        M.has_hyb.store(true);
         return CK_OK;
     }
     if (c.format == CK_FMT_COO) {
@@ -201,6 +246,10 @@ int32_t ck_config_id(const ck_config *c) {
         return 9;
     if (c->format == CK_FMT_COO)
         return 10;
+    if (c->format == CK_FMT_DIA)
+        return 12;
+    if (c->format == CK_FMT_HYB)
+        return 13;
     if (c->algorithm == CK_ALG_SCALAR)
         return 7;
     if (c->algorithm == CK_ALG_MERGE)
@@ -218,6 +267,10 @@ ck_status ck_config_from_id(int32_t id, ck_config *out) {
         return fail(CK_E_INVALID, "configuration id must be in [0, %d]", CK_NUM_CONFIGS - 1);
     if (id == 11) {
         *out = ck_config{CK_FMT_CSR, CK_ALG_PANEL, 0, 0};
+        return CK_OK;
+    }
+    if (id == 12 || id == 13) {
+        *out = ck_config{id == 12 ? CK_FMT_DIA : CK_FMT_HYB, 0, 0, 0};
         return CK_OK;
     }
     if (id <= 6)
@@ -367,7 +420,9 @@ ck_status ck_set_active(ck_handle h, const ck_config *cfg) {
     if (!h || !cfg || !config_valid(*cfg))
         return fail(CK_E_INVALID, "bad configuration");
     if ((cfg->format == CK_FMT_ELL && !h->has_ell.load()) ||
-        (cfg->format == CK_FMT_COO && !h->has_coo.load()))
+        (cfg->format == CK_FMT_COO && !h->has_coo.load()) ||
+        (cfg->format == CK_FMT_DIA && !h->has_dia.load()) ||
+        (cfg->format == CK_FMT_HYB && !h->has_hyb.load()))
         return fail(CK_E_INVALID, "format not converted yet");
     std::lock_guard<std::mutex> lk(h->mu);
     h->active = *cfg;
@@ -451,6 +506,44 @@ ck_status ck_export_ell(ck_handle h, int32_t *d_col, double *d_val, int64_t *K, 
         CK_HIP(hipMemcpyAsync(d_col, h->ell_col, cnt * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     if (d_val && cnt)
         CK_HIP(hipMemcpyAsync(d_val, h->ell_val, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return CK_OK;
+}
+
+ck_status ck_export_dia(ck_handle h, int32_t *d_off, double *d_val, int64_t *ndiag,
+                        int64_t *pitch, hipStream_t s) {
+    if (!h || !ndiag || !pitch)
+        return fail(CK_E_INVALID, "NULL argument");
+    if (!h->has_dia.load())
+        return fail(CK_E_INVALID, "matrix has no DIA copy");
+    *ndiag = h->dia_nd;
+    *pitch = h->dia_pitch;
+    if (d_off && h->dia_nd > 0)
+        CK_HIP(hipMemcpyAsync(d_off, h->dia_off, h->dia_nd * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, s));
+    if (d_val && h->dia_nd > 0)
+        CK_HIP(hipMemcpyAsync(d_val, h->dia_val, h->dia_nd * h->dia_pitch * sizeof(double),
+                              hipMemcpyDeviceToDevice, s));
+    return CK_OK;
+}
+
+ck_status ck_export_hyb(ck_handle h, int32_t *d_col, double *d_val, int32_t *d_rows, int64_t *K,
+                        int64_t *pitch, int64_t *ntail, int32_t *lanes, hipStream_t s) {
+    if (!h || !K || !pitch || !ntail || !lanes)
+        return fail(CK_E_INVALID, "NULL argument");
+    if (!h->has_hyb.load())
+        return fail(CK_E_INVALID, "matrix has no HYB copy");
+    *K = h->hyb_K;
+    *pitch = h->hyb_pitch;
+    *ntail = h->hyb_nt;
+    *lanes = h->hyb_L;
+    const size_t cnt = (size_t)(h->hyb_K * h->hyb_pitch);
+    if (d_col && cnt)
+        CK_HIP(hipMemcpyAsync(d_col, h->hyb_col, cnt * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    if (d_val && cnt)
+        CK_HIP(hipMemcpyAsync(d_val, h->hyb_val, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (d_rows && h->hyb_nt > 0)
+        CK_HIP(hipMemcpyAsync(d_rows, h->hyb_rows, h->hyb_nt * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, s));
     return CK_OK;
 }
 

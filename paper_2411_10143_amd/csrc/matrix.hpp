@@ -39,6 +39,23 @@ struct ck_matrix {
     // rows whose end lies among the first min(2048 q, n + nnz) merged items
     int32_t *merge_part = nullptr;
     std::atomic<bool> has_merge_part{false};
+    // DIA (after conversion): dia_nd offsets (col - row, ascending), values
+    // diagonal-major: diagonal k of row i at k*dia_pitch + i, absent = +0.0
+    int32_t *dia_off = nullptr;
+    double *dia_val = nullptr;
+    float *dia_val32 = nullptr;
+    int64_t dia_nd = 0, dia_pitch = 0;
+    std::atomic<bool> has_dia{false};
+    // HYB (after conversion): ELL part of width hyb_K (layout as ELL) and the
+    // hyb_nt rows longer than hyb_K, ascending; their entries hyb_K.. stay in
+    // the CSR arrays and are summed with hyb_L lanes per row
+    int32_t *hyb_col = nullptr;
+    double *hyb_val = nullptr;
+    float *hyb_val32 = nullptr;
+    int32_t *hyb_rows = nullptr;
+    int64_t hyb_K = 0, hyb_pitch = 0, hyb_nt = 0;
+    int hyb_L = 1;
+    std::atomic<bool> has_hyb{false};
     int64_t max_row = -1;             // longest row, once known
     ck_config active{};
     std::mutex mu;                    // guards conversions, `active` and `carry`

@@ -10,6 +10,9 @@ constexpr int kPanelLanes = 4;   // lanes per panel row (panel rows are short)
 // panels for a vector of ncols entries of value_bytes each (x slice <= 2 MB)
 int panel_count_for(int64_t ncols, int value_bytes);
 int64_t panel_scan_tmp_elems(int64_t N);
+// Exclusive scan of N ints into N + 1 outputs (out[N] = total); tmp holds
+// panel_scan_tmp_elems(N) ints.
+ck_status launch_scan_exclusive(int64_t N, const int *in, int *out, int *tmp, hipStream_t s);
 ck_status launch_to_panel(const ck_matrix &M, int P, int64_t W, int *cnt, int *tmp, int *prp,
                           int *pcol, double *pval, float *pval32, hipStream_t s);
 // partial sums go to ypart (P * n values); G_dot = dot partials for a fused CG step

@@ -90,16 +90,21 @@ bool parse_model(const std::string &path, Cascade &out, std::string &err) {
     }
     fclose(f);
     if (ok) {
+        // classes per stage: format 0..4, CSR algorithm 0..3, log2(lanes) 0..6
+        static const int kClasses[3] = {5, 4, 7};
         for (int t = 0; t < 3 && ok; ++t) {
             const Tree &T = out.tree[t];
             const int nn = (int)T.feature.size();
             if (nn == 0)
                 ok = false;
-            for (int i = 0; i < nn && ok; ++i)
+            for (int i = 0; i < nn && ok; ++i) {
                 if (T.feature[i] >= 0 &&
                     (T.feature[i] >= kNumModelFeatures || T.left[i] <= i || T.right[i] <= i ||
                      T.left[i] >= nn || T.right[i] >= nn))
                     ok = false;   // children come after parents: the walk ends
+                if (T.feature[i] < 0 && (T.cls[i] < 0 || T.cls[i] >= kClasses[t]))
+                    ok = false;   // a leaf names a class the stage does not have
+            }
         }
     }
     if (!ok)

@@ -111,6 +111,10 @@ int64_t handle_bytes(const ck_matrix &M) {
         b += M.ell_K * M.ell_pitch * (12 + (M.ell_val32 ? 4 : 0));
     if (M.has_coo.load())
         b += 4 * M.nnz;
+    if (M.has_dia.load())
+        b += 4 * M.dia_nd + M.dia_nd * M.dia_pitch * (8 + (M.dia_val32 ? 4 : 0));
+    if (M.has_hyb.load())
+        b += 4 * M.hyb_nt + M.hyb_K * M.hyb_pitch * (12 + (M.hyb_val32 ? 4 : 0));
     if (M.has_panel.load())
         b += 4 * ((int64_t)M.panel_P * M.n + 1) + M.nnz * (12 + (M.panel_val32 ? 4 : 0));
     return b;

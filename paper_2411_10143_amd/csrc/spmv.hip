@@ -17,12 +17,14 @@
 //   spmv_ell            column-major ELLPACK, one lane per row.
 //   spmv_coo            row-sorted triples, equal entry shares per thread,
 //                       the same carry scheme as merge-path.
+//   spmv_dia, HYB       diahyb.hip (HYB's ELL part is spmv_hyb_ell below).
 //
 // Matrix arrays are streamed with non-temporal loads so the cache keeps the
 // gathered vector; row blocks are mapped so that each XCD works on one
 // contiguous slice of rows (its L2 then holds the x entries that slice uses).
 // Every reduction has a fixed order, so a configuration always returns the
 // same bits for the same input.
+#include "diahyb.hpp"
 #include "matrix.hpp"
 #include "panel.hpp"
 
@@ -174,14 +176,11 @@ __global__ __launch_bounds__(256) void spmv_csr_scalar(int n, int64_t G,
 }
 
 template <typename T, bool BETA, bool DOT>
-__global__ __launch_bounds__(256) void spmv_ell(int n, int64_t G, int K, int64_t pitch,
-                                                const int *__restrict__ ecol,
-                                                const T *__restrict__ evl, T alpha,
-                                                const T *__restrict__ x, T beta,
-                                                T *__restrict__ y, const int *__restrict__ skip,
-                                                ck::CgDev<T> *cg, T *__restrict__ partials) {
-    if (skipped(skip))
-        return;
+__device__ __forceinline__ void ell_rows(int n, int64_t G, int K, int64_t pitch,
+                                         const int *__restrict__ ecol,
+                                         const T *__restrict__ evl, T alpha,
+                                         const T *__restrict__ x, T beta, T *__restrict__ y,
+                                         ck::CgDev<T> *cg, T *__restrict__ partials) {
     const int64_t b = ck::xcd_block(G);
     if (b < 0)
         return;
@@ -224,6 +223,31 @@ __global__ __launch_bounds__(256) void spmv_ell(int n, int64_t G, int K, int64_t
         }
     }
     cg_sigma_epilogue<T, DOT>(mine, cg, partials, b, G);
+}
+
+template <typename T, bool BETA, bool DOT>
+__global__ __launch_bounds__(256) void spmv_ell(int n, int64_t G, int K, int64_t pitch,
+                                                const int *__restrict__ ecol,
+                                                const T *__restrict__ evl, T alpha,
+                                                const T *__restrict__ x, T beta,
+                                                T *__restrict__ y, const int *__restrict__ skip,
+                                                ck::CgDev<T> *cg, T *__restrict__ partials) {
+    if (skipped(skip))
+        return;
+    ell_rows<T, BETA, DOT>(n, G, K, pitch, ecol, evl, alpha, x, beta, y, cg, partials);
+}
+
+// The ELL part of a HYB product (its own symbol, so profiles tell it apart).
+template <typename T, bool BETA>
+__global__ __launch_bounds__(256) void spmv_hyb_ell(int n, int64_t G, int K, int64_t pitch,
+                                                    const int *__restrict__ ecol,
+                                                    const T *__restrict__ evl, T alpha,
+                                                    const T *__restrict__ x, T beta,
+                                                    T *__restrict__ y,
+                                                    const int *__restrict__ skip) {
+    if (skipped(skip))
+        return;
+    ell_rows<T, BETA, false>(n, G, K, pitch, ecol, evl, alpha, x, beta, y, nullptr, nullptr);
 }
 
 // ---- carry completion shared by merge-path and COO -------------------------
@@ -544,7 +568,8 @@ __global__ __launch_bounds__(256) void scale_rows(int64_t n, T beta, T *__restri
 namespace ck {
 
 bool config_valid(const ck_config &c) {
-    if (c.format == CK_FMT_ELL || c.format == CK_FMT_COO)
+    if (c.format == CK_FMT_ELL || c.format == CK_FMT_COO || c.format == CK_FMT_DIA ||
+        c.format == CK_FMT_HYB)
         return true;
     if (c.format != CK_FMT_CSR)
         return false;
@@ -557,7 +582,7 @@ bool config_valid(const ck_config &c) {
 }
 
 bool spmv_fuses_dot(const ck_config &c) {
-    return c.format == CK_FMT_ELL ||
+    return c.format == CK_FMT_ELL || c.format == CK_FMT_DIA ||
            (c.format == CK_FMT_CSR && (c.algorithm == CK_ALG_VECTOR ||
                                        c.algorithm == CK_ALG_SCALAR ||
                                        c.algorithm == CK_ALG_PANEL));
@@ -626,6 +651,10 @@ const char *kernel_name(const ck_config &c, bool fp32) {
         "spmv_csr_vector<64, float, false, false>"};
     if (c.format == CK_FMT_ELL)
         return fp32 ? "spmv_ell<float, false, false>" : "spmv_ell<double, false, false>";
+    if (c.format == CK_FMT_DIA)
+        return fp32 ? "spmv_dia<float, false, false>" : "spmv_dia<double, false, false>";
+    if (c.format == CK_FMT_HYB)
+        return fp32 ? "spmv_hyb_ell<float, false>" : "spmv_hyb_ell<double, false>";
     if (c.format == CK_FMT_COO)
         return fp32 ? "spmv_coo<float, false>" : "spmv_coo<double, false>";
     if (c.algorithm == CK_ALG_SCALAR)
@@ -656,6 +685,22 @@ static const T *ell_values(const ck_matrix &M) {
         return M.ell_val;
 }
 
+template <typename T>
+static const T *dia_values(const ck_matrix &M) {
+    if constexpr (sizeof(T) == 4)
+        return M.dia_val32;
+    else
+        return M.dia_val;
+}
+
+template <typename T>
+static const T *hyb_values(const ck_matrix &M) {
+    if constexpr (sizeof(T) == 4)
+        return M.hyb_val32;
+    else
+        return M.hyb_val;
+}
+
 template <int L, typename T, bool BETA, bool DOT>
 static void go_vector(const ck_matrix &M, int64_t G, const SpmvArgs<T> &a, hipStream_t s) {
     hipLaunchKernelGGL((spmv_csr_vector<L, T, BETA, DOT>), dim3(xcd_grid(G)), dim3(256), 0, s,
@@ -667,6 +712,19 @@ template <typename T, bool BETA, bool DOT>
 static ck_status dispatch_rows(const ck_matrix &M, const ck_config &c, const SpmvArgs<T> &a,
                                hipStream_t s) {
     const int64_t G = std::min<int64_t>(std::max<int64_t>(row_groups(M, c), 1), kRowBlocks);
+    if (c.format == CK_FMT_DIA) {
+        launch_dia_spmv<T, BETA, DOT>(M, G, dia_values<T>(M), a, s);
+        return CK_OK;
+    }
+    if (c.format == CK_FMT_HYB) {   // ELL part for every row, then the long rows' remainder
+        if constexpr (DOT)
+            return fail(CK_E_INVALID, "HYB does not fuse the CG dot product");
+        hipLaunchKernelGGL((spmv_hyb_ell<T, BETA>), dim3(xcd_grid(G)), dim3(256), 0, s,
+                           (int)M.n, G, (int)M.hyb_K, M.hyb_pitch, M.hyb_col, hyb_values<T>(M),
+                           a.alpha, a.x, a.beta, a.y, a.skip);
+        launch_hyb_tail<T>(M, values<T>(M), a, s);
+        return CK_OK;
+    }
     if (c.format == CK_FMT_ELL) {
         hipLaunchKernelGGL((spmv_ell<T, BETA, DOT>), dim3(xcd_grid(G)), dim3(256), 0, s,
                            (int)M.n, G, (int)M.ell_K, M.ell_pitch, M.ell_col, ell_values<T>(M),
@@ -733,6 +791,10 @@ ck_status launch_spmv(const ck_matrix &M, const ck_config &c, const SpmvArgs<T> 
         return fail(CK_E_INVALID, "ELL requested but the matrix has not been converted");
     if (c.format == CK_FMT_COO && !M.has_coo.load())
         return fail(CK_E_INVALID, "COO requested but the matrix has not been converted");
+    if (c.format == CK_FMT_DIA && !M.has_dia.load())
+        return fail(CK_E_INVALID, "DIA requested but the matrix has not been converted");
+    if (c.format == CK_FMT_HYB && !M.has_hyb.load())
+        return fail(CK_E_INVALID, "HYB requested but the matrix has not been converted");
     const bool panel = c.format == CK_FMT_CSR && c.algorithm == CK_ALG_PANEL;
     if (panel && !M.has_panel.load())
         return fail(CK_E_INVALID, "CSR-panel requested but the matrix has not been converted");

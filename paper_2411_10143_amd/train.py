@@ -4,7 +4,8 @@ decision tree per stage and export the trees as the library's model file.
 
   collect : features (GPU kernels) + mean time of every configuration (the
             library's event-timed loop of back-to-back products) per matrix
-  label   : stage 1 = format of the fastest configuration overall;
+  label   : stage 1 = format of the fastest configuration overall (CSR,
+            ELL, COO, DIA or HYB);
             stage 2 = fastest CSR algorithm (vector at its best lane count,
             scalar, merge-path); stage 3 = fastest lane count.  Ties go to
             the lower configuration index.  With a perfect classifier the
@@ -32,8 +33,9 @@ import numpy as np
 
 FEATURES = ["nrows", "ncols", "nnz", "density", "mean", "sd", "cov", "max", "min", "maxavg",
             "distavg", "clusteravg", "fill", "ndiag", "diagfill"]
-CONFIGS = 12
+CONFIGS = 14
 CSR_IDS = (0, 1, 2, 3, 4, 5, 6, 7, 8, 11)   # configurations stored in CSR (incl. CSR-panel)
+FORMAT_OF = {9: 1, 10: 2, 12: 3, 13: 4}     # ELL, COO, DIA, HYB; every other id is CSR
 
 
 def reps_for(us_probe: float, budget_us: float = 4000.0, lo: int = 20, hi: int = 200) -> int:
@@ -41,7 +43,7 @@ def reps_for(us_probe: float, budget_us: float = 4000.0, lo: int = 20, hi: int =
 
 
 def time_all_configs(ck, Mx, x, y, warmup=10, reps=None):
-    """Mean us per product for each of the 11 configurations (inf if refused)."""
+    """Mean us per product for each of the 14 configurations (inf if refused)."""
     out = []
     for cid in range(CONFIGS):
         cfg = ck.config_from_id(cid)
@@ -60,19 +62,28 @@ def time_all_configs(ck, Mx, x, y, warmup=10, reps=None):
     return out
 
 
-def labels(times):
+def _first_within(t, tie):
+    """Index of the first time within a factor (1 + tie) of the smallest."""
+    t = np.asarray(t, dtype=np.float64)
+    return int(np.nonzero(t <= t.min() * (1.0 + tie))[0][0])
+
+
+def labels(times, tie=0.0):
     """(format, algorithm, log2 lanes) labels from the configuration times
     (ids: 0-6 CSR-vector lanes 1..64, 7 scalar, 8 merge, 9 ELL, 10 COO,
-    11 CSR-panel; a time of inf marks a refused conversion)."""
+    11 CSR-panel, 12 DIA, 13 HYB; a time of inf marks a refused conversion).
+    Times within a factor (1 + tie) of the fastest count as ties, and ties go
+    to the lower configuration index (so HYB without a remainder, which runs
+    the ELL kernel, is labelled ELL)."""
     t = np.full(CONFIGS, np.inf)
     t[:len(times)] = np.asarray(times, dtype=np.float64)
-    best = int(np.argmin(t))          # argmin takes the first (lowest index) on ties
-    fmt = 1 if best == 9 else (2 if best == 10 else 0)
-    lanes = int(np.argmin(t[:7]))
+    best = _first_within(t, tie)
+    fmt = FORMAT_OF.get(best, 0)
+    lanes = _first_within(t[:7], tie)
     # candidates in configuration-index order: vector at its best lanes (id
-    # 0..6), scalar (7), merge (8), panel (11); argmin keeps the first on ties
-    cand = [(t[lanes], 1), (t[7], 0), (t[8], 2), (t[11], 3)]
-    alg = cand[int(np.argmin([c[0] for c in cand]))][1]
+    # 0..6), scalar (7), merge (8), panel (11)
+    cand = [(t[int(np.argmin(t[:7]))], 1), (t[7], 0), (t[8], 2), (t[11], 3)]
+    alg = cand[_first_within([c[0] for c in cand], tie)][1]
     return fmt, alg, lanes
 
 
@@ -126,11 +137,11 @@ def load(path):
     return np.array(X), np.array(T), names
 
 
-def fit_trees(X, T, max_depth=8, min_leaf=2, seed=0):
+def fit_trees(X, T, max_depth=8, min_leaf=2, seed=0, tie=0.0):
     """Three classifiers; stage-2/3 trees are trained on every matrix (the
     labels are defined for all of them), as the cascade may reach them."""
     from sklearn.tree import DecisionTreeClassifier
-    Y = np.array([labels(t) for t in T])
+    Y = np.array([labels(t, tie) for t in T])
     # inputs as the library evaluates them: rounded to float32
     X32 = X.astype(np.float32)
     trees = []
@@ -166,10 +177,8 @@ def cascade_predict(trees, x):
     """Configuration id the cascade picks for one feature row (sklearn side)."""
     x = np.asarray(x, dtype=np.float32)[None, :]
     fmt = int(trees[0].predict(x)[0])
-    if fmt == 1:
-        return 9
-    if fmt == 2:
-        return 10
+    if fmt != 0:
+        return {1: 9, 2: 10, 3: 12, 4: 13}[fmt]
     alg = int(trees[1].predict(x)[0])
     if alg == 0:
         return 7
@@ -192,7 +201,9 @@ def main(argv=None):
     fa.add_argument("--data", required=True, nargs="+")
     fa.add_argument("--model", required=True)
     fa.add_argument("--max-depth", type=int, default=6)
-    fa.add_argument("--min-leaf", type=int, default=1)
+    fa.add_argument("--min-leaf", type=int, default=2)
+    fa.add_argument("--tie", type=float, default=0.04,
+                    help="times within this fraction of the fastest count as ties")
     a = p.parse_args(argv)
     if a.cmd == "collect":
         collect(a.out, a.count, a.seed, a.reps)
@@ -203,7 +214,7 @@ def main(argv=None):
             Xs.append(X)
             Ts.append(T)
         X, T = np.concatenate(Xs), np.concatenate(Ts)
-        trees, Y = fit_trees(X, T, a.max_depth, a.min_leaf)
+        trees, Y = fit_trees(X, T, a.max_depth, a.min_leaf, tie=a.tie)
         picks = np.array([cascade_predict(trees, x) for x in X])
         slow = T[np.arange(len(T)), picks] / T.min(axis=1)
         note = (f"{len(X)} training matrices; training-set geomean t_pred/t_best = "

@@ -3,10 +3,11 @@ configurations the bench times:
 
 * every matrix of the 48-matrix SpMV set (n = 1e4 .. 2e6): integer features
   and derived features bit-exact, the cascade's decision equal to the
-  oracle's, and every one of the 12 SpMV configurations element by element
+  oracle's, and every one of the 14 SpMV configurations element by element
   against the oracle's FP64 product (the oracle computes the whole product in
   well under a second);
-* ELL and COO conversions byte-exact on the largest member of each family;
+* ELL, COO, DIA and HYB conversions byte-exact on the largest member of each
+  family;
 * CG on the 3D Poisson 128^3 and 2^20-row graph Laplacian systems (async
   executor) and GMRES(30) on convection-diffusion 1024^2, FP64 and mixed,
   checked by the oracle's true FP64 residual.
@@ -49,15 +50,17 @@ def test_spmv_set_member(ck, orc, spec):
     x = np.random.default_rng(spec[4]).uniform(-1, 1, A.ncols)
     ref = orc.spmv(A, x)
     bound = spmv_bound(orc, A, x, 1.0, 0.0, None, U64)
+    bound_hyb = spmv_bound(orc, A, x, 1.0, 0.0, None, U64, k_extra=4)
     normA = float(np.max(orc.spmv(M.CSR(A.n, A.ncols, A.rp, A.col, np.abs(A.val)),
                                   np.ones(A.ncols))))
     dx = torch.from_numpy(x).cuda()
     dy = torch.empty(A.n, dtype=torch.float64, device="cuda")
-    ell_ok = orc.ell_shape(A)[0] == orc.OK
+    refused = {ck.ID_ELL: orc.ell_shape(A)[0] != orc.OK,
+               ck.ID_DIA: orc.dia_shape(A)[0] != orc.OK}
     for cid in range(ck.NUM_CONFIGS):
         cfg = ck.config_from_id(cid)
         say(f"  config {ck.CONFIG_NAMES[cid]}")
-        if cid == 9 and not ell_ok:
+        if refused.get(cid, False):
             with pytest.raises(ck.CkError) as e:
                 ck.spmv_convert(Mx.handle, cfg)
             assert e.value.status == ck.CK_E_UNSUPPORTED
@@ -67,7 +70,8 @@ def test_spmv_set_member(ck, orc, spec):
         ck.spmv_apply(Mx.handle, dx, dy, 1.0, 0.0, cfg)
         got = dy.cpu().numpy()
         err = np.abs(got - ref)
-        assert np.all(err <= bound), (A.name, cid, float(np.max(err - bound)))
+        assert np.all(err <= (bound_hyb if cid == 13 else bound)), \
+            (A.name, cid, float(np.max(err - bound)))
         assert float(np.max(err)) <= 1e-13 * normA * float(np.max(np.abs(x)))
     Mx.close()
 
@@ -92,6 +96,19 @@ def test_conversions_largest(ck, orc, spec):
     else:
         with pytest.raises(ck.CkError):
             ck.spmv_convert(Mx.handle, ck.config_from_id(9))
+    st, nd, pitch, off, dv = orc.to_dia(A)
+    if st == orc.OK:
+        ck.spmv_convert(Mx.handle, ck.config_from_id(ck.ID_DIA))
+        gnd, gp, goff, gdv = ck.export_dia(Mx.handle)
+        assert (gnd, gp) == (nd, pitch) and np.array_equal(goff.cpu().numpy(), off)
+        assert np.array_equal(gdv.cpu().numpy().view(np.uint64), dv.view(np.uint64))
+        del gdv
+    K, pitch, ec, ev, tr = orc.to_hyb(A)
+    ck.spmv_convert(Mx.handle, ck.config_from_id(13))
+    gK, gp, lanes, gc, gv, gtr = ck.export_hyb(Mx.handle)
+    assert (gK, gp) == (K, pitch) and np.array_equal(gtr.cpu().numpy(), tr)
+    assert np.array_equal(gc.cpu().numpy(), ec)
+    assert np.array_equal(gv.cpu().numpy().view(np.uint64), ev.view(np.uint64))
     Mx.close()
 
 

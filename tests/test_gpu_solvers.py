@@ -94,7 +94,7 @@ def test_cg_above_single_workgroup_limit(ck, orc):
     Mx.close()
 
 
-@pytest.mark.parametrize("cid", range(12))
+@pytest.mark.parametrize("cid", range(14))
 def test_cg_every_config(ck, orc, cid):
     A = M.laplacian_2d(40)
     xs, b = problem(orc, A, 2)
@@ -187,7 +187,7 @@ def test_gmres_convdiff_fp64(ck, orc):
     Mx.close()
 
 
-@pytest.mark.parametrize("cid", range(12))
+@pytest.mark.parametrize("cid", range(14))
 def test_gmres_every_config(ck, orc, cid):
     A = M.convection_diffusion_2d(24, 10.0)
     xs, b = problem(orc, A, 5)

@@ -60,11 +60,12 @@ def test_spmv_all_configs_fp64(ck, orc, name):
     y0 = rng.integers(-8, 9, A.n).astype(float) if integer else rng.uniform(-1, 1, A.n)
     Mx = ck.Matrix.from_csr(A)
     dx = torch.from_numpy(x).cuda()
-    st_ell = orc.ell_shape(A)[0]
+    refused = {ck.ID_ELL: orc.ell_shape(A)[0] != orc.OK,
+               ck.ID_DIA: orc.dia_shape(A)[0] != orc.OK}
     for cid in range(ck.NUM_CONFIGS):
         cfg = ck.config_from_id(cid)
         say(f"spmv {name} n={A.n} nnz={A.nnz} config={ck.CONFIG_NAMES[cid]}")
-        if cid == 9 and st_ell != orc.OK:
+        if refused.get(cid, False):
             with pytest.raises(ck.CkError) as e:
                 ck.spmv_convert(Mx.handle, cfg)
             assert e.value.status == ck.CK_E_UNSUPPORTED
@@ -80,7 +81,10 @@ def test_spmv_all_configs_fp64(ck, orc, name):
             if integer:
                 assert np.array_equal(got, ref), (name, cid, alpha, beta)
             else:
-                bound = spmv_bound(orc, A, x, alpha, beta, y0, U64)
+                # HYB rounds the ELL part and the remainder separately (two
+                # more roundings than one sequential row sum)
+                bound = spmv_bound(orc, A, x, alpha, beta, y0, U64,
+                                   k_extra=4 if cid == 13 else 2)
                 assert np.all(np.abs(got - ref) <= bound), (name, cid, alpha, beta)
                 normA = np.max(orc.spmv(M.CSR(A.n, A.ncols, A.rp, A.col, np.abs(A.val)),
                                         np.ones(A.ncols)), initial=0.0)
@@ -115,7 +119,8 @@ def test_spmv_all_configs_fp32(ck, orc, name):
         try:
             ck.spmv_convert(Mx.handle, cfg)
         except ck.CkError as e:
-            assert cid == 9 and e.status == ck.CK_E_UNSUPPORTED
+            assert cid in (ck.ID_ELL, ck.ID_DIA) and e.status == ck.CK_E_UNSUPPORTED
+            assert (orc.ell_shape(A) if cid == ck.ID_ELL else orc.dia_shape(A))[0] != orc.OK
             continue
         dy = torch.from_numpy(y32).cuda()
         ck.spmv_apply_f32(Mx.handle, dx, dy, -0.5, 2.0, cfg)
@@ -125,8 +130,44 @@ def test_spmv_all_configs_fp32(ck, orc, name):
             assert np.array_equal(got, ref)
         else:
             bound = spmv_bound(orc, A32, x32.astype(np.float64), -0.5, 2.0,
-                               y32.astype(np.float64), U32, k_extra=3)
+                               y32.astype(np.float64), U32, k_extra=5 if cid == 13 else 3)
             assert np.all(np.abs(got - ref) <= bound), (name, cid)
+    Mx.close()
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_dia_and_hyb_layouts_bit_exact(ck, orc, name):
+    """DIA offsets and values, HYB width, ELL part and long-row list equal the
+    oracle's conversions bit for bit (values compared as raw bits, so the sign
+    of a zero counts)."""
+    A = case(name)
+    say(f"dia/hyb layout {name} n={A.n} nnz={A.nnz}")
+    Mx = ck.Matrix.from_csr(A)
+    st, nd, pitch, off, dv = orc.to_dia(A)
+    if st != orc.OK:
+        with pytest.raises(ck.CkError) as e:
+            ck.spmv_convert(Mx.handle, ck.config_from_id(ck.ID_DIA))
+        assert e.value.status == ck.CK_E_UNSUPPORTED
+    else:
+        ck.spmv_convert(Mx.handle, ck.config_from_id(ck.ID_DIA))
+        gnd, gpitch, goff, gdv = ck.export_dia(Mx.handle)
+        assert (gnd, gpitch) == (nd, pitch)
+        assert np.array_equal(goff.cpu().numpy(), off)
+        assert np.array_equal(gdv.cpu().numpy().view(np.uint64), dv.view(np.uint64))
+    K, pitch, ec, ev, tr = orc.to_hyb(A)
+    ck.spmv_convert(Mx.handle, ck.config_from_id(13))
+    gK, gpitch, lanes, gec, gev, gtr = ck.export_hyb(Mx.handle)
+    assert (gK, gpitch) == (K, pitch)
+    assert np.array_equal(gec.cpu().numpy(), ec)
+    assert np.array_equal(gev.cpu().numpy().view(np.uint64), ev.view(np.uint64))
+    assert np.array_equal(gtr.cpu().numpy(), tr)
+    r = np.diff(A.rp.astype(np.int64))
+    tail = int(np.sum(r[tr] - K)) if tr.shape[0] else 0
+    mean = tail // tr.shape[0] if tr.shape[0] else 0
+    expect_lanes = 1
+    while expect_lanes * 2 <= mean and expect_lanes < 64:
+        expect_lanes *= 2
+    assert lanes == expect_lanes
     Mx.close()
 
 

@@ -25,14 +25,21 @@ def test_labels_rule_and_ties():
     # CSR-panel (id 11) fastest: a CSR format label and algorithm class 3
     t = [9, 8, 7, 6, 5, 4, 4, 5, 3.0, 8, 2.0, 1.0]
     assert train.labels(t) == (0, 3, 5)
+    # DIA (id 12) and HYB (id 13) fastest: format classes 3 and 4
+    t = [9, 8, 7, 6, 5, 4, 4, 5, 3.0, 8, 2.0, 1.5, 1.0, 1.2]
+    assert train.labels(t) == (3, 3, 5)
+    t = [9, 8, 7, 6, 5, 4, 4, 5, 3.0, 8, 2.0, 1.5, inf, 1.0]
+    assert train.labels(t) == (4, 3, 5)
 
 
 def test_export_round_trip_matches_sklearn(orc, tmp_path):
     rng = np.random.default_rng(0)
     X = np.exp(rng.normal(0, 2, size=(300, 15)))
-    T = rng.uniform(1, 10, size=(300, 11))
+    T = rng.uniform(1, 10, size=(300, 14))
     T[X[:, 4] > 3, 9] = 0.5          # make ELL win on part of the data
     T[X[:, 6] > 5, 8] = 0.4          # merge on another part
+    T[X[:, 2] > 20, 12] = 0.3        # DIA and HYB on others
+    T[X[:, 9] < 0.05, 13] = 0.2
     trees, Y = train.fit_trees(X, T, max_depth=6)
     path = tmp_path / "model.txt"
     train.export(trees, str(path))
@@ -41,10 +48,8 @@ def test_export_round_trip_matches_sklearn(orc, tmp_path):
     for x in Xt:
         stages = orc.cascade(parsed, x)
         cid = train.cascade_predict(trees, x)
-        if stages[0] == 1:
-            assert cid == 9
-        elif stages[0] == 2:
-            assert cid == 10
+        if stages[0] != 0:
+            assert cid == {1: 9, 2: 10, 3: 12, 4: 13}[stages[0]]
         elif stages[1] == 0:
             assert cid == 7
         elif stages[1] == 2:
@@ -64,6 +69,6 @@ def test_shipped_model_is_well_formed():
             if t["feature"][i] >= 0:
                 assert 0 <= t["feature"][i] < 15
                 assert i < t["left"][i] < n and i < t["right"][i] < n
-    assert {c for c in trees[0]["cls"] if c >= 0} <= {0, 1, 2}
+    assert {c for c in trees[0]["cls"] if c >= 0} <= {0, 1, 2, 3, 4}
     assert {c for c in trees[1]["cls"] if c >= 0} <= {0, 1, 2, 3}
     assert {c for c in trees[2]["cls"] if c >= 0} <= set(range(7))

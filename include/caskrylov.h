@@ -99,6 +99,18 @@ typedef struct {
 
 /* ---- Solver options and results ---- */
 enum { CK_PREC_FP64 = 0, CK_PREC_MIXED = 1 };
+/* Execution modes (ck_solve_opts.async; ignored when use_config = 1):
+ *   CK_EXEC_DEFAULT    the whole solve on the default configuration;
+ *   CK_EXEC_ASYNC      start on the default configuration while features,
+ *                      inference and conversion run on a side stream, and
+ *                      swap each stage's choice in at the next iteration
+ *                      boundary (Section III-C-2);
+ *   CK_EXEC_SEQUENTIAL features, cascade and conversion first, then the
+ *                      whole solve on the prediction (the sequential form
+ *                      the asynchronous one is compared with, Section IV);
+ *                      their times count in t_total_us and switch_iter[t]
+ *                      = 0 for every stage that took effect. */
+enum { CK_EXEC_DEFAULT = 0, CK_EXEC_ASYNC = 1, CK_EXEC_SEQUENTIAL = 2 };
 
 typedef struct {
     double tol;            /* stop when ||b - A x||_2 / ||b||_2 <= tol        */
@@ -106,8 +118,8 @@ typedef struct {
     int32_t restart;       /* GMRES restart length m (<= 64); CG ignores it   */
     int32_t precision;     /* CK_PREC_FP64 or CK_PREC_MIXED (FP32 inner solve
                               + FP64 refinement; needs CK_KEEP_FP32)          */
-    int32_t async;         /* 1: start on the default configuration and swap
-                              in the cascade's choices mid-solve              */
+    int32_t async;         /* CK_EXEC_DEFAULT, CK_EXEC_ASYNC or
+                              CK_EXEC_SEQUENTIAL (see below)                  */
     int32_t check_every;   /* iterations between host convergence polls       */
     int32_t use_config;    /* 1: run every SpMV with `config` (async ignored) */
     ck_config config;
@@ -163,6 +175,13 @@ ck_status spmv_select(const ck_features *f, const char *model_path, ck_config *o
  * stage[0] format, stage[1] algorithm (-1 if not run), stage[2] log2(lanes)
  * (-1 if not run). */
 ck_status ck_select_stages(const ck_features *f, const char *model_path, int32_t stage[3]);
+
+/* ck_eval_stage -- one stage's tree alone, without the cascade's gating
+ * (stage 0 format, 1 CSR algorithm, 2 log2(lanes)); *cls = its class.  For
+ * single-stage ablations of the cascade (Section IV compares predicting one
+ * part of the configuration with predicting all three). */
+ck_status ck_eval_stage(const ck_features *f, const char *model_path, int32_t stage,
+                        int32_t *cls);
 
 /* ck_default_config -- the configuration a solve starts from before any
  * prediction: CSR-vector with lanes = clamp(2^floor(log2(max(1, nnz/nrows))),

@@ -20,6 +20,7 @@ STATUS_NAMES = {0: "OK", -1: "INVALID", -2: "NOMEM", -3: "HIP", -4: "NOT_CONVERG
 CK_FMT_CSR, CK_FMT_ELL, CK_FMT_COO, CK_FMT_DIA, CK_FMT_HYB = 0, 1, 2, 3, 4
 CK_ALG_SCALAR, CK_ALG_VECTOR, CK_ALG_MERGE, CK_ALG_PANEL = 0, 1, 2, 3
 CK_PREC_FP64, CK_PREC_MIXED = 0, 1
+CK_EXEC_DEFAULT, CK_EXEC_ASYNC, CK_EXEC_SEQUENTIAL = 0, 1, 2
 CK_KEEP_FP32 = 1
 NUM_CONFIGS = 14
 CONFIG_NAMES = ["csr-vector-1", "csr-vector-2", "csr-vector-4", "csr-vector-8",
@@ -59,6 +60,22 @@ class Features(C.Structure):
     def derived(self):
         return [self.density, self.mean, self.sd, self.cov, self.maxavg, self.distavg,
                 self.clusteravg, self.fill, self.diagfill]
+
+    @classmethod
+    def from_model_inputs(cls, f15):
+        """A record whose 15 model inputs are f15 (feature-table order); the
+        other accumulators stay 0.  For host-only use of the cascade."""
+        F = cls()
+        ints = {0: "nrows", 1: "ncols", 2: "nnz", 7: "max_r", 8: "min_r", 13: "ndiag"}
+        dbls = {3: "density", 4: "mean", 5: "sd", 6: "cov", 9: "maxavg", 10: "distavg",
+                11: "clusteravg", 12: "fill", 14: "diagfill"}
+        for i, v in enumerate(f15):
+            if i in ints:
+                assert float(v) == int(v), "integer feature expected"
+                setattr(F, ints[i], int(v))
+            else:
+                setattr(F, dbls[i], float(v))
+        return F
 
     def model_inputs(self):
         return [float(self.nrows), float(self.ncols), float(self.nnz), self.density, self.mean,
@@ -135,6 +152,7 @@ SIGNATURES = {
     "gmres_solve": (_i32, [_vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveResult), _vp]),
     "ck_export_ell": (_i32, [_vp, _vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp]),
     "ck_export_coo_rows": (_i32, [_vp, _vp, _vp]),
+    "ck_eval_stage": (_i32, [C.POINTER(Features), C.c_char_p, _i32, C.POINTER(_i32)]),
     "ck_export_dia": (_i32, [_vp, _vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp]),
     "ck_export_hyb": (_i32, [_vp, _vp, _vp, _vp, C.POINTER(_i64), C.POINTER(_i64),
                              C.POINTER(_i64), C.POINTER(_i32), _vp]),
@@ -252,6 +270,14 @@ def select_stages(features, model_path=None):
     mp = model_path.encode() if model_path else None
     _check(lib().ck_select_stages(C.byref(features), mp, st))
     return list(st)
+
+
+def eval_stage(features, stage, model_path=None):
+    """Class of one stage's tree alone (no cascade gating)."""
+    cls = _i32()
+    mp = model_path.encode() if model_path else None
+    _check(lib().ck_eval_stage(C.byref(features), mp, int(stage), C.byref(cls)))
+    return cls.value
 
 
 def default_config(h):

@@ -386,8 +386,22 @@ ck_status ck_select_stages(const ck_features *f, const char *model_path, int32_t
         if (stage[1] == CK_ALG_VECTOR)
             stage[2] = C->tree[2].eval(in);
     }
-    if (stage[0] < 0 || stage[0] > 2 || stage[1] > 3 || stage[2] > 6)
+    if (stage[0] < 0 || stage[0] > CK_FMT_HYB || stage[1] > CK_ALG_PANEL || stage[2] > 6)
         return fail(CK_E_INVALID, "cascade model produced an unknown class");
+    return CK_OK;
+}
+
+ck_status ck_eval_stage(const ck_features *f, const char *model_path, int32_t stage,
+                        int32_t *cls) {
+    if (!f || !cls || stage < 0 || stage > 2)
+        return fail(CK_E_INVALID, "bad arguments");
+    std::string err;
+    const Cascade *C = load_cascade(model_path, err);
+    if (!C)
+        return fail(CK_E_INVALID, "%s", err.c_str());
+    double in[kNumModelFeatures];
+    model_inputs(*f, in);
+    *cls = C->tree[stage].eval(in);
     return CK_OK;
 }
 

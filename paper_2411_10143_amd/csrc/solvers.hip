@@ -662,6 +662,44 @@ ck_status small_solve(SolveCtx &c, const double *b, double *x, bool cg, int m) {
                 hs.relres);
 }
 
+// Sequential execution (the form the asynchronous executor is measured
+// against, Section IV): features, the three cascade stages and the format
+// conversion all finish before the first iteration, which then runs on the
+// prediction.  A refused or failed conversion keeps the default
+// configuration (its stages stay unapplied, switch_iter -1).
+ck_status sequential_predict(SolveCtx &c) {
+    auto t0 = Clock::now();
+    ck_features F;
+    CK_TRY(compute_features(c.M, F, c.s, false));
+    c.res.t_features_us = us_since(t0);
+    std::string err;
+    const Cascade *C = load_cascade(nullptr, err);
+    if (!C)
+        return fail(CK_E_INVALID, "%s", err.c_str());
+    double in[kNumModelFeatures];
+    model_inputs(F, in);
+    auto t1 = Clock::now();
+    ck_config cfg = c.cfg;
+    int stages = 0;
+    for (int t = 0; t < 3; ++t) {
+        const int cls = C->tree[t].eval(in);
+        cfg = stage_config(t, cls, cfg);
+        stages = t + 1;
+        if ((t == 0 && cls != CK_FMT_CSR) || (t == 1 && cls != CK_ALG_VECTOR))
+            break;
+    }
+    c.res.t_infer_us = us_since(t1);
+    auto t2 = Clock::now();
+    if (convert_format(c.M, cfg, c.s) == CK_OK) {
+        CK_HIP(hipStreamSynchronize(c.s));
+        c.cfg = cfg;
+        for (int t = 0; t < stages; ++t)
+            c.res.switch_iter[t] = 0;
+    }
+    c.res.t_convert_us = us_since(t2);
+    return CK_OK;
+}
+
 ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *opts,
                 ck_solve_result *res, hipStream_t s, Solver which) {
     if (!hnd || !opts || !res || (hnd->n > 0 && (!b || !x)))
@@ -673,6 +711,8 @@ ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *
         return fail(CK_E_INVALID, "tol must be >= 0");
     if (opts->precision == CK_PREC_MIXED && !M.val32)
         return fail(CK_E_INVALID, "mixed precision needs a handle created with CK_KEEP_FP32");
+    if (opts->async < CK_EXEC_DEFAULT || opts->async > CK_EXEC_SEQUENTIAL)
+        return fail(CK_E_INVALID, "async must be CK_EXEC_DEFAULT, _ASYNC or _SEQUENTIAL");
     std::memset(res, 0, sizeof *res);
     res->switch_iter[0] = res->switch_iter[1] = res->switch_iter[2] = -1;
     const auto t0 = Clock::now();
@@ -688,9 +728,12 @@ ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *
         res->final_config = c.cfg;
         return CK_OK;
     }
+    const bool run_async = opts->async == CK_EXEC_ASYNC && !opts->use_config;
+    if (opts->async == CK_EXEC_SEQUENTIAL && !opts->use_config)
+        CK_TRY(sequential_predict(c));
     const int m = opts->restart > 0 ? opts->restart : 30;
     if (M.n <= kWgCgMaxN && which == Solver::CG && opts->precision == CK_PREC_FP64 &&
-        !opts->async && !opts->use_config) {
+        opts->async == CK_EXEC_DEFAULT && !opts->use_config) {
         // the whole solve in one single-workgroup launch; its product takes
         // one lane per row
         const ck_status st = wg_cg_solve(c, b, x);
@@ -700,7 +743,7 @@ ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *
         return st;
     }
     const bool vector_cfg = c.cfg.format == CK_FMT_CSR && c.cfg.algorithm == CK_ALG_VECTOR;
-    if (M.n <= kSmallN && !opts->async && vector_cfg && (which == Solver::CG || m <= kBMaxM)) {
+    if (M.n <= kSmallN && !run_async && vector_cfg && (which == Solver::CG || m <= kBMaxM)) {
         const ck_status st = small_solve(c, b, x, which == Solver::CG, m);
         res->final_config = c.cfg;
         res->status = st;
@@ -716,7 +759,7 @@ ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *
     CK_TRY(ws.get(&cbuf, carry));
     c.carry = cbuf;
     AsyncExec *exec = nullptr;
-    if (opts->async && !opts->use_config) {
+    if (run_async) {
         exec = new AsyncExec(M, c.cfg);
         ck_status e = exec->start();
         if (e != CK_OK) {

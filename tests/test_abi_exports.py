@@ -56,3 +56,29 @@ def test_host_only_calls_work_without_gpu():
     f.nrows, f.ncols, f.nnz = 100, 100, 500
     c = ck.spmv_select(f)
     assert c.format in (0, 1, 2) and 1 <= c.stages_done <= 3
+
+
+def test_library_cascade_equals_oracle_on_training_features(orc):
+    """The library's host-side cascade (spmv_select / ck_select_stages /
+    ck_eval_stage) against the oracle's tree walk over the shipped model, on
+    the 600 feature rows of the shipped training timings (every format class
+    the model can output)."""
+    ensure_built()
+    import csv
+    import paper_2411_10143_amd as ck
+    from helpers import MODEL, parse_model
+    from paper_2411_10143_amd import train
+    trees = parse_model(MODEL)
+    path = os.path.join(ROOT, "paper_2411_10143_amd", "training", "mi355x_spmv_timings.csv")
+    seen = set()
+    for row in csv.DictReader(open(path)):
+        f15 = [float(row[k]) for k in train.FEATURES]
+        F = ck.Features.from_model_inputs(f15)
+        want = orc.cascade(trees, f15)
+        assert ck.select_stages(F) == want, row["name"]
+        assert [ck.eval_stage(F, t) for t in range(3)] == \
+            [orc.tree_eval(trees[t], f15) for t in range(3)]
+        c = ck.spmv_select(F)
+        assert c.format == want[0] and c.stages_done == sum(1 for v in want if v >= 0)
+        seen.add(want[0])
+    assert {0, 1, 3} <= seen, seen

@@ -258,3 +258,48 @@ def test_gmres_async(ck, orc):
     assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10
     assert r["switch_iter"][0] >= 0
     Mx.close()
+
+
+SEQ_CASES = {
+    "cg_lap3d_40": ("cg", lambda: M.laplacian_3d(40)),
+    "cg_graph_20000": ("cg", lambda: M.graph_laplacian_chung_lu(20000, 21)),
+    "gmres_convdiff_120": ("gmres", lambda: M.convection_diffusion_2d(120, 10.0)),
+    "gmres_powerlaw_dd": ("gmres", lambda: M.diagonally_dominant(M.power_law_rows(30000, 2.0, 8))),
+}
+
+
+@pytest.mark.parametrize("name", list(SEQ_CASES))
+def test_sequential_mode_solves_on_the_prediction(ck, orc, name):
+    """Sequential execution: the cascade's configuration (or the default when
+    its conversion is refused) runs from iteration 0; every stage that took
+    effect reports switch iteration 0."""
+    solver, make = SEQ_CASES[name]
+    A = make()
+    xs, b = problem(orc, A, 11)
+    say(f"sequential {name} n={A.n} nnz={A.nnz}")
+    Mx = ck.Matrix.from_csr(A)
+    stages = ck.select_stages(ck.spmv_features(Mx.handle))
+    want = ck.spmv_select(ck.spmv_features(Mx.handle))
+    if stages[0] in (ck.CK_FMT_ELL, ck.CK_FMT_DIA) and \
+            (orc.ell_shape(A) if stages[0] == ck.CK_FMT_ELL else orc.dia_shape(A))[0] != orc.OK:
+        want, ran = ck.default_config(Mx.handle), 0
+    else:
+        ran = sum(1 for v in stages if v >= 0)
+    fn = ck.cg_solve if solver == "cg" else ck.gmres_solve
+    x, r = run(ck, fn, Mx, b, tol=1e-10, async_=ck.CK_EXEC_SEQUENTIAL)
+    assert r["status"] == ck.CK_OK, r
+    assert orc.relres(A, b, x) <= 1e-10
+    assert r["final_config"] == ck.config_id(want)
+    assert list(r["switch_iter"]) == [0] * ran + [-1] * (3 - ran), (r["switch_iter"], stages)
+    assert r["t_features_us"] > 0
+    Mx.close()
+
+
+def test_invalid_execution_mode_rejected(ck, orc):
+    A = M.laplacian_2d(8)
+    xs, b = problem(orc, A, 1)
+    Mx = ck.Matrix.from_csr(A)
+    with pytest.raises(ck.CkError) as e:
+        run(ck, ck.cg_solve, Mx, b, tol=1e-10, async_=3, raise_on_error=True)
+    assert e.value.status == ck.CK_E_INVALID
+    Mx.close()

@@ -426,13 +426,17 @@ def bench_cg_async(args):
         b = _rhs(ck, probe, xs)
         best_id, _ = _best_fixed_config(ck, probe, A)
         probe.close()
-        res = {"async": [], "sequential": [], "default": [], "best_fixed": []}
+        res = {"async": [], "async_overhead_aware": [], "sequential": [], "default": [],
+               "best_fixed": []}
         for s in range(args.warmup + args.steps):
             for mode in res:
                 Mx = ck.Matrix(rp, col, val)        # fresh handle: nothing cached
                 kw = {}
                 if mode == "async":
                     kw["async_"] = ck.CK_EXEC_ASYNC
+                elif mode == "async_overhead_aware":
+                    kw["async_"] = ck.CK_EXEC_ASYNC
+                    kw["overhead_aware"] = True
                 elif mode == "sequential":
                     kw["async_"] = ck.CK_EXEC_SEQUENTIAL
                 elif mode == "best_fixed":
@@ -458,6 +462,8 @@ def bench_cg_async(args):
         tot_bytes += sum(r["iterations"] for r in a) * _cg_iter_bytes(A)
         rows.append({"problem": name, "n": A.n, "nnz": A.nnz,
                      "async_solves_per_s": round(len(a) / t_async, 3),
+                     "async_overhead_aware_solves_per_s": round(len(res["async_overhead_aware"]) / sum(r["wall_s"] for r in res["async_overhead_aware"]), 3),
+                     "overhead_gate": {k: res["async_overhead_aware"][-1][k] for k in ("conversion_gated", "est_remaining_iters", "switch_iter")},
                      "sequential_solves_per_s": round(len(res["sequential"]) / sum(r["wall_s"] for r in res["sequential"]), 3),
                      "sequential_prep_us": round(sum(res["sequential"][-1][k] for k in ("t_features_us", "t_infer_us", "t_convert_us")), 1),
                      "default_solves_per_s": round(len(res["default"]) / sum(r["wall_s"] for r in res["default"]), 3),

@@ -111,6 +111,15 @@ enum { CK_PREC_FP64 = 0, CK_PREC_MIXED = 1 };
  *                      their times count in t_total_us and switch_iter[t]
  *                      = 0 for every stage that took effect. */
 enum { CK_EXEC_DEFAULT = 0, CK_EXEC_ASYNC = 1, CK_EXEC_SEQUENTIAL = 2 };
+/* Overhead-aware conversion (ck_solve_opts.overhead_aware = 1 with
+ * CK_EXEC_ASYNC in FP64; the overhead-conscious selection discussed among
+ * the paper's related work): a decision that needs a new copy of the matrix
+ * (ELL, COO, DIA, HYB, CSR-panel) waits for the solver's residual reports
+ * of the first few iterations, extrapolates the remaining iterations R from
+ * the residual's geometric decay, and is converted only if 0.25 * R is at
+ * least the conversion's cost in products (its modelled bytes over one
+ * product's bytes, plus 2); otherwise the solve keeps its configuration
+ * (conversion_gated = 1 in the result). */
 
 typedef struct {
     double tol;            /* stop when ||b - A x||_2 / ||b||_2 <= tol        */
@@ -123,6 +132,10 @@ typedef struct {
     int32_t check_every;   /* iterations between host convergence polls       */
     int32_t use_config;    /* 1: run every SpMV with `config` (async ignored) */
     ck_config config;
+    int32_t overhead_aware; /* CK_EXEC_ASYNC, FP64 only: convert a decision's
+                              format only if the remaining iterations,
+                              extrapolated from the residual's decay, can
+                              repay the conversion (see below)              */
 } ck_solve_opts;
 
 typedef struct {
@@ -134,6 +147,9 @@ typedef struct {
     double true_relres;      /* ||b - A x||/||b|| recomputed in FP64 at exit  */
     double t_features_us, t_infer_us, t_convert_us, t_total_us;
     ck_config final_config;
+    int32_t conversion_gated;    /* overhead-aware gate: -1 not consulted,
+                                    0 converted, 1 conversion skipped        */
+    int32_t est_remaining_iters; /* the gate's estimate (-1 if none)         */
 } ck_solve_result;
 
 /* Flags for spmv_create */
@@ -256,6 +272,18 @@ ck_status gmres_solve(ck_handle h, const double *d_b, double *d_x, const ck_solv
  * buffers only *K and *pitch are returned. */
 ck_status ck_export_ell(ck_handle h, int32_t *d_col, double *d_val, int64_t *K,
                         int64_t *pitch, hipStream_t s);
+
+/* ck_overhead_gate -- the overhead-aware conversion rule on host values
+ * (host only; the asynchronous executor applies the same rule): from two
+ * residual reports (iteration t0, relative residual r0) and (t1, r1),
+ * t0 < t1, *remaining = (t1 - t0) * ln(tol / r1) / ln(r1 / r0), the
+ * iterations a geometric decay needs from r1 down to tol (0 if r1 <= tol,
+ * 1e9 if the residual did not decrease); *cost = the modelled bytes of the
+ * conversion to `target` over one product's bytes, plus 2 (features f give
+ * the sizes); *convert = 1 iff 0.25 * remaining >= cost. */
+ck_status ck_overhead_gate(const ck_features *f, const ck_config *target, int32_t t0, double r0,
+                           int32_t t1, double r1, double tol, double *remaining, double *cost,
+                           int32_t *convert);
 
 /* ck_export_dia -- after spmv_convert to DIA: *ndiag and *pitch, and (if
  * non-NULL) the offsets into d_off int32[ndiag] and the values into d_val

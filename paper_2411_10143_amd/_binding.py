@@ -86,7 +86,7 @@ class Features(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32),
                 ("precision", C.c_int32), ("async_", C.c_int32), ("check_every", C.c_int32),
-                ("use_config", C.c_int32), ("config", Config)]
+                ("use_config", C.c_int32), ("config", Config), ("overhead_aware", C.c_int32)]
 
 
 class SolveResult(C.Structure):
@@ -94,14 +94,17 @@ class SolveResult(C.Structure):
                 ("switch_iter", C.c_int32 * 3), ("outer_steps", C.c_int32),
                 ("true_relres", C.c_double), ("t_features_us", C.c_double),
                 ("t_infer_us", C.c_double), ("t_convert_us", C.c_double),
-                ("t_total_us", C.c_double), ("final_config", Config)]
+                ("t_total_us", C.c_double), ("final_config", Config),
+                ("conversion_gated", C.c_int32), ("est_remaining_iters", C.c_int32)]
 
     def as_dict(self):
         return dict(status=self.status, iterations=self.iterations,
                     switch_iter=list(self.switch_iter), outer_steps=self.outer_steps,
                     true_relres=self.true_relres, t_features_us=self.t_features_us,
                     t_infer_us=self.t_infer_us, t_convert_us=self.t_convert_us,
-                    t_total_us=self.t_total_us, final_config=config_id(self.final_config))
+                    t_total_us=self.t_total_us, final_config=config_id(self.final_config),
+                    conversion_gated=self.conversion_gated,
+                    est_remaining_iters=self.est_remaining_iters)
 
 
 class ServerOpts(C.Structure):
@@ -153,6 +156,8 @@ SIGNATURES = {
     "ck_export_ell": (_i32, [_vp, _vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp]),
     "ck_export_coo_rows": (_i32, [_vp, _vp, _vp]),
     "ck_eval_stage": (_i32, [C.POINTER(Features), C.c_char_p, _i32, C.POINTER(_i32)]),
+    "ck_overhead_gate": (_i32, [C.POINTER(Features), C.POINTER(Config), _i32, _dbl, _i32, _dbl,
+                                _dbl, C.POINTER(_dbl), C.POINTER(_dbl), C.POINTER(_i32)]),
     "ck_export_dia": (_i32, [_vp, _vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp]),
     "ck_export_hyb": (_i32, [_vp, _vp, _vp, _vp, C.POINTER(_i64), C.POINTER(_i64),
                              C.POINTER(_i64), C.POINTER(_i32), _vp]),
@@ -280,6 +285,16 @@ def eval_stage(features, stage, model_path=None):
     return cls.value
 
 
+def overhead_gate(features, target, t0, r0, t1, r1, tol):
+    """(remaining iterations, conversion cost in products, convert?) of the
+    overhead-aware conversion rule."""
+    rem, cost, go = _dbl(), _dbl(), _i32()
+    _check(lib().ck_overhead_gate(C.byref(features), C.byref(target), int(t0), float(r0),
+                                  int(t1), float(r1), float(tol), C.byref(rem), C.byref(cost),
+                                  C.byref(go)))
+    return rem.value, cost.value, bool(go.value)
+
+
 def default_config(h):
     c = Config()
     _check(lib().ck_default_config(h, C.byref(c)))
@@ -314,8 +329,9 @@ def spmv_apply_f32(h, x, y, alpha=1.0, beta=0.0, cfg=None, stream=None):
                                 _stream(stream)))
 
 
-def _opts(tol, max_iter, restart, precision, async_, check_every, cfg):
+def _opts(tol, max_iter, restart, precision, async_, check_every, cfg, overhead_aware=False):
     o = SolveOpts()
+    o.overhead_aware = int(overhead_aware)
     o.tol = tol
     o.max_iter = max_iter
     o.restart = restart
@@ -329,9 +345,9 @@ def _opts(tol, max_iter, restart, precision, async_, check_every, cfg):
 
 
 def _solve(fn, h, b, x, tol, max_iter, restart, precision, async_, check_every, cfg, stream,
-           raise_on_error):
+           raise_on_error, overhead_aware=False):
     import torch
-    o = _opts(tol, max_iter, restart, precision, async_, check_every, cfg)
+    o = _opts(tol, max_iter, restart, precision, async_, check_every, cfg, overhead_aware)
     r = SolveResult()
     st = fn(h, _ptr(b, torch.float64), _ptr(x, torch.float64), C.byref(o), C.byref(r),
             _stream(stream))
@@ -341,16 +357,19 @@ def _solve(fn, h, b, x, tol, max_iter, restart, precision, async_, check_every, 
 
 
 def cg_solve(h, b, x, tol=1e-10, max_iter=100000, precision=CK_PREC_FP64, async_=False,
-             check_every=8, config=None, stream=None, raise_on_error=False):
-    """x holds x0 on entry and the solution on return; returns the result record."""
+             check_every=8, config=None, stream=None, raise_on_error=False,
+             overhead_aware=False):
+    """x holds x0 on entry and the solution on return; returns the result record.
+    async_: CK_EXEC_DEFAULT/False, CK_EXEC_ASYNC/True or CK_EXEC_SEQUENTIAL."""
     return _solve(lib().cg_solve, h, b, x, tol, max_iter, 0, precision, async_, check_every,
-                  config, stream, raise_on_error)
+                  config, stream, raise_on_error, overhead_aware)
 
 
 def gmres_solve(h, b, x, tol=1e-10, max_iter=100000, restart=30, precision=CK_PREC_FP64,
-                async_=False, check_every=8, config=None, stream=None, raise_on_error=False):
+                async_=False, check_every=8, config=None, stream=None, raise_on_error=False,
+                overhead_aware=False):
     return _solve(lib().gmres_solve, h, b, x, tol, max_iter, restart, precision, async_,
-                  check_every, config, stream, raise_on_error)
+                  check_every, config, stream, raise_on_error, overhead_aware)
 
 
 def export_ell(h, stream=None):

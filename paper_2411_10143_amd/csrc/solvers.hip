@@ -15,8 +15,12 @@
 #include <cstring>
 #include <thread>
 
+#include <mutex>
+#include <vector>
+
 #include "batched.hpp"
 #include "matrix.hpp"
+#include "panel.hpp"
 #include "predictor.hpp"
 #include "solvers.hpp"
 
@@ -78,9 +82,56 @@ thread_local Pinned tl_pinned;
 // stream) and publishes each stage's configuration as soon as it is known.
 // The solver calls poll() at every iteration boundary and adopts a published
 // configuration once its conversion (if any) has completed.
+//
+// Overhead-aware conversion (opt-in, after the overhead-conscious selection
+// the paper discusses among related work): before a decision that needs a
+// new copy of the matrix is converted, the worker waits for the solver's
+// first residual reports, extrapolates the remaining iterations R from the
+// residual's geometric decay and converts only if R * kGain >= C, where C
+// is the conversion's cost in products of the matrix (its bytes over one
+// product's bytes, plus two for launches and the host read-back) and kGain
+// the fraction of a product each remaining iteration is assumed to save.
+constexpr double kGain = 0.25;
+constexpr int kGateMinIter = 4;
+
+}  // namespace
+
+// Bytes a conversion to `c` moves, in products of the CSR matrix (+2).
+double conversion_products(const ck_features &F, const ck_config &c) {
+    const double n = (double)F.nrows, nnz = (double)F.nnz;
+    const double pitch = (double)ceil_div(F.nrows, 64) * 64;
+    const double product = 12.0 * nnz + 20.0 * n + 4.0;
+    double b = 0;
+    if (c.format == CK_FMT_ELL)
+        b = 4 * n + 12 * nnz + 12 * (double)F.max_r * pitch;
+    else if (c.format == CK_FMT_COO)
+        b = 4 * n + 4 * nnz;
+    else if (c.format == CK_FMT_DIA)   // mark, three scan levels, zero-fill + scatter
+        b = 8 * nnz + 16 * (n + (double)F.ncols) * 3 + 16 * (double)F.ndiag * pitch + 12 * nnz;
+    else if (c.format == CK_FMT_HYB)   // histogram, ELL part (<= 3 nnz slots), long-row list
+        b = 4 * n + 12 * nnz + 36 * nnz + 16 * n;
+    else if (c.algorithm == CK_ALG_PANEL)
+        b = 16.0 * panel_count_for(F.ncols, 8) * n + 24 * nnz;
+    return b / product + 2.0;
+}
+
+// Remaining iterations extrapolated from two residual reports (t0, r0) and
+// (t1, r1), t0 < t1, assuming the decay from r0 to r1 continues
+// geometrically down to tol; 1e9 when the residual has not decreased.
+double remaining_iterations(int t0, double r0, int t1, double r1, double tol) {
+    if (!(r1 > 0.0) || r1 <= tol)
+        return 0.0;
+    if (!(r1 < r0) || !(tol > 0.0) || t1 <= t0)
+        return 1e9;
+    return std::min(1e9, (t1 - t0) * std::log(tol / r1) / std::log(r1 / r0));
+}
+
+namespace {
+
 class AsyncExec {
   public:
-    AsyncExec(ck_matrix &M, const ck_config &start) : M_(M), current_(start) {
+    AsyncExec(ck_matrix &M, const ck_config &start, bool gate)
+        : M_(M), current_(start), gate_(gate) {
         for (int t = 0; t < 3; ++t) {
             published_[t].store(-1);
             applied_[t] = false;
@@ -123,6 +174,21 @@ class AsyncExec {
     // true while a stage decision has not been applied yet
     bool pending() const { return !(applied_[0] && applied_[1] && applied_[2]); }
 
+    // The solver's residual reports (iterations done, relative residual, its
+    // tolerance), for the overhead-aware gate.
+    void progress(int iter, double relres, double tol) {
+        if (!gate_ || iter <= 0 || !(relres > 0.0))
+            return;
+        std::lock_guard<std::mutex> lk(prog_mu_);
+        if (first_iter_ < 0) {
+            first_iter_ = iter;
+            first_relres_ = relres;
+        }
+        last_iter_ = iter;
+        last_relres_ = relres;
+        tol_ = tol;
+    }
+
     void finish() {
         cancel_.store(true);
         if (worker_.joinable())
@@ -140,6 +206,8 @@ class AsyncExec {
 
     double t_features = 0, t_infer = 0, t_convert = 0;
     int conversion_failed = 0;
+    int gate_decision = -1;      // -1 not asked, 0 converted, 1 skipped
+    int est_remaining = -1;      // the gate's estimate of the remaining iterations
 
   private:
     static constexpr int kNoStage = 1000;
@@ -152,6 +220,40 @@ class AsyncExec {
     void skip_rest(int from) {
         for (int t = from; t < 3; ++t)
             published_[t].store(kNoStage, std::memory_order_release);
+    }
+
+    // Overhead-aware gate: true = convert.  Waits (until cancelled) for a
+    // residual report at least kGateMinIter iterations after the first.
+    bool worth_converting(const ck_features &F, const ck_config &c) {
+        if (!gate_)
+            return true;
+        const double C = conversion_products(F, c);
+        while (!cancel_.load()) {
+            int i0, i1;
+            double r0, r1, tol;
+            {
+                std::lock_guard<std::mutex> lk(prog_mu_);
+                i0 = first_iter_;
+                i1 = last_iter_;
+                r0 = first_relres_;
+                r1 = last_relres_;
+                tol = tol_;
+            }
+            // the first report serves as the reference when it comes after
+            // iteration 0 (x0 = 0 gives relres 1 at iteration 0)
+            const int t = i1 >= 0 ? i1 : -1;
+            if (t >= kGateMinIter) {
+                const double r_ref = (i0 >= 0 && i0 < i1) ? r0 : 1.0;
+                const int t_ref = (i0 >= 0 && i0 < i1) ? i0 : 0;
+                const double R = remaining_iterations(t_ref, r_ref, t, r1, tol);
+                est_remaining = (int)R;
+                const bool go = R * kGain >= C;
+                gate_decision = go ? 0 : 1;
+                return go;
+            }
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+        }
+        return false;
     }
 
     void run() {
@@ -176,7 +278,7 @@ class AsyncExec {
         t_infer += us_since(t1);
         ck_config c = stage_config(0, fmt, current_);
         if (fmt != CK_FMT_CSR) {
-            if (cancel_.load()) {
+            if (cancel_.load() || !worth_converting(F, c)) {
                 skip_rest(0);
                 return;
             }
@@ -206,7 +308,8 @@ class AsyncExec {
         c = stage_config(1, alg, c);
         if (alg == CK_ALG_PANEL || alg == CK_ALG_MERGE) {
             // the panel-major copy / merge-path partition must exist first
-            if (cancel_.load()) {
+            // (the partition costs a fraction of a product: never gated)
+            if (cancel_.load() || (alg == CK_ALG_PANEL && !worth_converting(F, c))) {
                 skip_rest(1);
                 return;
             }
@@ -238,6 +341,10 @@ class AsyncExec {
 
     ck_matrix &M_;
     ck_config current_;
+    bool gate_ = false;
+    std::mutex prog_mu_;
+    int first_iter_ = -1, last_iter_ = -1;
+    double first_relres_ = 0, last_relres_ = 0, tol_ = 0;
     hipStream_t side_ = nullptr;
     hipEvent_t conv_done_ = nullptr;
     std::thread worker_;
@@ -348,16 +455,22 @@ ck_status cg_core(SolveCtx &c, T *x, T *r, T *p, T *q, T *partials, CgDev<T> *de
         ++issued;
         if (++since_poll >= every_now || issued >= budget) {
             since_poll = 0;
-            // stage this poll, then read the previous one
-            CK_HIP(hipMemcpyAsync(pin.buf + 64 * slot, &dev->state, 2 * sizeof(int),
+            // stage this poll (relres, state, iter: adjacent fields), then
+            // read the previous one
+            CK_HIP(hipMemcpyAsync(pin.buf + 64 * slot, &dev->relres, sizeof(double) + 2 * sizeof(int),
                                   hipMemcpyDeviceToHost, c.s));
             CK_HIP(hipEventRecord(pin.ev[slot], c.s));
             ++polls;
             if (polls >= 2 || issued >= budget) {
                 const int prev = (issued >= budget) ? slot : slot ^ 1;
                 CK_HIP(hipEventSynchronize(pin.ev[prev]));
-                int st;
-                std::memcpy(&st, pin.buf + 64 * prev, sizeof st);
+                double rr;
+                int st, it;
+                std::memcpy(&rr, pin.buf + 64 * prev, sizeof rr);
+                std::memcpy(&st, pin.buf + 64 * prev + sizeof(double), sizeof st);
+                std::memcpy(&it, pin.buf + 64 * prev + sizeof(double) + sizeof(int), sizeof it);
+                if (c.exec)
+                    c.exec->progress(it, rr, tol);
                 if (st != RUN)
                     break;
             }
@@ -527,7 +640,8 @@ ck_status gmres_run(SolveCtx &c, const double *b, double *x) {
     CK_HIP(hipStreamSynchronize(c.s));
     const int *final_ptr = &st->final_state;
     const int *halt_ptr = &st->halt;
-    const int status_off = (int)offsetof(GmDev<T>, j);   // j, iter, max_iter, cycle_stop, final_state
+    // relres, m, j, iter, max_iter, cycle_stop, final_state (adjacent fields)
+    const int status_off = (int)offsetof(GmDev<T>, relres);
     int issued = 0, slot = 0, cycles = 0;
     ck_status out = CK_OK;
     while (true) {
@@ -544,14 +658,19 @@ ck_status gmres_run(SolveCtx &c, const double *b, double *x) {
         }
         CK_TRY(launch_gm_cycle_end<T>(M.n, x, V, ldv, st, c.s));
         ++cycles;
-        CK_HIP(hipMemcpyAsync(pin.buf + 64 * slot, (char *)st + status_off, 5 * sizeof(int),
-                              hipMemcpyDeviceToHost, c.s));
+        CK_HIP(hipMemcpyAsync(pin.buf + 64 * slot, (char *)st + status_off,
+                              sizeof(double) + 6 * sizeof(int), hipMemcpyDeviceToHost, c.s));
         CK_HIP(hipEventRecord(pin.ev[slot], c.s));
         if (cycles >= 2) {
             const int prev = slot ^ 1;
             CK_HIP(hipEventSynchronize(pin.ev[prev]));
-            int fs;
-            std::memcpy(&fs, pin.buf + 64 * prev + 4 * sizeof(int), sizeof fs);
+            double rr;
+            int it, fs;
+            std::memcpy(&rr, pin.buf + 64 * prev, sizeof rr);
+            std::memcpy(&it, pin.buf + 64 * prev + sizeof(double) + 2 * sizeof(int), sizeof it);
+            std::memcpy(&fs, pin.buf + 64 * prev + sizeof(double) + 5 * sizeof(int), sizeof fs);
+            if (c.exec && sizeof(T) == 8)
+                c.exec->progress(it, rr, c.o.tol);
             if (fs != RUN)
                 break;
         }
@@ -714,6 +833,8 @@ ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *
     if (opts->async < CK_EXEC_DEFAULT || opts->async > CK_EXEC_SEQUENTIAL)
         return fail(CK_E_INVALID, "async must be CK_EXEC_DEFAULT, _ASYNC or _SEQUENTIAL");
     std::memset(res, 0, sizeof *res);
+    res->conversion_gated = -1;
+    res->est_remaining_iters = -1;
     res->switch_iter[0] = res->switch_iter[1] = res->switch_iter[2] = -1;
     const auto t0 = Clock::now();
     SolveCtx c{M, *opts, *res, s, default_config(M.n, M.nnz)};
@@ -760,7 +881,8 @@ ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *
     c.carry = cbuf;
     AsyncExec *exec = nullptr;
     if (run_async) {
-        exec = new AsyncExec(M, c.cfg);
+        exec = new AsyncExec(M, c.cfg, opts->overhead_aware != 0 &&
+                                           opts->precision == CK_PREC_FP64);
         ck_status e = exec->start();
         if (e != CK_OK) {
             delete exec;
@@ -779,6 +901,8 @@ ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *
         res->t_features_us = exec->t_features;
         res->t_infer_us = exec->t_infer;
         res->t_convert_us = exec->t_convert;
+        res->conversion_gated = exec->gate_decision;
+        res->est_remaining_iters = exec->est_remaining;
         delete exec;
     }
     (void)hipStreamSynchronize(s);
@@ -792,6 +916,17 @@ ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *
 }  // namespace ck
 
 extern "C" {
+
+ck_status ck_overhead_gate(const ck_features *f, const ck_config *target, int32_t t0, double r0,
+                           int32_t t1, double r1, double tol, double *remaining, double *cost,
+                           int32_t *convert) {
+    if (!f || !target || !remaining || !cost || !convert || !ck::config_valid(*target))
+        return ck::fail(CK_E_INVALID, "bad arguments");
+    *remaining = ck::remaining_iterations(t0, r0, t1, r1, tol);
+    *cost = ck::conversion_products(*f, *target);
+    *convert = *remaining * ck::kGain >= *cost ? 1 : 0;
+    return CK_OK;
+}
 
 ck_status cg_solve(ck_handle h, const double *d_b, double *d_x, const ck_solve_opts *opts,
                    ck_solve_result *res, hipStream_t s) {

@@ -82,3 +82,31 @@ def test_library_cascade_equals_oracle_on_training_features(orc):
         assert c.format == want[0] and c.stages_done == sum(1 for v in want if v >= 0)
         seen.add(want[0])
     assert {0, 1, 3} <= seen, seen
+
+
+def test_overhead_gate_rule_on_host():
+    """The overhead-aware conversion rule: exact geometric extrapolation, the
+    no-decay and converged cases, cost ordering, and the 0.25 * R >= cost
+    threshold."""
+    ensure_built()
+    import math
+    import paper_2411_10143_amd as ck
+    F = ck.Features.from_model_inputs([1e6, 1e6, 7e6, 7e-6, 7.0, 0.0, 0.0, 7, 7, 0.0, 2e4,
+                                       3.0, 1.0, 7, 7e-6])
+    dia = ck.config_from_id(ck.ID_DIA)
+    q = 0.5
+    rem, cost, _ = ck.overhead_gate(F, dia, 2, q ** 2, 6, q ** 6, q ** 30)
+    assert abs(rem - 24.0) < 1e-9
+    assert ck.overhead_gate(F, dia, 2, 0.1, 6, 0.2, 1e-10)[0] == 1e9      # residual grew
+    assert ck.overhead_gate(F, dia, 2, 0.1, 6, 1e-11, 1e-10)[0] == 0.0    # already converged
+    coo = ck.overhead_gate(F, ck.config_from_id(10), 2, 0.5, 6, 0.1, 1e-10)[1]
+    ell = ck.overhead_gate(F, ck.config_from_id(ck.ID_ELL), 2, 0.5, 6, 0.1, 1e-10)[1]
+    assert 2.0 < coo < ell < cost
+    # threshold: convert iff 0.25 * remaining >= cost
+    for want_rem in (cost * 4 * 0.9, cost * 4 * 1.1):
+        t1 = 10
+        r1 = 1e-3
+        r0 = r1 * math.exp(-10 * math.log(1e-10 / r1) / want_rem)   # from t0 = 0
+        rem, c2, go = ck.overhead_gate(F, dia, 0, r0, t1, r1, 1e-10)
+        assert abs(rem - want_rem) < 1e-6 * want_rem and c2 == cost
+        assert go == (0.25 * rem >= cost)

@@ -303,3 +303,60 @@ def test_invalid_execution_mode_rejected(ck, orc):
         run(ck, ck.cg_solve, Mx, b, tol=1e-10, async_=3, raise_on_error=True)
     assert e.value.status == ck.CK_E_INVALID
     Mx.close()
+
+
+def _shifted_lap3d(N, shift):
+    A = M.laplacian_3d(N)
+    A.val = A.val.copy()
+    rows = np.repeat(np.arange(A.n), np.diff(A.rp))
+    A.val[A.col == rows] += shift
+    return A
+
+
+@pytest.mark.parametrize("shift", [1.0, 10.0])
+def test_overhead_aware_gate_skips_a_conversion_that_cannot_pay(ck, orc, shift):
+    """A well-conditioned 3D stencil system (~14 or ~40 CG iterations): the
+    cascade asks for a new format, but the remaining iterations cannot repay
+    its conversion, so the solve stays on the default configuration.  (When
+    the solve ends before the features are ready the gate is never asked;
+    either way no conversion takes effect.)"""
+    A = _shifted_lap3d(100, shift)
+    xs, b = problem(orc, A, 3)
+    say(f"overhead-aware gate: lap3d_100 + {shift} I n={A.n}")
+    Mx = ck.Matrix.from_csr(A)
+    stages = ck.select_stages(ck.spmv_features(Mx.handle))
+    x, r = run(ck, ck.cg_solve, Mx, b, tol=1e-10, async_=ck.CK_EXEC_ASYNC, overhead_aware=True)
+    assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10
+    assert stages[0] != ck.CK_FMT_CSR, stages
+    assert r["conversion_gated"] in (-1, 1), r
+    if r["conversion_gated"] == 1:
+        assert 0 <= r["est_remaining_iters"] < 80, r
+    assert r["switch_iter"][0] == -1
+    assert r["final_config"] == ck.config_id(ck.default_config(Mx.handle))
+    Mx.close()
+
+
+def test_overhead_aware_gate_converts_for_a_long_solve(ck, orc):
+    A = M.laplacian_3d(64)
+    xs, b = problem(orc, A, 4)
+    say(f"overhead-aware gate: lap3d_64 n={A.n}")
+    Mx = ck.Matrix.from_csr(A)
+    stages = ck.select_stages(ck.spmv_features(Mx.handle))
+    want = ck.spmv_select(ck.spmv_features(Mx.handle))
+    x, r = run(ck, ck.cg_solve, Mx, b, tol=1e-10, async_=ck.CK_EXEC_ASYNC, overhead_aware=True)
+    assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10
+    assert stages[0] != ck.CK_FMT_CSR, stages
+    assert r["conversion_gated"] == 0, r
+    assert r["est_remaining_iters"] > 50, r
+    assert r["switch_iter"][0] >= 4 and r["final_config"] == ck.config_id(want), r
+    Mx.close()
+
+
+def test_gate_off_by_default(ck, orc):
+    A = _shifted_lap3d(40, 10.0)
+    xs, b = problem(orc, A, 5)
+    Mx = ck.Matrix.from_csr(A)
+    x, r = run(ck, ck.cg_solve, Mx, b, tol=1e-10, async_=ck.CK_EXEC_ASYNC)
+    assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10
+    assert r["conversion_gated"] == -1 and r["est_remaining_iters"] == -1
+    Mx.close()

@@ -115,11 +115,10 @@ enum { CK_EXEC_DEFAULT = 0, CK_EXEC_ASYNC = 1, CK_EXEC_SEQUENTIAL = 2 };
  * CK_EXEC_ASYNC in FP64; the overhead-conscious selection discussed among
  * the paper's related work): a decision that needs a new copy of the matrix
  * (ELL, COO, DIA, HYB, CSR-panel) waits for the solver's residual reports
- * of the first few iterations, extrapolates the remaining iterations R from
- * the residual's geometric decay, and is converted only if 0.25 * R is at
- * least the conversion's cost in products (its modelled bytes over one
- * product's bytes, plus 2); otherwise the solve keeps its configuration
- * (conversion_gated = 1 in the result). */
+ * of the first eight or more iterations, extrapolates the remaining
+ * iterations R (ck_overhead_gate), and is converted only if 0.25 * R is at
+ * least the conversion's cost in products; otherwise the solve keeps its
+ * configuration (conversion_gated = 1 in the result). */
 
 typedef struct {
     double tol;            /* stop when ||b - A x||_2 / ||b||_2 <= tol        */
@@ -274,13 +273,15 @@ ck_status ck_export_ell(ck_handle h, int32_t *d_col, double *d_val, int64_t *K,
                         int64_t *pitch, hipStream_t s);
 
 /* ck_overhead_gate -- the overhead-aware conversion rule on host values
- * (host only; the asynchronous executor applies the same rule): from two
- * residual reports (iteration t0, relative residual r0) and (t1, r1),
- * t0 < t1, *remaining = (t1 - t0) * ln(tol / r1) / ln(r1 / r0), the
- * iterations a geometric decay needs from r1 down to tol (0 if r1 <= tol,
- * 1e9 if the residual did not decrease); *cost = the modelled bytes of the
- * conversion to `target` over one product's bytes, plus 2 (features f give
- * the sizes); *convert = 1 iff 0.25 * remaining >= cost. */
+ * (host only; the asynchronous executor applies the same rule to the
+ * latest report at iteration >= 8 and the latest report at least 4
+ * iterations before it): from two residual reports (iteration t0, relative
+ * residual r0) and (t1, r1), t0 < t1, *remaining = 2 (t1 - t0)
+ * ln(tol / r1) / ln(r1 / r0), twice the iterations the geometric decay
+ * needs from r1 down to tol (a Krylov residual falls fastest early; 0 if
+ * r1 <= tol, 1e9 if the residual did not decrease); *cost = the modelled
+ * bytes of the conversion to `target` over one product's bytes, plus 2
+ * (features f give the sizes); *convert = 1 iff 0.25 * remaining >= cost. */
 ck_status ck_overhead_gate(const ck_features *f, const ck_config *target, int32_t t0, double r0,
                            int32_t t1, double r1, double tol, double *remaining, double *cost,
                            int32_t *convert);

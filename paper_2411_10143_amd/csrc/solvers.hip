@@ -86,13 +86,19 @@ thread_local Pinned tl_pinned;
 // Overhead-aware conversion (opt-in, after the overhead-conscious selection
 // the paper discusses among related work): before a decision that needs a
 // new copy of the matrix is converted, the worker waits for the solver's
-// first residual reports, extrapolates the remaining iterations R from the
-// residual's geometric decay and converts only if R * kGain >= C, where C
-// is the conversion's cost in products of the matrix (its bytes over one
+// residual reports of at least kGateMinIter iterations, extrapolates the
+// remaining iterations R from the residual's decay over the last
+// kGateWindow or more iterations and converts only if R * kGain >= C, where
+// C is the conversion's cost in products of the matrix (its bytes over one
 // product's bytes, plus two for launches and the host read-back) and kGain
 // the fraction of a product each remaining iteration is assumed to save.
+// A Krylov residual falls fastest in the first iterations (on a 3D
+// Laplacian the decay over iterations 2-6 is about 3x the average), so the
+// geometric extrapolation is doubled (kSlowdown).
 constexpr double kGain = 0.25;
-constexpr int kGateMinIter = 4;
+constexpr double kSlowdown = 2.0;
+constexpr int kGateMinIter = 8;
+constexpr int kGateWindow = 4;
 
 }  // namespace
 
@@ -116,14 +122,15 @@ double conversion_products(const ck_features &F, const ck_config &c) {
 }
 
 // Remaining iterations extrapolated from two residual reports (t0, r0) and
-// (t1, r1), t0 < t1, assuming the decay from r0 to r1 continues
-// geometrically down to tol; 1e9 when the residual has not decreased.
+// (t1, r1), t0 < t1: kSlowdown times the iterations the decay from r0 to r1
+// needs, continued geometrically, to reach tol; 1e9 when the residual has
+// not decreased.
 double remaining_iterations(int t0, double r0, int t1, double r1, double tol) {
     if (!(r1 > 0.0) || r1 <= tol)
         return 0.0;
     if (!(r1 < r0) || !(tol > 0.0) || t1 <= t0)
         return 1e9;
-    return std::min(1e9, (t1 - t0) * std::log(tol / r1) / std::log(r1 / r0));
+    return std::min(1e9, kSlowdown * (t1 - t0) * std::log(tol / r1) / std::log(r1 / r0));
 }
 
 namespace {
@@ -180,12 +187,11 @@ class AsyncExec {
         if (!gate_ || iter <= 0 || !(relres > 0.0))
             return;
         std::lock_guard<std::mutex> lk(prog_mu_);
-        if (first_iter_ < 0) {
-            first_iter_ = iter;
-            first_relres_ = relres;
-        }
-        last_iter_ = iter;
-        last_relres_ = relres;
+        if (!hist_.empty() && iter <= hist_.back().first)
+            return;
+        if (hist_.size() >= 256)          // only recent reports matter
+            hist_.erase(hist_.begin(), hist_.begin() + 128);
+        hist_.emplace_back(iter, relres);
         tol_ = tol;
     }
 
@@ -229,22 +235,22 @@ class AsyncExec {
             return true;
         const double C = conversion_products(F, c);
         while (!cancel_.load()) {
-            int i0, i1;
-            double r0, r1, tol;
+            int t = -1, t_ref = 0;
+            double r1 = 0, r_ref = 1.0, tol = 0;   // x0 = 0: relres 1 at iteration 0
             {
                 std::lock_guard<std::mutex> lk(prog_mu_);
-                i0 = first_iter_;
-                i1 = last_iter_;
-                r0 = first_relres_;
-                r1 = last_relres_;
+                if (!hist_.empty()) {
+                    t = hist_.back().first;
+                    r1 = hist_.back().second;
+                    for (const auto &h : hist_)   // latest report >= kGateWindow back
+                        if (h.first <= t - kGateWindow) {
+                            t_ref = h.first;
+                            r_ref = h.second;
+                        }
+                }
                 tol = tol_;
             }
-            // the first report serves as the reference when it comes after
-            // iteration 0 (x0 = 0 gives relres 1 at iteration 0)
-            const int t = i1 >= 0 ? i1 : -1;
             if (t >= kGateMinIter) {
-                const double r_ref = (i0 >= 0 && i0 < i1) ? r0 : 1.0;
-                const int t_ref = (i0 >= 0 && i0 < i1) ? i0 : 0;
                 const double R = remaining_iterations(t_ref, r_ref, t, r1, tol);
                 est_remaining = (int)R;
                 const bool go = R * kGain >= C;
@@ -343,8 +349,8 @@ class AsyncExec {
     ck_config current_;
     bool gate_ = false;
     std::mutex prog_mu_;
-    int first_iter_ = -1, last_iter_ = -1;
-    double first_relres_ = 0, last_relres_ = 0, tol_ = 0;
+    std::vector<std::pair<int, double>> hist_;   // (iterations, relres) reports
+    double tol_ = 0;
     hipStream_t side_ = nullptr;
     hipEvent_t conv_done_ = nullptr;
     std::thread worker_;

@@ -96,7 +96,7 @@ def test_overhead_gate_rule_on_host():
     dia = ck.config_from_id(ck.ID_DIA)
     q = 0.5
     rem, cost, _ = ck.overhead_gate(F, dia, 2, q ** 2, 6, q ** 6, q ** 30)
-    assert abs(rem - 24.0) < 1e-9
+    assert abs(rem - 2 * 24.0) < 1e-9          # twice the geometric extrapolation
     assert ck.overhead_gate(F, dia, 2, 0.1, 6, 0.2, 1e-10)[0] == 1e9      # residual grew
     assert ck.overhead_gate(F, dia, 2, 0.1, 6, 1e-11, 1e-10)[0] == 0.0    # already converged
     coo = ck.overhead_gate(F, ck.config_from_id(10), 2, 0.5, 6, 0.1, 1e-10)[1]
@@ -106,7 +106,7 @@ def test_overhead_gate_rule_on_host():
     for want_rem in (cost * 4 * 0.9, cost * 4 * 1.1):
         t1 = 10
         r1 = 1e-3
-        r0 = r1 * math.exp(-10 * math.log(1e-10 / r1) / want_rem)   # from t0 = 0
+        r0 = r1 * math.exp(-2 * 10 * math.log(1e-10 / r1) / want_rem)   # from t0 = 0
         rem, c2, go = ck.overhead_gate(F, dia, 0, r0, t1, r1, 1e-10)
         assert abs(rem - want_rem) < 1e-6 * want_rem and c2 == cost
         assert go == (0.25 * rem >= cost)

@@ -355,8 +355,8 @@ def test_overhead_aware_gate_converts_for_a_long_solve(ck, orc):
     assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10
     assert stages[0] != ck.CK_FMT_CSR, stages
     assert r["conversion_gated"] == 0, r
-    assert r["est_remaining_iters"] > 50, r
-    assert r["switch_iter"][0] >= 4 and r["final_config"] == ck.config_id(want), r
+    assert r["est_remaining_iters"] > 20, r
+    assert r["switch_iter"][0] >= 8 and r["final_config"] == ck.config_id(want), r
     Mx.close()
 
 

@@ -98,6 +98,10 @@ def bench_spmv_set(args):
 
     torch.cuda.set_device(0)
     specs = W.spmv_set_specs(max_n=args.max_n)
+    if args.only:
+        specs = [sp for sp in specs if sp[0].startswith(args.only + "_")]
+        if not specs:
+            raise SystemExit(f"--only {args.only}: no such member of the SpMV set")
     mats, dev = [], []
     t0 = time.time()
     for i, spec in enumerate(specs):
@@ -627,6 +631,9 @@ def main():
                    choices=["spmv_set", "cg_lap2d", "cg_async", "gmres_mixed", "serve"])
     p.add_argument("--reps", type=int, default=200)
     p.add_argument("--max-n", type=int, default=None, help="drop set members above this n")
+    p.add_argument("--only", default=None,
+                   help="spmv_set: keep one member, named by its prefix (e.g. uniform_k11); "
+                        "for profiling a single matrix, not a bench line")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--table", default=None, help="write the per-matrix timing table (JSON)")
     p.add_argument("--no-table", action="store_true",

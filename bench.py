@@ -141,24 +141,39 @@ def bench_spmv_set(args):
             f" {T[m].min():.2f}us default={T[m, default_id[-1]]:.2f}us")
 
     # ---- timed steps: ingest -> features -> select -> convert -> R products ---
+    phase_ms = dict(ingest=0.0, features=0.0, select=0.0, convert=0.0, products=0.0,
+                    release=0.0)
+
     def one_step(record):
         picks, spmv_us = [], 0.0
+        clk = time.perf_counter
         for m, (A, d) in enumerate(zip(mats, dev)):
+            t0 = clk()
             Mx = ck.Matrix(d["rp"], d["col"], d["val"], A.ncols)
+            t1 = clk()
             F = ck.spmv_features(Mx.handle)
+            t2 = clk()
             cfg = ck.spmv_select(F)
+            t3 = clk()
             try:
                 ck.spmv_convert(Mx.handle, cfg)
             except ck.CkError as e:
                 if e.status != ck.CK_E_UNSUPPORTED:
                     raise
                 cfg = ck.default_config(Mx.handle)   # refused conversion: keep the default
+            t4 = clk()
             us = ck.time_spmv(Mx.handle, cfg, d["x"], d["y"], warmup=0, reps=R)
+            t5 = clk()
             spmv_us += us * R
             if record:
                 ledger.add(ck.kernel_name(cfg), R, us, nbytes[m])
             picks.append(ck.config_id(cfg))
             Mx.close()
+            t6 = clk()
+            if record:   # host wall time per phase (asynchronous work lands in the next blocking call)
+                for k, a, b in (("ingest", t0, t1), ("features", t1, t2), ("select", t2, t3),
+                                ("convert", t3, t4), ("products", t4, t5), ("release", t5, t6)):
+                    phase_ms[k] += (b - a) * 1e3
         return picks, spmv_us
 
     for _ in range(args.warmup):
@@ -252,6 +267,7 @@ def bench_spmv_set(args):
         "cpu_baseline": cpu,
         "spmv": {
             "kernel_GBs_in_steps": round(bytes_step / (np.mean(spmv_totals) * 1e3), 1),
+            "step_phase_ms": {k: round(v / len(step_times), 2) for k, v in phase_ms.items()},
             "copy_GBs": round(copy_gbs, 1),
             "kernels_in_steps": {k: dict(launches=v[0], avg_us=round(v[1] / v[0], 3))
                                  for k, v in sorted(ledger.k.items())},

@@ -4,7 +4,6 @@
 #include <cstdarg>
 #include <cstring>
 #include <limits>
-#include <set>
 
 #include "matrix.hpp"
 #include "diahyb.hpp"
@@ -41,50 +40,44 @@ ck_status launch_to_ell(const ck_matrix &M, int64_t K, int64_t pitch, int *ecol,
                         float *evl32, hipStream_t s);
 ck_status launch_to_coo(const ck_matrix &M, int *row, hipStream_t s);
 
-ck_status ensure_pool(int device) {
-    static std::mutex mu;
-    static std::set<int> done;
-    std::lock_guard<std::mutex> lk(mu);
-    if (done.count(device))
-        return CK_OK;
-    hipMemPool_t pool;
-    CK_HIP(hipDeviceGetDefaultMemPool(&pool, device));
-    uint64_t keep = kPoolKeepBytes;
-    CK_HIP(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep));
-    done.insert(device);
-    return CK_OK;
-}
-
 template <typename T>
-static ck_status dev_alloc(T **p, int64_t count, hipStream_t s) {
-    return pool_alloc(p, count, s);
+static ck_status dev_alloc(T **p, int64_t count) {
+    *p = nullptr;
+    const size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
+    hipError_t e = hipMalloc((void **)p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(CK_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
+    }
+    return CK_OK;
 }
 
 static void release(ck_matrix *M) {
     if (!M)
         return;
-    pool_free(M->rp);
-    pool_free(M->col);
-    pool_free(M->val);
-    pool_free(M->val32);
-    pool_free(M->ell_col);
-    pool_free(M->ell_val);
-    pool_free(M->ell_val32);
-    pool_free(M->coo_row);
-    pool_free(M->dia_off);
-    pool_free(M->dia_val);
-    pool_free(M->dia_val32);
-    pool_free(M->hyb_col);
-    pool_free(M->hyb_val);
-    pool_free(M->hyb_val32);
-    pool_free(M->hyb_rows);
-    pool_free(M->panel_rp);
-    pool_free(M->panel_col);
-    pool_free(M->panel_val);
-    pool_free(M->panel_val32);
-    pool_free(M->merge_part);
+    (void)hipFree(M->rp);
+    (void)hipFree(M->col);
+    (void)hipFree(M->val);
+    (void)hipFree(M->val32);
+    (void)hipFree(M->ell_col);
+    (void)hipFree(M->ell_val);
+    (void)hipFree(M->ell_val32);
+    (void)hipFree(M->coo_row);
+    (void)hipFree(M->dia_off);
+    (void)hipFree(M->dia_val);
+    (void)hipFree(M->dia_val32);
+    (void)hipFree(M->hyb_col);
+    (void)hipFree(M->hyb_val);
+    (void)hipFree(M->hyb_val32);
+    (void)hipFree(M->hyb_rows);
+    (void)hipFree(M->panel_rp);
+    (void)hipFree(M->panel_col);
+    (void)hipFree(M->panel_val);
+    (void)hipFree(M->panel_val32);
+    (void)hipFree(M->merge_part);
     for (auto &kv : M->carry)
-        pool_free(kv.second);
+        (void)hipFree(kv.second);
     delete M;
 }
 
@@ -134,7 +127,7 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
         // every workgroup of every product
         if (M.has_merge_part.load())
             return CK_OK;
-        CK_TRY(dev_alloc(&M.merge_part, merge_part_entries(M), s));
+        CK_TRY(dev_alloc(&M.merge_part, merge_part_entries(M)));
         CK_TRY(launch_merge_partition(M, M.merge_part, s));
         M.has_merge_part.store(true);
         return CK_OK;
@@ -147,11 +140,11 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
         const int64_t N = (int64_t)P * M.n;
         if (N + 1 > (int64_t)std::numeric_limits<int32_t>::max())
             return fail(CK_E_UNSUPPORTED, "too many panel rows");
-        CK_TRY(dev_alloc(&M.panel_rp, N + 1, s));
-        CK_TRY(dev_alloc(&M.panel_col, M.nnz, s));
-        CK_TRY(dev_alloc(&M.panel_val, M.nnz, s));
+        CK_TRY(dev_alloc(&M.panel_rp, N + 1));
+        CK_TRY(dev_alloc(&M.panel_col, M.nnz));
+        CK_TRY(dev_alloc(&M.panel_val, M.nnz));
         if (M.val32)
-            CK_TRY(dev_alloc(&M.panel_val32, M.nnz, s));
+            CK_TRY(dev_alloc(&M.panel_val32, M.nnz));
         int *tmp = nullptr;
         const int64_t tmp_elems = N + panel_scan_tmp_elems(N);
         CK_HIP(hipMallocAsync((void **)&tmp, (size_t)tmp_elems * sizeof(int), s));
@@ -170,9 +163,10 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
             return CK_OK;
         const ck_status st = convert_to_dia(M, s);
         if (st != CK_OK) {   // refused for fill, or out of memory: leave no partial copy
-            pool_free(M.dia_off, s);
-            pool_free(M.dia_val, s);
-            pool_free(M.dia_val32, s);
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(M.dia_off);
+            (void)hipFree(M.dia_val);
+            (void)hipFree(M.dia_val32);
             M.dia_off = nullptr;
             M.dia_val = nullptr;
             M.dia_val32 = nullptr;
@@ -186,10 +180,11 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
             return CK_OK;
         const ck_status st = convert_to_hyb(M, s);
         if (st != CK_OK) {
-            pool_free(M.hyb_col, s);
-            pool_free(M.hyb_val, s);
-            pool_free(M.hyb_val32, s);
-            pool_free(M.hyb_rows, s);
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(M.hyb_col);
+            (void)hipFree(M.hyb_val);
+            (void)hipFree(M.hyb_val32);
+            (void)hipFree(M.hyb_rows);
             M.hyb_col = nullptr;
             M.hyb_val = nullptr;
             M.hyb_val32 = nullptr;
@@ -202,7 +197,7 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
     if (c.format == CK_FMT_COO) {
         if (M.has_coo.load())
             return CK_OK;
-        CK_TRY(dev_alloc(&M.coo_row, M.nnz, s));
+        CK_TRY(dev_alloc(&M.coo_row, M.nnz));
         CK_TRY(launch_to_coo(M, M.coo_row, s));
         M.has_coo.store(true);
         return CK_OK;
@@ -225,10 +220,10 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
     if (K * pitch > 8 * M.nnz)
         return fail(CK_E_UNSUPPORTED, "ELL refused: %lld slots for %lld stored entries",
                     (long long)(K * pitch), (long long)M.nnz);
-    CK_TRY(dev_alloc(&M.ell_col, K * pitch, s));
-    CK_TRY(dev_alloc(&M.ell_val, K * pitch, s));
+    CK_TRY(dev_alloc(&M.ell_col, K * pitch));
+    CK_TRY(dev_alloc(&M.ell_val, K * pitch));
     if (M.val32)
-        CK_TRY(dev_alloc(&M.ell_val32, K * pitch, s));
+        CK_TRY(dev_alloc(&M.ell_val32, K * pitch));
     CK_TRY(launch_to_ell(M, K, pitch, M.ell_col, M.ell_val, M.ell_val32, s));
     M.ell_K = K;
     M.ell_pitch = pitch;
@@ -321,10 +316,9 @@ ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
     unsigned *bad = nullptr;
     unsigned hbad = 0;
     do {
-        if ((st = ensure_pool(M->device)) != CK_OK) break;
-        if ((st = dev_alloc(&M->rp, nrows + 1, s)) != CK_OK) break;
-        if ((st = dev_alloc(&M->col, nnz, s)) != CK_OK) break;
-        if ((st = dev_alloc(&M->val, nnz, s)) != CK_OK) break;
+        if ((st = dev_alloc(&M->rp, nrows + 1)) != CK_OK) break;
+        if ((st = dev_alloc(&M->col, nnz)) != CK_OK) break;
+        if ((st = dev_alloc(&M->val, nnz)) != CK_OK) break;
         hipError_t e = hipMemcpyAsync(M->rp, d_rowptr, sizeof(int32_t) * (nrows + 1),
                                       hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess && nnz > 0)
@@ -336,11 +330,11 @@ ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
             break;
         }
         if (flags & CK_KEEP_FP32) {
-            if ((st = dev_alloc(&M->val32, nnz, s)) != CK_OK) break;
+            if ((st = dev_alloc(&M->val32, nnz)) != CK_OK) break;
             if (nnz > 0 && (st = launch_copy<float, double>(nnz, M->val32, M->val, nullptr, s)) != CK_OK)
                 break;
         }
-        if ((st = dev_alloc(&bad, 1, s)) != CK_OK) break;
+        if ((st = dev_alloc(&bad, 1)) != CK_OK) break;
         if ((st = launch_fill<int>(1, (int *)bad, 0, s)) != CK_OK) break;
         if ((st = launch_validate(nrows, ncols, nnz, M->rp, M->col, bad, s)) != CK_OK) break;
         e = hipMemcpyAsync(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, s);
@@ -357,7 +351,7 @@ ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
             break;
         }
     } while (false);
-    pool_free(bad, s);
+    (void)hipFree(bad);
     if (st != CK_OK) {
         release(M);
         return st;
@@ -479,7 +473,7 @@ static ck_status carry_for(ck_handle h, const ck_config &c, hipStream_t s, void 
                  std::max(spmv_carry_bytes(*h, ck_config{CK_FMT_COO, 0, 0, 0}, false),
                           spmv_carry_bytes(*h, ck_config{CK_FMT_CSR, CK_ALG_PANEL, 0, 0}, false)));
     char *p = nullptr;
-    CK_TRY(dev_alloc(&p, bytes, s));
+    CK_TRY(dev_alloc(&p, bytes));
     h->carry[s] = p;
     *out = p;
     return CK_OK;

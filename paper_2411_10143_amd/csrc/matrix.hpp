@@ -66,35 +66,6 @@ struct ck_matrix {
 
 namespace ck {
 
-// Device memory of matrix handles (CSR copies, format copies, carries) comes
-// from the device's default stream-ordered pool, which keeps up to
-// kPoolKeepBytes of freed memory for reuse (ensure_pool sets this once per
-// device): ingesting a matrix then maps no new pages, and destroying one does
-// not synchronise the device as hipFree does.
-constexpr uint64_t kPoolKeepBytes = 32ull << 30;
-ck_status ensure_pool(int device);
-
-template <typename T>
-ck_status pool_alloc(T **p, int64_t count, hipStream_t s) {
-    *p = nullptr;
-    const size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
-    const hipError_t e = hipMallocAsync((void **)p, bytes, s);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(CK_E_NOMEM, "device allocation of %zu bytes failed: %s", bytes,
-                    hipGetErrorString(e));
-    }
-    return CK_OK;
-}
-
-// Stream-ordered free on `s` (the null stream when the caller guarantees the
-// memory is idle); NULL is ignored.
-inline void pool_free(void *p, hipStream_t s = nullptr) {
-    if (p)
-        (void)hipFreeAsync(p, s);
-}
-
 // Arguments of one product y = alpha*A*x + beta*y.
 //  skip   : if non-null and *skip != 0 when the launch starts, it does nothing
 //           (lets a solver enqueue iterations ahead of its convergence test).

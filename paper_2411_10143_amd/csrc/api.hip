@@ -76,6 +76,7 @@ static void release(ck_matrix *M) {
     (void)hipFree(M->panel_val);
     (void)hipFree(M->panel_val32);
     (void)hipFree(M->merge_part);
+    (void)hipFree(M->panel_part);
     for (auto &kv : M->carry)
         (void)hipFree(kv.second);
     delete M;
@@ -154,7 +155,8 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
         CK_TRY(st);
         M.panel_P = P;
         M.panel_W = W;
-        M.panel_L = kPanelLanes;
+        CK_TRY(dev_alloc(&M.panel_part, merge_part_entries_rows(N, M.nnz)));
+        CK_TRY(launch_merge_partition_rows(N, M.nnz, M.panel_rp, M.panel_part, s));
         M.has_panel.store(true);
         return CK_OK;
     }

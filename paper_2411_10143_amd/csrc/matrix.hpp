@@ -28,13 +28,15 @@ struct ck_matrix {
     std::atomic<bool> has_coo{false};
     // CSR-panel (after conversion): P column panels of width W, panel-major;
     // panel_rp[p*n + i] = start of row i in panel p (P*n + 1 entries)
-    int panel_P = 0, panel_L = 0;
+    int panel_P = 0;
     int64_t panel_W = 0;
     int32_t *panel_rp = nullptr;
     int32_t *panel_col = nullptr;
     double *panel_val = nullptr;
     float *panel_val32 = nullptr;
     std::atomic<bool> has_panel{false};
+    // merge-path partition of the panel-major arrays read as one CSR of P*n rows
+    int32_t *panel_part = nullptr;
     // merge-path partition (after conversion to CSR-merge): merge_part[q] =
     // rows whose end lies among the first min(2048 q, n + nnz) merged items
     int32_t *merge_part = nullptr;
@@ -96,6 +98,10 @@ int64_t spmv_carry_bytes(const ck_matrix &M, const ck_config &c, bool fp32);
 // Merge-path partition: entries of merge_part, and its launch (stream-ordered).
 int64_t merge_part_entries(const ck_matrix &M);
 ck_status launch_merge_partition(const ck_matrix &M, int32_t *part, hipStream_t s);
+// The same for any CSR of `rows` rows (used for the panel-major arrays).
+int64_t merge_part_entries_rows(int64_t rows, int64_t nnz);
+ck_status launch_merge_partition_rows(int64_t rows, int64_t nnz, const int32_t *rp,
+                                      int32_t *part, hipStream_t s);
 
 template <typename T>
 ck_status launch_spmv(const ck_matrix &M, const ck_config &c, const SpmvArgs<T> &a,

@@ -1,20 +1,20 @@
 // CSR-panel SpMV: an MI355X-specific CSR algorithm for matrices whose column
 // pattern is scattered (the gathered vector x does not fit one XCD's L2).
 //
-// The GPU has 8 XCDs, each with a private 4 MB L2, and deals workgroups to
-// them round-robin.  The columns are split into P = 8q panels whose slice of
-// x is at most 2 MB; the matrix is stored panel-major (all of panel 0, row by
-// row, then panel 1, ...).  Workgroup b works on panel b % P, so every
-// workgroup of panel p runs on XCD p % 8 and finds its x slice in that XCD's
-// L2 instead of fetching a cache line from the fabric for every entry.  Each
-// panel writes its partial row sums; a combine kernel adds the P partials in
-// panel order (deterministic) and applies alpha/beta (and the fused CG dot).
+// The GPU has 8 XCDs, each with a private 4 MB L2.  The columns are split
+// into P = 8q panels whose slice of x is at most 2 MB; the matrix is stored
+// panel-major (all of panel 0, row by row, then panel 1, ...), which is one
+// CSR of P*n rows.  Its product runs as a merge path (spmv.hip) whose
+// contiguous per-XCD block ranges give each XCD its own consecutive panels,
+// so the gathers find their x slice in that XCD's L2 instead of fetching a
+// cache line from the fabric for every entry.  Each panel writes its partial
+// row sums; a combine kernel adds the P partials in panel order
+// (deterministic) and applies alpha/beta (and the fused CG dot).
 #include <algorithm>
 
 #include "matrix.hpp"
 #include "panel.hpp"
 
-using ck::ld_stream;
 
 // cnt[p*n + i] = entries of row i whose column lies in panel p
 __global__ __launch_bounds__(256) void panel_count(int64_t n, int P, int64_t W,
@@ -111,45 +111,6 @@ __global__ __launch_bounds__(256) void scan_add(int64_t N, int *__restrict__ out
         out[g] += offs[g / 2048];
 }
 
-// One panel's partial products.  Workgroup b -> panel b % P (and so XCD
-// b % 8), row groups b / P, b / P + Gp, ...
-template <int L, typename T>
-__global__ __launch_bounds__(256) void spmv_panel(int n, int P, int64_t Gp,
-                                                  const int *__restrict__ prp,
-                                                  const int *__restrict__ pcol,
-                                                  const T *__restrict__ pval,
-                                                  const T *__restrict__ x, T *__restrict__ ypart,
-                                                  const int *__restrict__ skip) {
-    if (skip != nullptr && *skip != 0)
-        return;
-    const int p = blockIdx.x % P;
-    const int64_t g0 = blockIdx.x / P;
-    constexpr int R = 256 / L;
-    const int lane = threadIdx.x & (L - 1);
-    const int64_t groups = ((int64_t)n + R - 1) / R;
-    const int *pr = prp + (int64_t)p * n;
-    T *yp = ypart + (int64_t)p * n;
-    for (int64_t g = g0; g < groups; g += Gp) {
-        const int64_t row = g * R + threadIdx.x / L;
-        T sum = 0;
-        if (row < n) {
-            const int k0 = pr[row], k1 = pr[row + 1];
-            T s0 = 0, s1 = 0;
-            int k = k0 + lane;
-            for (; k + L < k1; k += 2 * L) {
-                s0 += ld_stream(&pval[k]) * x[ld_stream(&pcol[k])];
-                s1 += ld_stream(&pval[k + L]) * x[ld_stream(&pcol[k + L])];
-            }
-            if (k < k1)
-                s0 += ld_stream(&pval[k]) * x[ld_stream(&pcol[k])];
-            sum = s0 + s1;
-        }
-        sum = ck::group_sum<L>(sum);
-        if (lane == 0 && row < n)
-            yp[row] = sum;
-    }
-}
-
 // y = alpha * sum_p ypart[p] + beta * y   (+ per-block partial of y.x for CG)
 template <typename T, bool BETA, bool DOT>
 __global__ __launch_bounds__(256) void panel_combine(int64_t n, int P, int64_t G,
@@ -232,32 +193,9 @@ ck_status launch_to_panel(const ck_matrix &M, int P, int64_t W, int *cnt, int *t
     return CK_OK;
 }
 
-template <int L, typename T>
-static void go_panel(const ck_matrix &M, const T *pv, const T *x, T *ypart, const int *skip,
-                     hipStream_t s) {
-    const int64_t groups = std::max<int64_t>(ceil_div(M.n, 256 / L), 1);
-    const int64_t Gp = std::min<int64_t>(groups, std::max(kRowBlocks / M.panel_P, 1));
-    hipLaunchKernelGGL((spmv_panel<L, T>), dim3(Gp * M.panel_P), dim3(256), 0, s, (int)M.n,
-                       M.panel_P, Gp, M.panel_rp, M.panel_col, pv, x, ypart, skip);
-}
-
 template <typename T>
-ck_status launch_panel_spmv(const ck_matrix &M, const SpmvArgs<T> &a, T *ypart, int64_t G_dot,
-                            hipStream_t s) {
-    const T *pv;
-    if constexpr (sizeof(T) == 4)
-        pv = M.panel_val32;
-    else
-        pv = M.panel_val;
-    switch (M.panel_L) {
-    case 1: go_panel<1, T>(M, pv, a.x, ypart, a.skip, s); break;
-    case 2: go_panel<2, T>(M, pv, a.x, ypart, a.skip, s); break;
-    case 4: go_panel<4, T>(M, pv, a.x, ypart, a.skip, s); break;
-    case 8: go_panel<8, T>(M, pv, a.x, ypart, a.skip, s); break;
-    case 16: go_panel<16, T>(M, pv, a.x, ypart, a.skip, s); break;
-    case 32: go_panel<32, T>(M, pv, a.x, ypart, a.skip, s); break;
-    default: go_panel<64, T>(M, pv, a.x, ypart, a.skip, s); break;
-    }
+ck_status launch_panel_combine(const ck_matrix &M, const SpmvArgs<T> &a, const T *ypart,
+                               int64_t G_dot, hipStream_t s) {
     const bool beta = a.beta != T(0);
     const bool dot = a.cg != nullptr;
     const int64_t G = dot ? G_dot : std::min<int64_t>(ceil_div(M.n, 256), kRowBlocks);
@@ -275,9 +213,9 @@ ck_status launch_panel_spmv(const ck_matrix &M, const SpmvArgs<T> &a, T *ypart, 
     return CK_OK;
 }
 
-template ck_status launch_panel_spmv<double>(const ck_matrix &, const SpmvArgs<double> &,
-                                             double *, int64_t, hipStream_t);
-template ck_status launch_panel_spmv<float>(const ck_matrix &, const SpmvArgs<float> &, float *,
-                                            int64_t, hipStream_t);
+template ck_status launch_panel_combine<double>(const ck_matrix &, const SpmvArgs<double> &,
+                                                const double *, int64_t, hipStream_t);
+template ck_status launch_panel_combine<float>(const ck_matrix &, const SpmvArgs<float> &,
+                                               const float *, int64_t, hipStream_t);
 
 }  // namespace ck

@@ -1,11 +1,10 @@
-// CSR-panel SpMV (XCD-aware column panels), see panel.hip.
+// CSR-panel SpMV (XCD-aware column panels), see panel.hip.  G_dot = dot
+// partials for a fused CG step.
 #pragma once
 
 #include "matrix.hpp"
 
 namespace ck {
-
-constexpr int kPanelLanes = 4;   // lanes per panel row (panel rows are short)
 
 // panels for a vector of ncols entries of value_bytes each (x slice <= 2 MB)
 int panel_count_for(int64_t ncols, int value_bytes);
@@ -15,9 +14,9 @@ int64_t panel_scan_tmp_elems(int64_t N);
 ck_status launch_scan_exclusive(int64_t N, const int *in, int *out, int *tmp, hipStream_t s);
 ck_status launch_to_panel(const ck_matrix &M, int P, int64_t W, int *cnt, int *tmp, int *prp,
                           int *pcol, double *pval, float *pval32, hipStream_t s);
-// partial sums go to ypart (P * n values); G_dot = dot partials for a fused CG step
+// y = alpha * (sum of the P partial vectors, in panel order) + beta * y
 template <typename T>
-ck_status launch_panel_spmv(const ck_matrix &M, const SpmvArgs<T> &a, T *ypart, int64_t G_dot,
-                            hipStream_t s);
+ck_status launch_panel_combine(const ck_matrix &M, const SpmvArgs<T> &a, const T *ypart,
+                               int64_t G_dot, hipStream_t s);
 
 }  // namespace ck

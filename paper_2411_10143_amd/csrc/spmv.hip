@@ -320,23 +320,18 @@ __global__ __launch_bounds__(256) void merge_partition(int n, int nnz, int64_t Q
 // Rows cut by thread boundaries are completed in LDS, rows cut by workgroup
 // boundaries by carry_fixup.
 template <typename T, bool BETA>
-__global__ __launch_bounds__(256) void spmv_merge(int n, int nnz, int64_t G,
-                                                  const int *__restrict__ rp,
-                                                  const int *__restrict__ col,
-                                                  const T *__restrict__ val, T alpha,
-                                                  const T *__restrict__ x, T beta,
-                                                  T *__restrict__ y, int *__restrict__ crow_g,
-                                                  T *__restrict__ cval_g,
-                                                  const int *__restrict__ part,
-                                                  const int *__restrict__ skip) {
+__device__ __forceinline__ void merge_rows(int n, int nnz, int64_t G, const int *__restrict__ rp,
+                                           const int *__restrict__ col,
+                                           const T *__restrict__ val, T alpha,
+                                           const T *__restrict__ x, T beta, T *__restrict__ y,
+                                           int *__restrict__ crow_g, T *__restrict__ cval_g,
+                                           const int *__restrict__ part) {
     constexpr int ITEMS = 256 * kMergeIPT;
     __shared__ int s_crow[256];
     __shared__ T s_cval[256];
     __shared__ int s_rend[ITEMS + 1];   // ends of rows i0 .. i1 (local entry index + j0)
     __shared__ T s_prod[ITEMS];         // products of entries j0 .. j1-1
     __shared__ int s_coord[4];
-    if (skipped(skip))
-        return;
     const int64_t b = ck::xcd_block(G);
     if (b < 0)
         return;
@@ -439,6 +434,41 @@ __global__ __launch_bounds__(256) void spmv_merge(int n, int nnz, int64_t G,
         (int)min<int64_t>(255, (P - first_d + kMergeIPT - 1) / kMergeIPT - 1);
     finish_carries<T, BETA>(s_crow, s_cval, frow, fval, last_active, b, alpha, beta, y, crow_g,
                             cval_g);
+}
+
+template <typename T, bool BETA>
+__global__ __launch_bounds__(256) void spmv_merge(int n, int nnz, int64_t G,
+                                                  const int *__restrict__ rp,
+                                                  const int *__restrict__ col,
+                                                  const T *__restrict__ val, T alpha,
+                                                  const T *__restrict__ x, T beta,
+                                                  T *__restrict__ y, int *__restrict__ crow_g,
+                                                  T *__restrict__ cval_g,
+                                                  const int *__restrict__ part,
+                                                  const int *__restrict__ skip) {
+    if (skipped(skip))
+        return;
+    merge_rows<T, BETA>(n, nnz, G, rp, col, val, alpha, x, beta, y, crow_g, cval_g, part);
+}
+
+// CSR-panel products: the merge path over the panel-major arrays read as one
+// CSR of P*n rows, into the partial vectors (its own symbol, so profiles tell
+// it apart from CSR-merge).
+template <typename T>
+__global__ __launch_bounds__(256) void spmv_panel_merge(int rows, int nnz, int64_t G,
+                                                        const int *__restrict__ prp,
+                                                        const int *__restrict__ pcol,
+                                                        const T *__restrict__ pval,
+                                                        const T *__restrict__ x,
+                                                        T *__restrict__ ypart,
+                                                        int *__restrict__ crow_g,
+                                                        T *__restrict__ cval_g,
+                                                        const int *__restrict__ part,
+                                                        const int *__restrict__ skip) {
+    if (skipped(skip))
+        return;
+    merge_rows<T, false>(rows, nnz, G, prp, pcol, pval, T(1), x, T(0), ypart, crow_g, cval_g,
+                         part);
 }
 
 template <typename T, bool BETA>
@@ -610,22 +640,35 @@ static int64_t carry_blocks(const ck_matrix &M, const ck_config &c) {
 }
 
 int64_t spmv_carry_bytes(const ck_matrix &M, const ck_config &c, bool fp32) {
-    if (c.format == CK_FMT_CSR && c.algorithm == CK_ALG_PANEL)   // per-panel partial sums
-        return (int64_t)panel_count_for(M.ncols, 8) * M.n * (fp32 ? 4 : 8) + 256;
+    if (c.format == CK_FMT_CSR && c.algorithm == CK_ALG_PANEL) {
+        // per-panel partial sums, then (merge-path panels) the carries of the
+        // merge over the P*n panel rows
+        const int64_t rows = (int64_t)panel_count_for(M.ncols, 8) * M.n;
+        const int64_t Gt = ceil_div(rows + M.nnz, 256 * kMergeIPT);
+        return ((rows * (fp32 ? 4 : 8) + 255) / 256) * 256 +
+               ((Gt * (int64_t)sizeof(int) + 255) / 256) * 256 + Gt * (fp32 ? 4 : 8) + 256;
+    }
     const int64_t G = carry_blocks(M, c);
     return ((G * (int64_t)sizeof(int) + 255) / 256) * 256 + G * (fp32 ? 4 : 8) + 256;
 }
 
-int64_t merge_part_entries(const ck_matrix &M) {
-    return ceil_div(M.n + M.nnz, 256 * kMergeIPT) + 1;
+int64_t merge_part_entries_rows(int64_t rows, int64_t nnz) {
+    return ceil_div(rows + nnz, 256 * kMergeIPT) + 1;
+}
+
+int64_t merge_part_entries(const ck_matrix &M) { return merge_part_entries_rows(M.n, M.nnz); }
+
+ck_status launch_merge_partition_rows(int64_t rows, int64_t nnz, const int32_t *rp,
+                                      int32_t *part, hipStream_t s) {
+    const int64_t Q = merge_part_entries_rows(rows, nnz);
+    hipLaunchKernelGGL(merge_partition, dim3(ceil_div(Q, 256)), dim3(256), 0, s, (int)rows,
+                       (int)nnz, Q, rp, part);
+    CK_HIP(hipGetLastError());
+    return CK_OK;
 }
 
 ck_status launch_merge_partition(const ck_matrix &M, int32_t *part, hipStream_t s) {
-    const int64_t Q = merge_part_entries(M);
-    hipLaunchKernelGGL(merge_partition, dim3(ceil_div(Q, 256)), dim3(256), 0, s, (int)M.n,
-                       (int)M.nnz, Q, M.rp, part);
-    CK_HIP(hipGetLastError());
-    return CK_OK;
+    return launch_merge_partition_rows(M.n, M.nnz, M.rp, part, s);
 }
 
 ck_config default_config(int64_t n, int64_t nnz) {
@@ -662,7 +705,7 @@ const char *kernel_name(const ck_config &c, bool fp32) {
     if (c.algorithm == CK_ALG_MERGE)
         return fp32 ? "spmv_merge<float, false>" : "spmv_merge<double, false>";
     if (c.algorithm == CK_ALG_PANEL)
-        return fp32 ? "spmv_panel<4, float>" : "spmv_panel<4, double>";
+        return fp32 ? "spmv_panel_merge<float>" : "spmv_panel_merge<double>";
     int idx = 0;
     while ((1 << idx) < c.lanes)
         ++idx;
@@ -778,6 +821,36 @@ static ck_status dispatch_carry(const ck_matrix &M, const ck_config &c, const Sp
     return CK_OK;
 }
 
+// CSR-panel: the panel-major arrays are one CSR of P*n rows (panel p's row i
+// is row p*n + i), whose merge-path product writes the P partial vectors;
+// panel_combine then sums them in panel order.  Logical block ranges are
+// contiguous per XCD and a panel's rows are contiguous in the merged
+// sequence, so each XCD works through its own consecutive panels and their x
+// slices stay in its L2, while the merge balances hub rows.  (One to four
+// lanes per panel row instead measured 1.3-2.7x slower: the short panel rows
+// left the loads of a wave mostly idle and hub rows serialised.)
+template <typename T>
+static ck_status panel_merge_spmv(const ck_matrix &M, const SpmvArgs<T> &a, void *ws,
+                                  int64_t G_dot, hipStream_t s) {
+    const T *pv;
+    if constexpr (sizeof(T) == 4)
+        pv = M.panel_val32;
+    else
+        pv = M.panel_val;
+    const int64_t rows = (int64_t)M.panel_P * M.n;
+    const int64_t Gt = ceil_div(rows + M.nnz, 256 * kMergeIPT);
+    T *ypart = (T *)ws;
+    int *crow = (int *)((char *)ws + ((rows * (int64_t)sizeof(T) + 255) / 256) * 256);
+    T *cval = (T *)((char *)crow + ((Gt * (int64_t)sizeof(int) + 255) / 256) * 256);
+    hipLaunchKernelGGL((spmv_panel_merge<T>), dim3(xcd_grid(Gt)), dim3(256), 0, s, (int)rows,
+                       (int)M.nnz, Gt, M.panel_rp, M.panel_col, pv, a.x, ypart, crow, cval,
+                       M.panel_part, a.skip);
+    hipLaunchKernelGGL((carry_fixup<T>), dim3(ceil_div(Gt, 256)), dim3(256), 0, s, Gt, crow,
+                       cval, T(1), ypart, a.skip);
+    CK_HIP(hipGetLastError());
+    return launch_panel_combine<T>(M, a, ypart, G_dot, s);
+}
+
 template <typename T>
 ck_status launch_spmv(const ck_matrix &M, const ck_config &c, const SpmvArgs<T> &a,
                       hipStream_t s) {
@@ -809,7 +882,7 @@ ck_status launch_spmv(const ck_matrix &M, const ck_config &c, const SpmvArgs<T> 
         void *ws = a.carry;
         if (ws == nullptr)
             CK_HIP(hipMallocAsync(&ws, (size_t)spmv_carry_bytes(M, c, sizeof(T) == 4), s));
-        st = launch_panel_spmv<T>(M, a, (T *)ws, spmv_dot_blocks(M, c), s);
+        st = panel_merge_spmv<T>(M, a, ws, spmv_dot_blocks(M, c), s);
         if (a.carry == nullptr)
             CK_HIP(hipFreeAsync(ws, s));
     } else if (M.nnz == 0 && !dot) {

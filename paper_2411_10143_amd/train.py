@@ -200,9 +200,9 @@ def main(argv=None):
     fa = sub.add_parser("fit")
     fa.add_argument("--data", required=True, nargs="+")
     fa.add_argument("--model", required=True)
-    fa.add_argument("--max-depth", type=int, default=6)
-    fa.add_argument("--min-leaf", type=int, default=2)
-    fa.add_argument("--tie", type=float, default=0.04,
+    fa.add_argument("--max-depth", type=int, default=5)
+    fa.add_argument("--min-leaf", type=int, default=1)
+    fa.add_argument("--tie", type=float, default=0.02,
                     help="times within this fraction of the fastest count as ties")
     a = p.parse_args(argv)
     if a.cmd == "collect":

@@ -218,8 +218,8 @@ ck_status ck_default_config(ck_handle h, ck_config *out);
  * ascending list of rows longer than K (their entries K.. stay in the CSR
  * arrays).  A DIA product multiplies the +0.0 of an absent slot by x like
  * a stored value, so a non-finite x_j also reaches rows that store nothing
- * in column j.  Enqueued on s; DIA and HYB block on s once to read a count
- * back; the copy is usable by later work on s.  Idempotent. */
+ * in column j.  Runs on s and returns when the copy is built (it then
+ * serves any stream).  Idempotent. */
 ck_status spmv_convert(ck_handle h, const ck_config *cfg, hipStream_t s);
 
 /* ck_set_active / ck_get_active -- the configuration spmv_apply uses when

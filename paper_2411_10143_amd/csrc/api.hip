@@ -115,8 +115,18 @@ ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s, bool sym
     return CK_OK;
 }
 
+// A format copy is marked available only once every kernel that builds it
+// has finished: other threads use it at once on other streams (the request
+// loop's workers, a solve given the configuration), and a flag set at
+// enqueue time let them read half-built index arrays.
+static ck_status mark_built(std::atomic<bool> &flag, hipStream_t s) {
+    CK_HIP(hipStreamSynchronize(s));
+    flag.store(true);
+    return CK_OK;
+}
+
 // Builds the ELL, COO, DIA, HYB or CSR-panel copy (or the merge-path
-// partition) a configuration needs (idempotent).
+// partition) a configuration needs (idempotent); returns when it is built.
 ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
     if (!config_valid(c))
         return fail(CK_E_INVALID, "invalid SpMV configuration");
@@ -130,8 +140,7 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
             return CK_OK;
         CK_TRY(dev_alloc(&M.merge_part, merge_part_entries(M)));
         CK_TRY(launch_merge_partition(M, M.merge_part, s));
-        M.has_merge_part.store(true);
-        return CK_OK;
+        return mark_built(M.has_merge_part, s);
     }
     if (c.format == CK_FMT_CSR) {   // CSR-panel
         if (M.has_panel.load())
@@ -157,8 +166,7 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
         M.panel_W = W;
         CK_TRY(dev_alloc(&M.panel_part, merge_part_entries_rows(N, M.nnz)));
         CK_TRY(launch_merge_partition_rows(N, M.nnz, M.panel_rp, M.panel_part, s));
-        M.has_panel.store(true);
-        return CK_OK;
+        return mark_built(M.has_panel, s);
     }
     if (c.format == CK_FMT_DIA) {
         if (M.has_dia.load())
@@ -174,8 +182,7 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
             M.dia_val32 = nullptr;
             return st;
         }
-        M.has_dia.store(true);
-        return CK_OK;
+        return mark_built(M.has_dia, s);
     }
     if (c.format == CK_FMT_HYB) {
         if (M.has_hyb.load())
@@ -193,16 +200,14 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
             M.hyb_rows = nullptr;
             return st;
         }
-        M.has_hyb.store(true);
-        return CK_OK;
+        return mark_built(M.has_hyb, s);
     }
     if (c.format == CK_FMT_COO) {
         if (M.has_coo.load())
             return CK_OK;
         CK_TRY(dev_alloc(&M.coo_row, M.nnz));
         CK_TRY(launch_to_coo(M, M.coo_row, s));
-        M.has_coo.store(true);
-        return CK_OK;
+        return mark_built(M.has_coo, s);
     }
     if (M.has_ell.load())
         return CK_OK;
@@ -229,8 +234,7 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
     CK_TRY(launch_to_ell(M, K, pitch, M.ell_col, M.ell_val, M.ell_val32, s));
     M.ell_K = K;
     M.ell_pitch = pitch;
-    M.has_ell.store(true);
-    return CK_OK;
+    return mark_built(M.has_ell, s);
 }
 
 }  // namespace ck

@@ -320,3 +320,28 @@ def test_invalid_csr_rejected(ck):
     badrp[5] = rp[7]                      # row pointers not monotone
     with pytest.raises(ck.CkError):
         ck.spmv_create(badrp, col, val)
+
+
+@pytest.mark.parametrize("cid", [8, 9, 10, 11, 12, 13])
+def test_converted_copy_serves_another_stream_at_once(ck, orc, cid):
+    """spmv_convert returns when the copy is built, so a product on a
+    different stream right after it (no synchronisation in between) reads a
+    complete copy; the request loop relies on this when its scheduler
+    converts and a worker stream solves."""
+    import torch
+    A = M.uniform_random(200003, 31, 4, 40) if cid != 12 else M.banded_stencil(200003, 27, 31)
+    say(f"convert on one stream, product on another: config {ck.CONFIG_NAMES[cid]}")
+    Mx = ck.Matrix.from_csr(A)
+    x = np.random.default_rng(5).uniform(-1, 1, A.ncols)
+    dx = torch.from_numpy(x).cuda()
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    cfg = ck.config_from_id(cid)
+    dy = torch.empty(A.n, dtype=torch.float64, device="cuda")
+    torch.cuda.synchronize()
+    ck.spmv_convert(Mx.handle, cfg, stream=s1)
+    ck.spmv_apply(Mx.handle, dx, dy, 1.0, 0.0, cfg, stream=s2)
+    s2.synchronize()
+    ref = orc.spmv(A, x)
+    bound = spmv_bound(orc, A, x, 1.0, 0.0, None, U64, k_extra=4)
+    assert np.all(np.abs(dy.cpu().numpy() - ref) <= bound)
+    Mx.close()

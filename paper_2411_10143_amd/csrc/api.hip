@@ -6,6 +6,7 @@
 #include <limits>
 
 #include "matrix.hpp"
+#include "devcache.hpp"
 #include "diahyb.hpp"
 #include "panel.hpp"
 #include "predictor.hpp"
@@ -40,45 +41,32 @@ ck_status launch_to_ell(const ck_matrix &M, int64_t K, int64_t pitch, int *ecol,
                         float *evl32, hipStream_t s);
 ck_status launch_to_coo(const ck_matrix &M, int *row, hipStream_t s);
 
-template <typename T>
-static ck_status dev_alloc(T **p, int64_t count) {
-    *p = nullptr;
-    const size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
-    hipError_t e = hipMalloc((void **)p, bytes);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(CK_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-    }
-    return CK_OK;
-}
-
 static void release(ck_matrix *M) {
     if (!M)
         return;
-    (void)hipFree(M->rp);
-    (void)hipFree(M->col);
-    (void)hipFree(M->val);
-    (void)hipFree(M->val32);
-    (void)hipFree(M->ell_col);
-    (void)hipFree(M->ell_val);
-    (void)hipFree(M->ell_val32);
-    (void)hipFree(M->coo_row);
-    (void)hipFree(M->dia_off);
-    (void)hipFree(M->dia_val);
-    (void)hipFree(M->dia_val32);
-    (void)hipFree(M->hyb_col);
-    (void)hipFree(M->hyb_val);
-    (void)hipFree(M->hyb_val32);
-    (void)hipFree(M->hyb_rows);
-    (void)hipFree(M->panel_rp);
-    (void)hipFree(M->panel_col);
-    (void)hipFree(M->panel_val);
-    (void)hipFree(M->panel_val32);
-    (void)hipFree(M->merge_part);
-    (void)hipFree(M->panel_part);
+    dev_cache_free(M->rp);
+    dev_cache_free(M->col);
+    dev_cache_free(M->val);
+    dev_cache_free(M->val32);
+    dev_cache_free(M->ell_col);
+    dev_cache_free(M->ell_val);
+    dev_cache_free(M->ell_val32);
+    dev_cache_free(M->coo_row);
+    dev_cache_free(M->dia_off);
+    dev_cache_free(M->dia_val);
+    dev_cache_free(M->dia_val32);
+    dev_cache_free(M->hyb_col);
+    dev_cache_free(M->hyb_val);
+    dev_cache_free(M->hyb_val32);
+    dev_cache_free(M->hyb_rows);
+    dev_cache_free(M->panel_rp);
+    dev_cache_free(M->panel_col);
+    dev_cache_free(M->panel_val);
+    dev_cache_free(M->panel_val32);
+    dev_cache_free(M->merge_part);
+    dev_cache_free(M->panel_part);
     for (auto &kv : M->carry)
-        (void)hipFree(kv.second);
+        dev_cache_free(kv.second);
     delete M;
 }
 
@@ -174,9 +162,9 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
         const ck_status st = convert_to_dia(M, s);
         if (st != CK_OK) {   // refused for fill, or out of memory: leave no partial copy
             (void)hipStreamSynchronize(s);
-            (void)hipFree(M.dia_off);
-            (void)hipFree(M.dia_val);
-            (void)hipFree(M.dia_val32);
+            dev_cache_free(M.dia_off);
+            dev_cache_free(M.dia_val);
+            dev_cache_free(M.dia_val32);
             M.dia_off = nullptr;
             M.dia_val = nullptr;
             M.dia_val32 = nullptr;
@@ -190,10 +178,10 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
         const ck_status st = convert_to_hyb(M, s);
         if (st != CK_OK) {
             (void)hipStreamSynchronize(s);
-            (void)hipFree(M.hyb_col);
-            (void)hipFree(M.hyb_val);
-            (void)hipFree(M.hyb_val32);
-            (void)hipFree(M.hyb_rows);
+            dev_cache_free(M.hyb_col);
+            dev_cache_free(M.hyb_val);
+            dev_cache_free(M.hyb_val32);
+            dev_cache_free(M.hyb_rows);
             M.hyb_col = nullptr;
             M.hyb_val = nullptr;
             M.hyb_val32 = nullptr;
@@ -357,7 +345,8 @@ ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
             break;
         }
     } while (false);
-    (void)hipFree(bad);
+    (void)hipStreamSynchronize(s);   // nothing may still write the arrays
+    dev_cache_free(bad);
     if (st != CK_OK) {
         release(M);
         return st;

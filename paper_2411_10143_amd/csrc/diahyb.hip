@@ -21,6 +21,7 @@
 #include <climits>
 #include <vector>
 
+#include "devcache.hpp"
 #include "diahyb.hpp"
 #include "panel.hpp"
 #include "solvers.hpp"
@@ -235,19 +236,6 @@ ck_status launch_to_ell(const ck_matrix &M, int64_t K, int64_t pitch, int *ecol,
 
 namespace {
 
-template <typename T>
-ck_status alloc_n(T **p, int64_t count) {
-    *p = nullptr;
-    const size_t bytes = (size_t)(count > 0 ? count : 1) * sizeof(T);
-    const hipError_t e = hipMalloc((void **)p, bytes);
-    if (e != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return fail(CK_E_NOMEM, "hipMalloc(%zu) failed: %s", bytes, hipGetErrorString(e));
-    }
-    return CK_OK;
-}
-
 // Stream-ordered temporary that is released (stream-ordered) on scope exit.
 struct Tmp {
     hipStream_t s;
@@ -292,10 +280,10 @@ ck_status convert_to_dia(ck_matrix &M, hipStream_t s) {
     if (nd * pitch > 8 * M.nnz)
         return fail(CK_E_UNSUPPORTED, "DIA refused: %lld diagonals x %lld rows for %lld entries",
                     (long long)nd, (long long)pitch, (long long)M.nnz);
-    CK_TRY(alloc_n(&M.dia_off, nd));
-    CK_TRY(alloc_n(&M.dia_val, nd * pitch));
+    CK_TRY(dev_alloc(&M.dia_off, nd));
+    CK_TRY(dev_alloc(&M.dia_val, nd * pitch));
     if (M.val32)
-        CK_TRY(alloc_n(&M.dia_val32, nd * pitch));
+        CK_TRY(dev_alloc(&M.dia_val32, nd * pitch));
     if (nd > 0) {
         hipLaunchKernelGGL(dia_offsets, dim3(std::min<int64_t>(ceil_div(N, 256), 8192)), dim3(256),
                            0, s, N, n, flags, pos, M.dia_off);
@@ -349,11 +337,11 @@ ck_status convert_to_hyb(ck_matrix &M, hipStream_t s) {
         tail_nnz = M.nnz - ell_entries;
         nt = ge[K + 1];
     }
-    CK_TRY(alloc_n(&M.hyb_col, K * pitch));
-    CK_TRY(alloc_n(&M.hyb_val, K * pitch));
+    CK_TRY(dev_alloc(&M.hyb_col, K * pitch));
+    CK_TRY(dev_alloc(&M.hyb_val, K * pitch));
     if (M.val32)
-        CK_TRY(alloc_n(&M.hyb_val32, K * pitch));
-    CK_TRY(alloc_n(&M.hyb_rows, nt));
+        CK_TRY(dev_alloc(&M.hyb_val32, K * pitch));
+    CK_TRY(dev_alloc(&M.hyb_rows, nt));
     CK_TRY(launch_to_ell(M, K, pitch, M.hyb_col, M.hyb_val, M.hyb_val32, s));
     if (nt > 0) {
         Tmp tmp(s);

@@ -78,7 +78,7 @@ ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s, bool sym
     std::memset(&F, 0, sizeof F);
     const int64_t bytes = features_scratch_bytes(M.n, M.ncols);
     void *scratch = nullptr;
-    CK_HIP(hipMallocAsync(&scratch, (size_t)bytes, s));
+    CK_TRY(dev_cache_alloc(&scratch, (size_t)bytes));
     ck_status st = launch_features(M, scratch, symmetry, s);
     char acc[512];
     if (st == CK_OK) {
@@ -87,12 +87,11 @@ ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s, bool sym
         if (e != hipSuccess)
             st = fail(CK_E_HIP, "feature copy failed: %s", hipGetErrorString(e));
     }
-    const hipError_t ef = hipFreeAsync(scratch, s);
     const hipError_t es = hipStreamSynchronize(s);
+    dev_cache_free(scratch);   // the pass has finished with it
     CK_TRY(st);
-    if (ef != hipSuccess || es != hipSuccess)
-        return fail(CK_E_HIP, "feature pass failed: %s",
-                    hipGetErrorString(es != hipSuccess ? es : ef));
+    if (es != hipSuccess)
+        return fail(CK_E_HIP, "feature pass failed: %s", hipGetErrorString(es));
     int64_t ints[28];
     features_from_acc(acc, M, ints);
     if (!symmetry)
@@ -145,16 +144,20 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
             CK_TRY(dev_alloc(&M.panel_val32, M.nnz));
         int *tmp = nullptr;
         const int64_t tmp_elems = N + panel_scan_tmp_elems(N);
-        CK_HIP(hipMallocAsync((void **)&tmp, (size_t)tmp_elems * sizeof(int), s));
-        const ck_status st = launch_to_panel(M, P, W, tmp, tmp + N, M.panel_rp, M.panel_col,
-                                             M.panel_val, M.panel_val32, s);
-        CK_HIP(hipFreeAsync(tmp, s));
-        CK_TRY(st);
+        CK_TRY(dev_alloc(&tmp, tmp_elems));
+        ck_status st = launch_to_panel(M, P, W, tmp, tmp + N, M.panel_rp, M.panel_col,
+                                       M.panel_val, M.panel_val32, s);
         M.panel_P = P;
         M.panel_W = W;
-        CK_TRY(dev_alloc(&M.panel_part, merge_part_entries_rows(N, M.nnz)));
-        CK_TRY(launch_merge_partition_rows(N, M.nnz, M.panel_rp, M.panel_part, s));
-        return mark_built(M.has_panel, s);
+        if (st == CK_OK)
+            st = dev_alloc(&M.panel_part, merge_part_entries_rows(N, M.nnz));
+        if (st == CK_OK)
+            st = launch_merge_partition_rows(N, M.nnz, M.panel_rp, M.panel_part, s);
+        if (st == CK_OK)
+            st = mark_built(M.has_panel, s);
+        (void)hipStreamSynchronize(s);   // the conversion has finished with tmp
+        dev_cache_free(tmp);
+        return st;
     }
     if (c.format == CK_FMT_DIA) {
         if (M.has_dia.load())

@@ -236,14 +236,17 @@ ck_status launch_to_ell(const ck_matrix &M, int64_t K, int64_t pitch, int *ecol,
 
 namespace {
 
-// Stream-ordered temporary that is released (stream-ordered) on scope exit.
+// Temporary device memory of one conversion, returned to the handle-memory
+// cache once the conversion's stream has finished with it.
 struct Tmp {
     hipStream_t s;
     void *p = nullptr;
     explicit Tmp(hipStream_t st) : s(st) {}
     ~Tmp() {
-        if (p)
-            (void)hipFreeAsync(p, s);
+        if (p) {
+            (void)hipStreamSynchronize(s);
+            dev_cache_free(p);
+        }
     }
 };
 
@@ -265,7 +268,7 @@ ck_status convert_to_dia(ck_matrix &M, hipStream_t s) {
     const int64_t N = n + M.ncols - 1;   // offsets -(n-1) .. ncols-1
     if (n > 0 && M.nnz > 0) {
         const int64_t scan_tmp = panel_scan_tmp_elems(N);
-        CK_HIP(hipMallocAsync(&tmp.p, (size_t)(2 * N + 1 + scan_tmp) * sizeof(int), s));
+        CK_TRY(dev_cache_alloc(&tmp.p, (size_t)(2 * N + 1 + scan_tmp) * sizeof(int)));
         flags = (int *)tmp.p;
         pos = flags + N;
         CK_TRY(launch_fill<int>(N, flags, 0, s));
@@ -314,7 +317,7 @@ ck_status convert_to_hyb(ck_matrix &M, hipStream_t s) {
             return fail(CK_E_UNSUPPORTED, "HYB: rows too long");
         const int B = (int)(Kcap + 1);
         Tmp tmp(s);
-        CK_HIP(hipMallocAsync(&tmp.p, (size_t)B * sizeof(unsigned), s));
+        CK_TRY(dev_cache_alloc(&tmp.p, (size_t)B * sizeof(unsigned)));
         unsigned *hist = (unsigned *)tmp.p;
         CK_TRY(launch_fill<int>(B, (int *)hist, 0, s));
         hipLaunchKernelGGL(hyb_hist, dim3(std::min<int64_t>(ceil_div(n, 256), 2048)), dim3(256), 0,
@@ -346,7 +349,7 @@ ck_status convert_to_hyb(ck_matrix &M, hipStream_t s) {
     if (nt > 0) {
         Tmp tmp(s);
         const int64_t scan_tmp = panel_scan_tmp_elems(n);
-        CK_HIP(hipMallocAsync(&tmp.p, (size_t)(2 * n + 1 + scan_tmp) * sizeof(int), s));
+        CK_TRY(dev_cache_alloc(&tmp.p, (size_t)(2 * n + 1 + scan_tmp) * sizeof(int)));
         int *flag = (int *)tmp.p, *pos = flag + n;
         hipLaunchKernelGGL(hyb_long_flags, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, (int)K,
                            M.rp, flag);

@@ -168,8 +168,10 @@ ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
                       const int32_t *d_rowptr, const int32_t *d_col, const double *d_val,
                       uint32_t flags, hipStream_t s);
 
-/* spmv_destroy -- free every device copy.  The caller must have finished all
- * work that uses the handle.  NULL is ignored. */
+/* spmv_destroy -- release every device copy.  The caller must have finished
+ * all work that uses the handle (the memory goes back to a per-device cache,
+ * up to 16 GiB, from which later handles are served without mapping new
+ * pages; it is not synchronised again).  NULL is ignored. */
 void spmv_destroy(ck_handle h);
 
 /* spmv_features -- the 15 features of the feature table (Section III-B-1),

@@ -42,6 +42,10 @@ __global__ __launch_bounds__(256) void panel_count(int64_t n, int P, int64_t W,
 }
 
 // Panel-major copy: row i's panel-p entries go to prp[p*n + i] onwards.
+// Eight lanes per row, lane l taking panels l, l + 8, ...: a row's entries
+// of consecutive panels are consecutive (columns are sorted), so an
+// exclusive sum of the eight segment lengths gives each lane the start of its
+// segment, and the eight lanes read the row as one contiguous run.
 template <bool F32>
 __global__ __launch_bounds__(256) void panel_fill(int64_t n, int P, const int *__restrict__ rp,
                                                   const int *__restrict__ col,
@@ -49,19 +53,33 @@ __global__ __launch_bounds__(256) void panel_fill(int64_t n, int P, const int *_
                                                   const int *__restrict__ prp,
                                                   int *__restrict__ pcol, double *__restrict__ pval,
                                                   float *__restrict__ pval32) {
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    constexpr int L = 8;
+    const int lane = threadIdx.x & (L - 1);
+    const int64_t i = (int64_t)blockIdx.x * (256 / L) + threadIdx.x / L;
     if (i >= n)
-        return;
-    int k = rp[i];
-    for (int p = 0; p < P; ++p) {
-        const int dst0 = prp[(int64_t)p * n + i];
-        const int len = prp[(int64_t)p * n + i + 1] - dst0;
-        for (int t = 0; t < len; ++t, ++k) {
-            pcol[dst0 + t] = col[k];
-            pval[dst0 + t] = val[k];
-            if (F32)
-                pval32[dst0 + t] = (float)val[k];
+        return;   // whole groups leave together (8 divides the wave)
+    int base = rp[i];
+    for (int p0 = 0; p0 < P; p0 += L) {
+        const int64_t at = (int64_t)(p0 + lane) * n + i;
+        const int dst0 = prp[at];
+        const int len = prp[at + 1] - dst0;
+        int ex = len;   // inclusive scan over the group's lanes, then exclusive
+#pragma unroll
+        for (int off = 1; off < L; off <<= 1) {
+            const int o = __shfl_up(ex, off, L);
+            if (lane >= off)
+                ex += o;
         }
+        const int total = __shfl(ex, L - 1, L);
+        ex -= len;
+        const int src = base + ex;
+        for (int t = 0; t < len; ++t) {
+            pcol[dst0 + t] = col[src + t];
+            pval[dst0 + t] = val[src + t];
+            if (F32)
+                pval32[dst0 + t] = (float)val[src + t];
+        }
+        base += total;
     }
 }
 
@@ -183,11 +201,12 @@ ck_status launch_to_panel(const ck_matrix &M, int P, int64_t W, int *cnt, int *t
     const int64_t g = ceil_div(M.n, 256);
     hipLaunchKernelGGL(panel_count, dim3(g), dim3(256), 0, s, M.n, P, W, M.rp, M.col, cnt);
     CK_TRY(launch_scan_exclusive((int64_t)P * M.n, cnt, prp, tmp, s));
+    const int64_t g8 = ceil_div(M.n, 256 / 8);
     if (pval32)
-        hipLaunchKernelGGL((panel_fill<true>), dim3(g), dim3(256), 0, s, M.n, P, M.rp, M.col,
+        hipLaunchKernelGGL((panel_fill<true>), dim3(g8), dim3(256), 0, s, M.n, P, M.rp, M.col,
                            M.val, prp, pcol, pval, pval32);
     else
-        hipLaunchKernelGGL((panel_fill<false>), dim3(g), dim3(256), 0, s, M.n, P, M.rp, M.col,
+        hipLaunchKernelGGL((panel_fill<false>), dim3(g8), dim3(256), 0, s, M.n, P, M.rp, M.col,
                            M.val, prp, pcol, pval, pval32);
     CK_HIP(hipGetLastError());
     return CK_OK;

@@ -659,8 +659,9 @@ def main():
     p.add_argument("--tol", type=float, default=1e-8, help="serve: tolerance")
     args = p.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: this build runs on a single MI355X (the serving and "
-              "solver paths shard by request, not across GPUs); use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs on a single MI355X (its serving "
+              "and solver paths would shard by request, not across GPUs); use --gpus 1.",
+              file=sys.stderr)
         return 2
     {"spmv_set": bench_spmv_set, "cg_lap2d": bench_cg_lap2d, "cg_async": bench_cg_async,
      "gmres_mixed": bench_gmres_mixed, "serve": bench_serve}[args.workload](args)

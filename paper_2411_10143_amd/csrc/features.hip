@@ -8,8 +8,7 @@
 //               row-length histogram                           (reads rowptr, 2 cols/row)
 //   feat_nnz  : 8 lanes per row   -> longest run of consecutive columns,
 //               diagonal flags, main-diagonal count, symmetry  (reads col [+ val])
-//   feat_ndiag: count set diagonal flags (one bit per diagonal, so the
-//               flags of 2^22 diagonals take 512 KB and stay in L2)
+//   feat_ndiag: count set diagonal flags
 #include <algorithm>
 
 #include "matrix.hpp"
@@ -148,17 +147,16 @@ __device__ __forceinline__ Run run_join(const Run &A, const Run &B) {
 
 // Diagonal flags: a thread remembers the last kDiagMemo diagonals it set, so
 // a banded matrix (whose k-th entry of every row lies on the same diagonal)
-// touches its few flag words once per thread instead of once per entry; every
-// other entry reads its flag bit and sets it (atomicOr) only when clear.
-// Without this, all entries of a stencil matrix hammer the same few cache
-// lines.
+// touches its few flag bytes once per thread instead of once per entry; every
+// other entry reads its flag before setting it.  Without this, all entries of
+// a stencil matrix hammer the same few cache lines.
 constexpr int kDiagMemo = 4;
 
 template <bool SYM>
 __global__ __launch_bounds__(256) void feat_nnz(int64_t n, const int *__restrict__ rp,
                                                 const int *__restrict__ col,
                                                 const double *__restrict__ val,
-                                                unsigned *__restrict__ diag_flag,
+                                                unsigned char *__restrict__ diag_flag,
                                                 FeatAcc *acc) {
     constexpr int L = 8;
     __shared__ unsigned long long part[3][4];
@@ -202,9 +200,8 @@ __global__ __launch_bounds__(256) void feat_nnz(int64_t n, const int *__restrict
                 for (int m = 0; m < kDiagMemo; ++m)
                     seen |= memo[m] == d;
                 if (!seen) {
-                    const unsigned bit = 1u << (d & 31);
-                    if ((diag_flag[d >> 5] & bit) == 0)
-                        atomicOr(&diag_flag[d >> 5], bit);
+                    if (diag_flag[d] == 0)
+                        diag_flag[d] = 1;
 #pragma unroll
                     for (int m = 0; m < kDiagMemo; ++m)
                         if (m == slot)
@@ -268,12 +265,12 @@ __global__ __launch_bounds__(256) void feat_nnz(int64_t n, const int *__restrict
     }
 }
 
-__global__ __launch_bounds__(256) void feat_ndiag(int64_t words, const unsigned *__restrict__ f,
+__global__ __launch_bounds__(256) void feat_ndiag(int64_t nd, const unsigned char *__restrict__ f,
                                                   FeatAcc *acc) {
     unsigned long long c = 0;
-    for (int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x; w < words;
-         w += (int64_t)gridDim.x * 256)
-        c += __popc(f[w]);
+    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < nd;
+         d += (int64_t)gridDim.x * 256)
+        c += f[d];
     c = ck::wave_sum(c);
     if ((threadIdx.x & 63) == 0 && c)
         atomicAdd(&acc->ndiag, c);
@@ -383,14 +380,12 @@ int64_t features_scratch_bytes(int64_t n, int64_t ncols) {
 
 ck_status launch_features(const ck_matrix &M, void *scratch, bool symmetry, hipStream_t s) {
     const int64_t nd = M.n + M.ncols - 1;
-    const int64_t words = nd > 0 ? ceil_div(nd, 32) : 0;   // one bit per diagonal
-    unsigned *flags = (unsigned *)scratch;
+    unsigned char *flags = (unsigned char *)scratch;
     FeatAcc *acc = (FeatAcc *)((char *)scratch + ((M.n + M.ncols + 255) / 256) * 256);
     hipLaunchKernelGGL(feat_init, dim3(1), dim3(64), 0, s, acc);
-    if (words > 0) {
-        const int64_t g = std::min<int64_t>(ceil_div(4 * words, 256), 8192);
-        hipLaunchKernelGGL((fill_u8), dim3(g), dim3(256), 0, s, 4 * words,
-                           (unsigned char *)flags);
+    if (nd > 0) {
+        const int64_t g = std::min<int64_t>(ceil_div(nd, 256), 8192);
+        hipLaunchKernelGGL((fill_u8), dim3(g), dim3(256), 0, s, nd, flags);
     }
     if (M.n > 0) {
         hipLaunchKernelGGL(feat_rows, dim3(std::min<int64_t>(ceil_div(M.n, 256), 2048)), dim3(256),
@@ -402,9 +397,8 @@ ck_status launch_features(const ck_matrix &M, void *scratch, bool symmetry, hipS
         else
             hipLaunchKernelGGL((feat_nnz<false>), dim3(G), dim3(256), 0, s, M.n, M.rp, M.col,
                                M.val, flags, acc);
-        const int64_t g = std::min<int64_t>(ceil_div(words, 256), 4096);
-        hipLaunchKernelGGL(feat_ndiag, dim3(std::max<int64_t>(g, 1)), dim3(256), 0, s, words, flags,
-                           acc);
+        const int64_t g = std::min<int64_t>(ceil_div(nd, 256), 4096);
+        hipLaunchKernelGGL(feat_ndiag, dim3(g), dim3(256), 0, s, nd, flags, acc);
     }
     CK_HIP(hipGetLastError());
     return CK_OK;

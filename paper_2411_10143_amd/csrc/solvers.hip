@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "batched.hpp"
+#include "devcache.hpp"
 #include "matrix.hpp"
 #include "panel.hpp"
 #include "predictor.hpp"
@@ -37,7 +38,8 @@ double us_since(Clock::time_point t0) {
 }
 
 // ---------------------------------------------------------------------------
-// Device workspace owned by one solve (freed in stream order at the end).
+// Device workspace owned by one solve, from the handle-memory cache; it goes
+// back once the solve's stream has finished with it.
 struct Workspace {
     hipStream_t s;
     std::vector<void *> blocks;
@@ -45,19 +47,17 @@ struct Workspace {
     template <typename T>
     ck_status get(T **p, int64_t count) {
         void *q = nullptr;
-        const size_t bytes = (size_t)std::max<int64_t>(count, 1) * sizeof(T);
-        hipError_t e = hipMallocAsync(&q, bytes, s);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return fail(CK_E_NOMEM, "workspace allocation of %zu bytes failed", bytes);
-        }
+        CK_TRY(dev_cache_alloc(&q, (size_t)std::max<int64_t>(count, 1) * sizeof(T)));
         blocks.push_back(q);
         *p = (T *)q;
         return CK_OK;
     }
     ~Workspace() {
+        if (blocks.empty())
+            return;
+        (void)hipStreamSynchronize(s);
         for (void *q : blocks)
-            (void)hipFreeAsync(q, s);
+            dev_cache_free(q);
     }
 };
 
@@ -135,6 +135,18 @@ double remaining_iterations(int t0, double r0, int t1, double r1, double tol) {
 
 namespace {
 
+// Side streams (with their conversion events) of finished executors, kept
+// per device for the next solve: creating and destroying a stream per solve
+// costs as much as the feature pass of a mid-size matrix.
+struct SideStreams {
+    std::mutex mu;
+    std::map<int, std::vector<std::pair<hipStream_t, hipEvent_t>>> idle;
+};
+SideStreams &side_streams() {
+    static SideStreams *p = new SideStreams();   // never destroyed: outlives every solve
+    return *p;
+}
+
 class AsyncExec {
   public:
     AsyncExec(ck_matrix &M, const ck_config &start, bool gate)
@@ -147,8 +159,20 @@ class AsyncExec {
     ~AsyncExec() { finish(); }
 
     ck_status start() {
-        CK_HIP(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
-        CK_HIP(hipEventCreateWithFlags(&conv_done_, hipEventDisableTiming));
+        {
+            SideStreams &ss = side_streams();
+            std::lock_guard<std::mutex> lk(ss.mu);
+            auto &v = ss.idle[M_.device];
+            if (!v.empty()) {
+                side_ = v.back().first;
+                conv_done_ = v.back().second;
+                v.pop_back();
+            }
+        }
+        if (!side_)
+            CK_HIP(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
+        if (!conv_done_)
+            CK_HIP(hipEventCreateWithFlags(&conv_done_, hipEventDisableTiming));
         worker_ = std::thread([this] { run(); });
         return CK_OK;
     }
@@ -199,15 +223,18 @@ class AsyncExec {
         cancel_.store(true);
         if (worker_.joinable())
             worker_.join();
-        if (side_) {
-            (void)hipStreamSynchronize(side_);
-            (void)hipStreamDestroy(side_);
-            side_ = nullptr;
+        if (side_ && conv_done_ && hipStreamSynchronize(side_) == hipSuccess) {
+            SideStreams &ss = side_streams();
+            std::lock_guard<std::mutex> lk(ss.mu);
+            ss.idle[M_.device].emplace_back(side_, conv_done_);
+        } else {
+            if (side_)
+                (void)hipStreamDestroy(side_);
+            if (conv_done_)
+                (void)hipEventDestroy(conv_done_);
         }
-        if (conv_done_) {
-            (void)hipEventDestroy(conv_done_);
-            conv_done_ = nullptr;
-        }
+        side_ = nullptr;
+        conv_done_ = nullptr;
     }
 
     double t_features = 0, t_infer = 0, t_convert = 0;

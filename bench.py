@@ -600,14 +600,14 @@ def bench_serve(args):
     log(f"[serve] pool of {len(pool)} matrices generated in {time.time() - t0:.0f}s; "
         f"n from {min(A.n for A, _ in pool)} to {max(A.n for A, _ in pool)}")
     Wl = ServingWorkload(pool, args.requests, tol=args.tol, precision=ck.CK_PREC_MIXED,
-                         budget_bytes=64 << 30, max_slots=256, chunk_iters=32, small_n=32768,
-                         large_workers=4)
+                         budget_bytes=64 << 30, max_slots=256, chunk_iters=32,
+                         small_n=args.small_n, large_workers=args.large_workers)
     log(f"[serve] {args.requests} requests prepared")
     # closed loop: capacity C (also warms the prediction cache and residency)
     prog = lambda m: log(f"[serve] {m}")
     cap = latency_summary(Wl.run(progress=prog))
     log(f"[serve] closed loop: {cap['solves_per_s']:.1f} solves/s")
-    rate = 0.8 * cap["solves_per_s"]
+    rate = args.rate if args.rate else 0.8 * cap["solves_per_s"]
     runs = []
     for s in range(args.steps):
         done = Wl.run(arrivals_s=poisson_arrivals(args.requests, rate, seed=5001 + s),
@@ -623,9 +623,10 @@ def bench_serve(args):
     mean_sps = float(np.mean([r[0]["solves_per_s"] for r in runs]))
     _solve_json(args, mean_sps, "solves/s",
                 1e3 * float(np.mean([r[0]["makespan_s"] for r in runs])),
-                f"serve: {args.requests} requests, Poisson arrivals at 0.8x closed-loop "
-                f"capacity, 64-matrix pool (n log-uniform 1e3-1e6), CG if symmetric else "
-                f"GMRES(30), mixed FP32/FP64, tol {args.tol:g}, batched slots for n <= 32768",
+                f"serve: {args.requests} requests, Poisson arrivals at "
+                f"{f'{rate:g}/s' if args.rate else '0.8x closed-loop capacity'}, 64-matrix pool (n log-uniform 1e3-1e6), CG if symmetric else "
+                f"GMRES(30), mixed FP32/FP64, tol {args.tol:g}, batched slots for n <= {args.small_n}, "
+                f"{args.large_workers} large-system workers",
                 {"latency_ms": {"p50": round(summ["p50_ms"], 3), "p99": round(summ["p99_ms"], 3),
                                 "mean": round(summ["mean_ms"], 3)},
                  "closed_loop_solves_per_s": round(cap["solves_per_s"], 3),
@@ -657,6 +658,11 @@ def main():
     p.add_argument("--grid", type=int, default=1024, help="gmres_mixed grid side")
     p.add_argument("--requests", type=int, default=2000, help="serve: requests per trace")
     p.add_argument("--tol", type=float, default=1e-8, help="serve: tolerance")
+    p.add_argument("--small-n", type=int, default=32768,
+                   help="serve: systems with n <= this run in batched slots")
+    p.add_argument("--large-workers", type=int, default=4, help="serve: concurrent large solves")
+    p.add_argument("--rate", type=float, default=None,
+                   help="serve: fixed arrival rate (solves/s) instead of 0.8x closed-loop capacity")
     args = p.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the library runs on a single MI355X (its serving "

@@ -348,7 +348,10 @@ ck_status ck_time_spmv(ck_handle h, const ck_config *cfg, int32_t fp32, const vo
  * batched kernel (n <= small_n: one workgroup per system, chunk_iters
  * iterations per launch, new requests joining between launches) or as a
  * full cg_solve / gmres_solve on a worker stream.  Symmetric matrices are
- * solved with CG, the others with GMRES(restart).  x0 = 0. */
+ * solved with CG, the others with GMRES(restart).  x0 = 0.  Admission is in
+ * arrival order within each of the two paths; a request waiting only for a
+ * free slot or worker does not hold back the other path, and one waiting for
+ * memory holds back both. */
 typedef struct ck_server *ck_server_t;
 
 typedef struct {

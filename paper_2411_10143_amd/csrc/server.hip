@@ -2,9 +2,12 @@
 // resident matrices with a per-matrix prediction cache).
 //
 // A scheduler thread owns the device-side state:
-//   - requests wait in a FIFO until their matrix is resident and their
-//     workspace fits the memory budget (least-recently-used idle matrices are
-//     evicted to make room; a request that still does not fit waits);
+//   - requests wait in arrival order until their matrix is resident and
+//     their workspace fits the memory budget (least-recently-used idle
+//     matrices are evicted to make room; a request that still does not fit
+//     waits, and nothing behind it is admitted meanwhile).  Small and large
+//     requests are FIFO within their class, but a request waiting only for a
+//     slot (small) or a worker (large) does not hold back the other class;
 //   - the first request on a matrix runs GPU features + the cascade once; the
 //     decision (configuration, symmetric or not) is cached for the matrix;
 //   - small systems (n <= small_n) take a slot of the batched chunk kernel,
@@ -205,8 +208,12 @@ int lanes_for(const MatEntry &e) {
     return default_config(e.n, e.nnz).lanes;
 }
 
-// Tries to admit the head request; returns false if it has to wait.
-bool admit_one(ck_server &S, Request *r) {
+enum Admit { ADMITTED, WAIT_CLASS, WAIT_MEMORY };
+
+// Tries to admit a request.  WAIT_CLASS: every slot (small) or worker (large)
+// is taken; WAIT_MEMORY: the matrix or the workspace does not fit the budget
+// (or an allocation failed), so no later request may pass it.
+Admit admit_one(ck_server &S, Request *r) {
     MatEntry &e = S.mats[r->matrix];
     const bool small = e.n <= S.o.small_n;
     int slot = -1;
@@ -217,16 +224,16 @@ bool admit_one(ck_server &S, Request *r) {
                 break;
             }
         if (slot < 0)
-            return false;
+            return WAIT_CLASS;
     } else if (S.large_running >= S.o.large_workers) {
-        return false;
+        return WAIT_CLASS;
     }
     // prediction first (needs the matrix), then the request's own workspace
     if (ensure_resident(S, e, 0) != CK_OK)
-        return false;
+        return WAIT_MEMORY;
     const int64_t need = request_bytes(S, e, small);
     if (S.bytes_in_use + need > S.o.budget_bytes)
-        return false;
+        return WAIT_MEMORY;
     r->bytes = need;
     r->t_admit = S.now();
     S.bytes_in_use += need;
@@ -237,7 +244,7 @@ bool admit_one(ck_server &S, Request *r) {
         std::lock_guard<std::mutex> lk(S.lq_mu);
         S.large_q.push_back(r);
         S.lq_cv.notify_one();
-        return true;
+        return ADMITTED;
     }
     // batched slot: workspace + slot record
     const int m = std::min(S.o.restart > 0 ? S.o.restart : 30, kBMaxM);
@@ -248,10 +255,13 @@ bool admit_one(ck_server &S, Request *r) {
                        S.stream) != hipSuccess ||
         hipMallocAsync((void **)&r->r64, (size_t)ld * 8, S.stream) != hipSuccess) {
         (void)hipGetLastError();
+        if (r->work)
+            (void)hipFreeAsync(r->work, S.stream);
+        r->work = nullptr;
         S.bytes_in_use -= need;
         e.in_flight -= 1;
         S.st.in_flight -= 1;
-        return false;
+        return WAIT_MEMORY;
     }
     BSlot &b = S.slot_init[slot];
     std::memset(&b, 0, sizeof b);
@@ -274,11 +284,21 @@ bool admit_one(ck_server &S, Request *r) {
     b.inner_cap = std::max(50, (int)(4.0 * std::sqrt((double)e.n)));
     b.phase = B_OUTER;
     b.status = RUN;
-    if (hipMemcpyAsync(S.slots + slot, &b, sizeof b, hipMemcpyHostToDevice, S.stream) != hipSuccess)
-        return false;
+    if (hipMemcpyAsync(S.slots + slot, &b, sizeof b, hipMemcpyHostToDevice, S.stream) !=
+        hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipFreeAsync(r->work, S.stream);
+        (void)hipFreeAsync(r->r64, S.stream);
+        r->work = nullptr;
+        r->r64 = nullptr;
+        S.bytes_in_use -= need;
+        e.in_flight -= 1;
+        S.st.in_flight -= 1;
+        return WAIT_MEMORY;
+    }
     S.slot_req[slot] = r;
     r->slot = slot;
-    return true;
+    return ADMITTED;
 }
 
 void scheduler(ck_server *Sp) {
@@ -301,17 +321,32 @@ void scheduler(ck_server *Sp) {
             }
             S.st.queued = (int64_t)S.pending.size();
         }
-        // admit in arrival order while slots, workers and memory allow
-        while (!S.pending.empty()) {
-            Request *r = S.pending.front();
-            bool ok;
+        // admit in arrival order while slots, workers and memory allow; a
+        // class whose oldest request waits for a slot or a worker admits
+        // nothing more, the other class goes on, and a request waiting for
+        // memory stops both
+        bool blocked[2] = {false, false};
+        for (auto it = S.pending.begin(); it != S.pending.end() && !(blocked[0] && blocked[1]);) {
+            Request *r = *it;
+            Admit a;
+            int cls;
             {
                 std::lock_guard<std::mutex> lk(S.mu);
-                ok = admit_one(S, r);
+                cls = S.mats.at(r->matrix).n <= S.o.small_n ? 0 : 1;
+                a = blocked[cls] ? WAIT_CLASS : admit_one(S, r);
             }
-            if (!ok)
+            if (blocked[cls]) {
+                ++it;
+                continue;
+            }
+            if (a == ADMITTED)
+                it = S.pending.erase(it);
+            else if (a == WAIT_MEMORY)
                 break;
-            S.pending.pop_front();
+            else {
+                blocked[cls] = true;
+                ++it;
+            }
         }
         // one batched launch over the occupied slots
         int na = 0;

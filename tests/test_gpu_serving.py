@@ -95,3 +95,32 @@ def test_poisson_arrivals_latency(ck):
     lat = latency_summary(W.run(arrivals_s=arr))
     assert lat["ok"] == 40 and lat["p99_ms"] >= lat["p50_ms"] > 0
     W.close()
+
+
+def test_small_requests_pass_a_waiting_large_one(ck, orc):
+    from paper_2411_10143_amd.serving import ServingWorkload
+    say("serving admission classes")
+    # one worker for large systems: the second large request waits for the
+    # first to finish, and the small requests queued behind it are admitted
+    # to batched slots meanwhile (each class stays in arrival order)
+    pool = [(M.laplacian_2d(150), True), (M.laplacian_2d(20), True)]
+    W = ServingWorkload(pool, 40, seed=11, tol=1e-10, precision=0, small_n=4096,
+                        max_slots=16, chunk_iters=8, large_workers=1)
+    large = [t for t in range(len(W.mid)) if W.mid[t] == 0][:2]
+    small = [t for t in range(len(W.mid)) if W.mid[t] == 1][:6]
+    assert len(large) == 2 and len(small) == 6
+    W.run(which=[large[0]])            # makes both matrices resident and predicted
+    W.run(which=[small[0]])
+    done = {c["tag"]: c for c in W.run(which=large + small)}
+    assert all(c["status"] == ck.CK_OK for c in done.values())
+    for t in large + small:
+        A = pool[W.mid[t]][0]
+        assert orc.relres(A, W.b[t].cpu().numpy(), W.x[t].cpu().numpy()) <= 1e-10
+    second = done[large[1]]
+    assert second["t_admit_us"] > done[large[0]]["t_admit_us"]
+    for t in small:
+        assert done[t]["path"] == 0
+        assert done[t]["t_admit_us"] < second["t_admit_us"], (done[t], second)
+    adm = [done[t]["t_admit_us"] for t in small]
+    assert adm == sorted(adm)          # FIFO within the class
+    W.close()

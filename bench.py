@@ -658,9 +658,9 @@ def main():
     p.add_argument("--grid", type=int, default=1024, help="gmres_mixed grid side")
     p.add_argument("--requests", type=int, default=2000, help="serve: requests per trace")
     p.add_argument("--tol", type=float, default=1e-8, help="serve: tolerance")
-    p.add_argument("--small-n", type=int, default=32768,
+    p.add_argument("--small-n", type=int, default=8192,
                    help="serve: systems with n <= this run in batched slots")
-    p.add_argument("--large-workers", type=int, default=4, help="serve: concurrent large solves")
+    p.add_argument("--large-workers", type=int, default=8, help="serve: concurrent large solves")
     p.add_argument("--rate", type=float, default=None,
                    help="serve: fixed arrival rate (solves/s) instead of 0.8x closed-loop capacity")
     args = p.parse_args()

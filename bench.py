@@ -239,14 +239,21 @@ def bench_spmv_set(args):
     if not args.no_cpu_baseline:
         import oracle
         xs = [d["x"].cpu().numpy() for d in dev]
+        # whole passes over the set (one product per matrix each) until about
+        # 10 s of CPU time have been spent
+        passes = 0
         tc = time.perf_counter()
-        for A, x in zip(mats, xs):
-            oracle.spmv(A, x)
+        while passes == 0 or (time.perf_counter() - tc < 10.0 and passes < 200):
+            for A, x in zip(mats, xs):
+                oracle.spmv(A, x)
+            passes += 1
         dt = time.perf_counter() - tc
-        cpu = dict(value=round(sum(nbytes) / dt / 1e9, 3), unit="GB/s", cores=1, kind="oracle",
-                   sample=f"one FP64 product per matrix of the {len(mats)}-matrix set "
-                          f"({sum(nbytes) / 1e9:.2f} GB algorithmic), single-threaded plain C, "
-                          f"{dt:.1f} s; host has {os.cpu_count()} logical CPUs")
+        cpu = dict(value=round(passes * sum(nbytes) / dt / 1e9, 3), unit="GB/s", cores=1,
+                   kind="oracle",
+                   sample=f"{passes} passes of one FP64 product per matrix of the "
+                          f"{len(mats)}-matrix set ({sum(nbytes) / 1e9:.2f} GB algorithmic per "
+                          f"pass), single-threaded plain C, {dt:.1f} s; host has "
+                          f"{os.cpu_count()} logical CPUs")
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
@@ -381,7 +388,7 @@ def bench_cg_lap2d(args):
         bh = b.cpu().numpy()
         tc = time.perf_counter()
         n = 0
-        while time.perf_counter() - tc < 2.0:
+        while time.perf_counter() - tc < 10.0:
             oracle.cg(A, bh, tol=1e-10)
             n += 1
         dt = time.perf_counter() - tc

@@ -453,8 +453,8 @@ def bench_cg_async(args):
         b = _rhs(ck, probe, xs)
         best_id, _ = _best_fixed_config(ck, probe, A)
         probe.close()
-        res = {"async": [], "async_overhead_aware": [], "sequential": [], "default": [],
-               "best_fixed": []}
+        res = {"async": [], "async_overhead_aware": [], "async_known_start": [],
+               "sequential": [], "default": [], "known_start": [], "best_fixed": []}
         for s in range(args.warmup + args.steps):
             for mode in res:
                 Mx = ck.Matrix(rp, col, val)        # fresh handle: nothing cached
@@ -464,6 +464,11 @@ def bench_cg_async(args):
                 elif mode == "async_overhead_aware":
                     kw["async_"] = ck.CK_EXEC_ASYNC
                     kw["overhead_aware"] = True
+                elif mode == "async_known_start":
+                    kw["async_"] = ck.CK_EXEC_ASYNC
+                    kw["known_start"] = True
+                elif mode == "known_start":
+                    kw["known_start"] = True
                 elif mode == "sequential":
                     kw["async_"] = ck.CK_EXEC_SEQUENTIAL
                 elif mode == "best_fixed":
@@ -491,6 +496,9 @@ def bench_cg_async(args):
                      "async_solves_per_s": round(len(a) / t_async, 3),
                      "async_overhead_aware_solves_per_s": round(len(res["async_overhead_aware"]) / sum(r["wall_s"] for r in res["async_overhead_aware"]), 3),
                      "overhead_gate": {k: res["async_overhead_aware"][-1][k] for k in ("conversion_gated", "est_remaining_iters", "switch_iter")},
+                     "async_known_start_solves_per_s": round(len(res["async_known_start"]) / sum(r["wall_s"] for r in res["async_known_start"]), 3),
+                     "known_start_solves_per_s": round(len(res["known_start"]) / sum(r["wall_s"] for r in res["known_start"]), 3),
+                     "known_start_config": ck.CONFIG_NAMES[ck.config_id(ck.start_config(A.n, A.ncols, A.nnz)[0])],
                      "sequential_solves_per_s": round(len(res["sequential"]) / sum(r["wall_s"] for r in res["sequential"]), 3),
                      "sequential_prep_us": round(sum(res["sequential"][-1][k] for k in ("t_features_us", "t_infer_us", "t_convert_us")), 1),
                      "default_solves_per_s": round(len(res["default"]) / sum(r["wall_s"] for r in res["default"]), 3),

@@ -135,6 +135,9 @@ typedef struct {
                               format only if the remaining iterations,
                               extrapolated from the residual's decay, can
                               repay the conversion (see below)              */
+    int32_t known_start;   /* CK_EXEC_DEFAULT / _ASYNC: start from the start
+                              tree's configuration (ck_start_config) instead
+                              of the default one                           */
 } ck_solve_opts;
 
 typedef struct {
@@ -199,6 +202,17 @@ ck_status ck_select_stages(const ck_features *f, const char *model_path, int32_t
  * part of the configuration with predicting all three). */
 ck_status ck_eval_stage(const ck_features *f, const char *model_path, int32_t stage,
                         int32_t *cls);
+
+/* ck_start_config -- the starting configuration from the inputs known
+ * without a pass over the entries (nrows, ncols, nnz, density, mean row
+ * length): the model's optional "start" tree, which names one of the CSR
+ * configurations that need no copy of the matrix (ids 0..8: CSR-vector,
+ * CSR-scalar, CSR-merge).  Without a start tree in the model, or for
+ * nrows = 0, the default configuration below.  *from_tree (may be NULL) = 1
+ * if the tree decided.  A known-features-only first stage, as the paper's
+ * related work discusses for cheap, early decisions (Sections II-B, V). */
+ck_status ck_start_config(int64_t nrows, int64_t ncols, int64_t nnz, const char *model_path,
+                          ck_config *out, int32_t *from_tree);
 
 /* ck_default_config -- the configuration a solve starts from before any
  * prediction: CSR-vector with lanes = clamp(2^floor(log2(max(1, nnz/nrows))),

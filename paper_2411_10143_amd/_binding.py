@@ -86,7 +86,8 @@ class Features(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("restart", C.c_int32),
                 ("precision", C.c_int32), ("async_", C.c_int32), ("check_every", C.c_int32),
-                ("use_config", C.c_int32), ("config", Config), ("overhead_aware", C.c_int32)]
+                ("use_config", C.c_int32), ("config", Config), ("overhead_aware", C.c_int32),
+                ("known_start", C.c_int32)]
 
 
 class SolveResult(C.Structure):
@@ -146,6 +147,8 @@ SIGNATURES = {
     "spmv_select": (_i32, [C.POINTER(Features), C.c_char_p, C.POINTER(Config)]),
     "ck_select_stages": (_i32, [C.POINTER(Features), C.c_char_p, C.POINTER(_i32)]),
     "ck_default_config": (_i32, [_vp, C.POINTER(Config)]),
+    "ck_start_config": (_i32, [C.c_int64, C.c_int64, C.c_int64, C.c_char_p, C.POINTER(Config),
+                               C.POINTER(_i32)]),
     "spmv_convert": (_i32, [_vp, C.POINTER(Config), _vp]),
     "ck_set_active": (_i32, [_vp, C.POINTER(Config)]),
     "ck_get_active": (_i32, [_vp, C.POINTER(Config)]),
@@ -295,6 +298,15 @@ def overhead_gate(features, target, t0, r0, t1, r1, tol):
     return rem.value, cost.value, bool(go.value)
 
 
+def start_config(nrows, ncols, nnz, model_path=None):
+    """(configuration, from_tree) a solve with known_start begins on: the
+    model's start tree over the inputs known without a pass over the entries."""
+    c, ft = Config(), _i32()
+    mp = model_path.encode() if model_path else None
+    _check(lib().ck_start_config(int(nrows), int(ncols), int(nnz), mp, C.byref(c), C.byref(ft)))
+    return c, bool(ft.value)
+
+
 def default_config(h):
     c = Config()
     _check(lib().ck_default_config(h, C.byref(c)))
@@ -329,9 +341,11 @@ def spmv_apply_f32(h, x, y, alpha=1.0, beta=0.0, cfg=None, stream=None):
                                 _stream(stream)))
 
 
-def _opts(tol, max_iter, restart, precision, async_, check_every, cfg, overhead_aware=False):
+def _opts(tol, max_iter, restart, precision, async_, check_every, cfg, overhead_aware=False,
+          known_start=False):
     o = SolveOpts()
     o.overhead_aware = int(overhead_aware)
+    o.known_start = int(known_start)
     o.tol = tol
     o.max_iter = max_iter
     o.restart = restart
@@ -345,9 +359,10 @@ def _opts(tol, max_iter, restart, precision, async_, check_every, cfg, overhead_
 
 
 def _solve(fn, h, b, x, tol, max_iter, restart, precision, async_, check_every, cfg, stream,
-           raise_on_error, overhead_aware=False):
+           raise_on_error, overhead_aware=False, known_start=False):
     import torch
-    o = _opts(tol, max_iter, restart, precision, async_, check_every, cfg, overhead_aware)
+    o = _opts(tol, max_iter, restart, precision, async_, check_every, cfg, overhead_aware,
+              known_start)
     r = SolveResult()
     st = fn(h, _ptr(b, torch.float64), _ptr(x, torch.float64), C.byref(o), C.byref(r),
             _stream(stream))
@@ -358,18 +373,18 @@ def _solve(fn, h, b, x, tol, max_iter, restart, precision, async_, check_every, 
 
 def cg_solve(h, b, x, tol=1e-10, max_iter=100000, precision=CK_PREC_FP64, async_=False,
              check_every=8, config=None, stream=None, raise_on_error=False,
-             overhead_aware=False):
+             overhead_aware=False, known_start=False):
     """x holds x0 on entry and the solution on return; returns the result record.
     async_: CK_EXEC_DEFAULT/False, CK_EXEC_ASYNC/True or CK_EXEC_SEQUENTIAL."""
     return _solve(lib().cg_solve, h, b, x, tol, max_iter, 0, precision, async_, check_every,
-                  config, stream, raise_on_error, overhead_aware)
+                  config, stream, raise_on_error, overhead_aware, known_start)
 
 
 def gmres_solve(h, b, x, tol=1e-10, max_iter=100000, restart=30, precision=CK_PREC_FP64,
                 async_=False, check_every=8, config=None, stream=None, raise_on_error=False,
-                overhead_aware=False):
+                overhead_aware=False, known_start=False):
     return _solve(lib().gmres_solve, h, b, x, tol, max_iter, restart, precision, async_,
-                  check_every, config, stream, raise_on_error, overhead_aware)
+                  check_every, config, stream, raise_on_error, overhead_aware, known_start)
 
 
 def export_ell(h, stream=None):

@@ -415,6 +415,28 @@ ck_status spmv_select(const ck_features *f, const char *model_path, ck_config *o
     return CK_OK;
 }
 
+ck_status ck_start_config(int64_t nrows, int64_t ncols, int64_t nnz, const char *model_path,
+                          ck_config *out, int32_t *from_tree) {
+    if (!out)
+        return fail(CK_E_INVALID, "NULL argument");
+    if (nrows < 0 || ncols < 0 || nnz < 0)
+        return fail(CK_E_INVALID, "negative dimension");
+    std::string err;
+    const Cascade *C = load_cascade(model_path, err);
+    if (!C)
+        return fail(CK_E_INVALID, "%s", err.c_str());
+    *out = default_config(nrows, nnz);
+    if (from_tree)
+        *from_tree = 0;
+    const int id = nrows > 0 ? start_config_id(*C, nrows, ncols, nnz) : -1;
+    if (id >= 0) {
+        CK_TRY(ck_config_from_id(id, out));
+        if (from_tree)
+            *from_tree = 1;
+    }
+    return CK_OK;
+}
+
 ck_status ck_default_config(ck_handle h, ck_config *out) {
     if (!h || !out)
         return fail(CK_E_INVALID, "NULL argument");

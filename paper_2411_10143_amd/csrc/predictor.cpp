@@ -3,6 +3,11 @@
 //   stage 1 "format"    : CSR / ELL / COO
 //   stage 2 "algorithm" : (CSR only) scalar / vector / merge-path
 //   stage 3 "lanes"     : (CSR-vector only) log2 of lanes per row, 0..6
+// and optionally a "start" tree over the inputs known before any pass over
+// the entries (dimensions, nnz, density, mean row length), which picks the
+// configuration a solve starts from among those that need no copy of the
+// matrix (a known-features-only first stage, from the related work the
+// paper discusses, Sections II-B and V).
 // The paper compiles its trained models to C with m2cgen so inference costs
 // microseconds instead of milliseconds (inference-time table); here each tree
 // is a flat node table walked by a few lines of C++.
@@ -59,7 +64,10 @@ bool parse_model(const std::string &path, Cascade &out, std::string &err) {
                 cur = &out.tree[1];
             else if (!strcmp(name, "lanes"))
                 cur = &out.tree[2];
-            else {
+            else if (!strcmp(name, "start")) {
+                cur = &out.start;
+                out.has_start = true;
+            } else {
                 ok = false;
                 break;
             }
@@ -90,16 +98,21 @@ bool parse_model(const std::string &path, Cascade &out, std::string &err) {
     }
     fclose(f);
     if (ok) {
-        // classes per stage: format 0..4, CSR algorithm 0..3, log2(lanes) 0..6
-        static const int kClasses[3] = {5, 4, 7};
-        for (int t = 0; t < 3 && ok; ++t) {
-            const Tree &T = out.tree[t];
+        // classes per stage: format 0..4, CSR algorithm 0..3, log2(lanes)
+        // 0..6; the start tree: configuration ids 0..8 on the known inputs
+        static const int kClasses[4] = {5, 4, 7, 9};
+        static const int kInputs[4] = {kNumModelFeatures, kNumModelFeatures,
+                                       kNumModelFeatures, kNumKnownFeatures};
+        for (int t = 0; t < 4 && ok; ++t) {
+            if (t == 3 && !out.has_start)
+                break;
+            const Tree &T = t < 3 ? out.tree[t] : out.start;
             const int nn = (int)T.feature.size();
             if (nn == 0)
                 ok = false;
             for (int i = 0; i < nn && ok; ++i) {
                 if (T.feature[i] >= 0 &&
-                    (T.feature[i] >= kNumModelFeatures || T.left[i] <= i || T.right[i] <= i ||
+                    (T.feature[i] >= kInputs[t] || T.left[i] <= i || T.right[i] <= i ||
                      T.left[i] >= nn || T.right[i] >= nn))
                     ok = false;   // children come after parents: the walk ends
                 if (T.feature[i] < 0 && (T.cls[i] < 0 || T.cls[i] >= kClasses[t]))
@@ -185,6 +198,20 @@ void model_inputs(const ck_features &F, double *f) {
     f[12] = F.fill;
     f[13] = (double)F.ndiag;
     f[14] = F.diagfill;
+}
+
+int start_config_id(const Cascade &C, int64_t nrows, int64_t ncols, int64_t nnz) {
+    if (!C.has_start)
+        return -1;
+    // the same derivation as for the full feature set, from dimensions only
+    ck_features F{};
+    F.nrows = nrows;
+    F.ncols = ncols;
+    F.nnz = nnz;
+    derive_features(F);
+    double in[kNumModelFeatures];
+    model_inputs(F, in);
+    return C.start.eval(in);
 }
 
 ck_config stage_config(int stage, int cls, const ck_config &prev) {

@@ -339,6 +339,8 @@ class AsyncExec {
         const int alg = C->tree[1].eval(in);
         t_infer += us_since(t1);
         c = stage_config(1, alg, c);
+        if (alg == CK_ALG_VECTOR && c.lanes <= 0)   // started on a non-vector kernel
+            c.lanes = default_config(M_.n, M_.nnz).lanes;
         if (alg == CK_ALG_PANEL || alg == CK_ALG_MERGE) {
             // the panel-major copy / merge-path partition must exist first
             // (the partition costs a fraction of a product: never gated)
@@ -876,6 +878,14 @@ ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *
             return fail(CK_E_INVALID, "invalid configuration in opts");
         CK_TRY(convert_format(M, opts->config, s));
         c.cfg = opts->config;
+    } else if (opts->known_start && opts->async != CK_EXEC_SEQUENTIAL) {
+        // the start tree's choice among the configurations that need no copy
+        std::string err;
+        const Cascade *C = load_cascade(nullptr, err);
+        const int id = C && M.n > 0 ? start_config_id(*C, M.n, M.ncols, M.nnz) : -1;
+        ck_config sc;
+        if (id >= 0 && ck_config_from_id(id, &sc) == CK_OK)
+            c.cfg = sc;
     }
     if (M.n == 0) {
         res->status = CK_OK;

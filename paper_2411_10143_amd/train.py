@@ -10,7 +10,11 @@ decision tree per stage and export the trees as the library's model file.
             scalar, merge-path); stage 3 = fastest lane count.  Ties go to
             the lower configuration index.  With a perfect classifier the
             cascade therefore reaches the fastest configuration.
-  fit     : a CART tree per stage (scikit-learn), exported as node tables.
+  fit     : a CART tree per stage (scikit-learn), exported as node tables;
+            plus a "start" tree over the five inputs known without a pass
+            over the entries (nrows, ncols, nnz, density, mean), labelled
+            with the fastest configuration that needs no copy of the matrix
+            (ids 0..8), for the configuration a solve starts from.
 
 The corpus is synthetic (stencil, power-law, block-diagonal and uniform-random
 families, disjoint seeds from the 48 held-out evaluation matrices, plus
@@ -36,6 +40,8 @@ FEATURES = ["nrows", "ncols", "nnz", "density", "mean", "sd", "cov", "max", "min
 CONFIGS = 14
 CSR_IDS = (0, 1, 2, 3, 4, 5, 6, 7, 8, 11)   # configurations stored in CSR (incl. CSR-panel)
 FORMAT_OF = {9: 1, 10: 2, 12: 3, 13: 4}     # ELL, COO, DIA, HYB; every other id is CSR
+KNOWN = 5                                   # inputs 0..4 need no pass over the entries
+NO_COPY = 9                                 # ids 0..8 run on the CSR arrays as given
 
 
 def reps_for(us_probe: float, budget_us: float = 4000.0, lo: int = 20, hi: int = 200) -> int:
@@ -85,6 +91,20 @@ def labels(times, tie=0.0):
     cand = [(t[int(np.argmin(t[:7]))], 1), (t[7], 0), (t[8], 2), (t[11], 3)]
     alg = cand[_first_within([c[0] for c in cand], tie)][1]
     return fmt, alg, lanes
+
+
+def start_label(times, tie=0.0):
+    """Fastest configuration among those that need no copy (ids 0..8)."""
+    t = np.full(CONFIGS, np.inf)
+    t[:len(times)] = np.asarray(times, dtype=np.float64)
+    return _first_within(t[:NO_COPY], tie)
+
+
+def default_id(n, nnz):
+    """Configuration id of the library's default: CSR-vector with
+    clamp(2^floor(log2(max(1, nnz/n))), 2, 64) lanes."""
+    q = max(1, nnz // n) if n > 0 else 1
+    return min(max(int(q).bit_length() - 1, 1), 6)
 
 
 def collect(out_csv, count=600, seed=9000, reps=None):
@@ -153,8 +173,17 @@ def fit_trees(X, T, max_depth=8, min_leaf=2, seed=0, tie=0.0):
     return trees, Y
 
 
+def fit_start(X, T, max_depth=5, min_leaf=1, seed=0, tie=0.0):
+    from sklearn.tree import DecisionTreeClassifier
+    y = np.array([start_label(t, tie) for t in T])
+    clf = DecisionTreeClassifier(max_depth=max_depth, min_samples_leaf=min_leaf,
+                                 random_state=seed)
+    clf.fit(X[:, :KNOWN].astype(np.float32), y)
+    return clf
+
+
 def export(trees, path, note=""):
-    names = ["format", "algorithm", "lanes"]
+    names = ["format", "algorithm", "lanes", "start"][:len(trees)]
     with open(path, "w") as f:
         f.write("# caskrylov cascade model: CART trees fitted on MI355X SpMV timings\n")
         if note:
@@ -215,11 +244,18 @@ def main(argv=None):
             Ts.append(T)
         X, T = np.concatenate(Xs), np.concatenate(Ts)
         trees, Y = fit_trees(X, T, a.max_depth, a.min_leaf, tie=a.tie)
+        start = fit_start(X, T, a.max_depth, a.min_leaf, tie=a.tie)
         picks = np.array([cascade_predict(trees, x) for x in X])
-        slow = T[np.arange(len(T)), picks] / T.min(axis=1)
+        rows = np.arange(len(T))
+        slow = T[rows, picks] / T.min(axis=1)
+        s_pick = start.predict(X[:, :KNOWN].astype(np.float32)).astype(int)
+        d_pick = np.array([default_id(int(x[0]), int(x[2])) for x in X])
+        gm = lambda r: math.exp(np.mean(np.log(r)))
+        best9 = T[:, :NO_COPY].min(axis=1)
         note = (f"{len(X)} training matrices; training-set geomean t_pred/t_best = "
-                f"{math.exp(np.mean(np.log(slow))):.4f}")
-        export(trees, a.model, note)
+                f"{gm(slow):.4f}; start tree vs the best of ids 0..8 {gm(T[rows, s_pick] / best9):.4f} "
+                f"(default rule {gm(T[rows, d_pick] / best9):.4f})")
+        export(trees + [start], a.model, note)
         print(note)
 
 

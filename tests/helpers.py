@@ -53,8 +53,24 @@ def parse_model(path=MODEL):
     return [trees["format"], trees["algorithm"], trees["lanes"]]
 
 
+def parse_start_tree(path=MODEL):
+    """The model's optional start tree (None if it has none)."""
+    trees, cur = {}, None
+    for line in open(path):
+        if line.startswith("#") or not line.strip():
+            continue
+        parts = line.split()
+        if parts[0] == "tree":
+            cur = parts[1]
+            trees[cur] = dict(feature=[], threshold=[], left=[], right=[], cls=[])
+            continue
+        for k, v in zip(("feature", "threshold", "left", "right", "cls"), parts):
+            trees[cur][k].append(float.fromhex(v) if k == "threshold" else int(v))
+    return trees.get("start")
+
+
 def write_model(path, trees):
-    names = ["format", "algorithm", "lanes"]
+    names = ["format", "algorithm", "lanes", "start"][:len(trees)]
     with open(path, "w") as f:
         f.write("# test model\n")
         for name, t in zip(names, trees):

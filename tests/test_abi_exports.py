@@ -84,6 +84,59 @@ def test_library_cascade_equals_oracle_on_training_features(orc):
     assert {0, 1, 3} <= seen, seen
 
 
+def test_start_config_equals_oracle_tree_walk(orc):
+    """The known-inputs start tree (ck_start_config): the library, deriving
+    density and mean from (nrows, ncols, nnz) itself, against the oracle's
+    walk of the shipped start tree over the stored feature rows; every pick
+    is a configuration that needs no copy of the matrix."""
+    ensure_built()
+    import csv
+    import paper_2411_10143_amd as ck
+    from helpers import MODEL, parse_start_tree
+    from paper_2411_10143_amd import train
+    start = parse_start_tree(MODEL)
+    assert start is not None and max(f for f in start["feature"]) < train.KNOWN
+    path = os.path.join(ROOT, "paper_2411_10143_amd", "training", "mi355x_spmv_timings.csv")
+    seen = set()
+    for row in csv.DictReader(open(path)):
+        f15 = [float(row[k]) for k in train.FEATURES]
+        want = orc.tree_eval(start, f15)
+        c, from_tree = ck.start_config(int(f15[0]), int(f15[1]), int(f15[2]))
+        assert from_tree and ck.config_id(c) == want, row["name"]
+        assert 0 <= want < train.NO_COPY
+        seen.add(want)
+    assert len(seen) >= 3, seen
+    c, from_tree = ck.start_config(0, 0, 0)
+    assert not from_tree
+
+
+def test_start_tree_optional_and_checked(tmp_path):
+    ensure_built()
+    import paper_2411_10143_amd as ck
+    from helpers import MODEL, parse_model, write_model
+    from paper_2411_10143_amd import train
+    trees = parse_model(MODEL)
+    plain = str(tmp_path / "three.txt")
+    write_model(plain, trees)
+    c, from_tree = ck.start_config(1000, 1000, 9000, model_path=plain)
+    assert not from_tree and ck.config_id(c) == train.default_id(1000, 9000)
+    leaf = dict(feature=[-1], threshold=[0.0], left=[-1], right=[-1], cls=[8])
+    ok = str(tmp_path / "leaf.txt")
+    write_model(ok, trees + [leaf])
+    c, from_tree = ck.start_config(1000, 1000, 9000, model_path=ok)
+    assert from_tree and ck.config_id(c) == 8
+    for bad_tree in (dict(feature=[5, -1, -1], threshold=[1.0, 0.0, 0.0], left=[1, -1, -1],
+                          right=[2, -1, -1], cls=[-1, 0, 1]),     # a gathered input
+                     dict(leaf, cls=[9])):                        # ELL needs a copy
+        bad = str(tmp_path / "bad.txt")
+        write_model(bad, trees + [bad_tree])
+        try:
+            ck.start_config(1000, 1000, 9000, model_path=bad)
+            raise AssertionError("expected a malformed-model error")
+        except ck.CkError as e:
+            assert e.status == ck.CK_E_INVALID
+
+
 def test_overhead_gate_rule_on_host():
     """The overhead-aware conversion rule: exact geometric extrapolation, the
     no-decay and converged cases, cost ordering, and the 0.25 * R >= cost

@@ -153,6 +153,47 @@ def test_async_switch_to_panel_converts_first(ck, orc, tmp_path, solver, monkeyp
     Mx.close()
 
 
+@pytest.mark.parametrize("solver", ["cg", "gmres"])
+def test_known_start_then_cascade(ck, orc, tmp_path, solver, monkeypatch):
+    """known_start: the solve begins on the start tree's configuration (here
+    CSR-merge) and the cascade's stages still take over; stage 2 choosing
+    CSR-vector runs with the default lane count until stage 3 lands."""
+    from helpers import write_model
+    leaf = lambda c: dict(feature=[-1], threshold=[0.0], left=[-1], right=[-1], cls=[c])
+    path = str(tmp_path / "start_model.txt")
+    write_model(path, [leaf(0), leaf(1), leaf(2), leaf(8)])   # CSR, vector, 4 lanes; start merge
+    monkeypatch.setenv("CK_CASCADE_MODEL", path)
+    A = M.laplacian_3d(40) if solver == "cg" else M.convection_diffusion_2d(200, 10.0)
+    xs, b = problem(orc, A, 13)
+    fn = ck.cg_solve if solver == "cg" else ck.gmres_solve
+    Mx = ck.Matrix.from_csr(A)
+    say(f"{solver} known start, default mode n={A.n}")
+    x, r = run(ck, fn, Mx, b, tol=1e-10, known_start=True)
+    assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10, r
+    assert r["final_config"] == 8, r
+    say(f"{solver} known start, async n={A.n}")
+    x, r = run(ck, fn, Mx, b, tol=1e-10, async_=True, known_start=True)
+    assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10, r
+    assert r["final_config"] == 2 and r["switch_iter"][2] >= 0, r
+    Mx.close()
+
+
+@pytest.mark.parametrize("name", ["lap3d_48", "graph_8k", "lap2d_90"])
+def test_known_start_shipped_model(ck, orc, name):
+    A = {"lap3d_48": lambda: M.laplacian_3d(48),
+         "graph_8k": lambda: M.graph_laplacian_chung_lu(8000, 31, wmax=400),
+         "lap2d_90": lambda: M.laplacian_2d(90)}[name]()
+    xs, b = problem(orc, A, 14)
+    start, from_tree = ck.start_config(A.n, A.ncols, A.nnz)
+    assert from_tree and ck.config_id(start) < 9
+    Mx = ck.Matrix.from_csr(A)
+    for async_ in (False, True):
+        say(f"cg known start {name} async={async_} start={ck.config_id(start)}")
+        x, r = run(ck, ck.cg_solve, Mx, b, tol=1e-10, async_=async_, known_start=True)
+        assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10, (name, r)
+    Mx.close()
+
+
 def test_cg_breakdown_budget_zero_rhs(ck, orc):
     import torch
     say("cg breakdown")

@@ -296,8 +296,16 @@ def bench_spmv_set(args):
             abl[key] = dict(GBs=round(agg(t), 1), geomean_t_over_t_best=round(geomean(t / best), 4))
         abl["cascade"] = dict(GBs=round(agg(t_pred), 1),
                               geomean_t_over_t_best=round(geomean(ratio), 4))
+        # the known-inputs start tree (no pass over the entries) against the
+        # default rule, both among the configurations that need no copy
+        t_start = np.array([T[m, ck.config_id(ck.start_config(A.n, A.ncols, A.nnz)[0])]
+                            for m, A in enumerate(mats)])
+        best9 = T[:, :9].min(axis=1)
+        known = dict(GBs=round(agg(t_start), 1), best_no_copy_GBs=round(agg(best9), 1),
+                     geomean_t_over_t_best_no_copy=round(geomean(t_start / best9), 4),
+                     default_geomean_t_over_t_best_no_copy=round(geomean(t_def / best9), 4))
         out["spmv"].update({
-            "single_stage_ablation": abl,
+            "single_stage_ablation": abl, "known_start": known,
             "predicted_GBs": round(agg(t_pred), 1), "best_GBs": round(agg(best), 1),
             "default_csr_vector_GBs": round(agg(t_def), 1),
             "geomean_t_pred_over_t_best": round(geomean(ratio), 4),

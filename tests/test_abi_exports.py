@@ -118,8 +118,10 @@ def test_start_tree_optional_and_checked(tmp_path):
     trees = parse_model(MODEL)
     plain = str(tmp_path / "three.txt")
     write_model(plain, trees)
-    c, from_tree = ck.start_config(1000, 1000, 9000, model_path=plain)
-    assert not from_tree and ck.config_id(c) == train.default_id(1000, 9000)
+    for n, nnz in [(1000, 9000), (1000, 0), (1000, 1999), (1000, 2000), (7, 7 * 64),
+                   (5, 5 * 1000), (3, 2), (1 << 20, 17 << 20)]:
+        c, from_tree = ck.start_config(n, n, nnz, model_path=plain)   # the default rule
+        assert not from_tree and ck.config_id(c) == train.default_id(n, nnz), (n, nnz)
     leaf = dict(feature=[-1], threshold=[0.0], left=[-1], right=[-1], cls=[8])
     ok = str(tmp_path / "leaf.txt")
     write_model(ok, trees + [leaf])

@@ -267,7 +267,7 @@ ck_status spmv_apply_f32(ck_handle h, const ck_config *cfg, float alpha, const f
  * Small systems run in one launch: FP64 solves of at most 4096 rows with
  * neither async nor use_config run on a single 1024-thread workgroup whose
  * product takes one lane per row (final_config reports CSR-vector with 1
- * lane); other systems of at most 16384 rows with a CSR-vector configuration
+ * lane; known_start does not change this path); other systems of at most 16384 rows with a CSR-vector configuration
  * and no async run on the request loop's batched kernel. */
 ck_status cg_solve(ck_handle h, const double *d_b, double *d_x, const ck_solve_opts *opts,
                    ck_solve_result *res, hipStream_t s);

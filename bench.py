@@ -623,7 +623,7 @@ def bench_serve(args):
     log(f"[serve] pool of {len(pool)} matrices generated in {time.time() - t0:.0f}s; "
         f"n from {min(A.n for A, _ in pool)} to {max(A.n for A, _ in pool)}")
     Wl = ServingWorkload(pool, args.requests, tol=args.tol, precision=ck.CK_PREC_MIXED,
-                         budget_bytes=64 << 30, max_slots=256, chunk_iters=32,
+                         budget_bytes=64 << 30, max_slots=256, chunk_iters=args.chunk_iters,
                          small_n=args.small_n, large_workers=args.large_workers)
     log(f"[serve] {args.requests} requests prepared")
     # closed loop: capacity C (also warms the prediction cache and residency)
@@ -649,6 +649,7 @@ def bench_serve(args):
                 f"serve: {args.requests} requests, Poisson arrivals at "
                 f"{f'{rate:g}/s' if args.rate else '0.8x closed-loop capacity'}, 64-matrix pool (n log-uniform 1e3-1e6), CG if symmetric else "
                 f"GMRES(30), mixed FP32/FP64, tol {args.tol:g}, batched slots for n <= {args.small_n}, "
+                f"{args.chunk_iters} iterations per batched launch, "
                 f"{args.large_workers} large-system workers",
                 {"latency_ms": {"p50": round(summ["p50_ms"], 3), "p99": round(summ["p99_ms"], 3),
                                 "mean": round(summ["mean_ms"], 3)},
@@ -684,6 +685,8 @@ def main():
     p.add_argument("--small-n", type=int, default=8192,
                    help="serve: systems with n <= this run in batched slots")
     p.add_argument("--large-workers", type=int, default=8, help="serve: concurrent large solves")
+    p.add_argument("--chunk-iters", type=int, default=8,
+                   help="serve: iterations per batched slot per launch")
     p.add_argument("--rate", type=float, default=None,
                    help="serve: fixed arrival rate (solves/s) instead of 0.8x closed-loop capacity")
     args = p.parse_args()

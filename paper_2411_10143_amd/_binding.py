@@ -454,7 +454,7 @@ def spmv_bytes(h, fp32=False, beta_nonzero=False):
     return int(lib().ck_spmv_bytes(h, int(fp32), int(beta_nonzero)))
 
 
-def server_create(budget_bytes=64 << 30, max_slots=256, chunk_iters=32, small_n=8192,
+def server_create(budget_bytes=64 << 30, max_slots=256, chunk_iters=8, small_n=8192,
                   large_workers=8, precision=CK_PREC_MIXED, restart=30, max_iter=100000,
                   tol=1e-8):
     o = ServerOpts(int(budget_bytes), max_slots, chunk_iters, small_n, large_workers,

@@ -22,7 +22,7 @@ class ServingWorkload:
     """A pool of matrices registered with a server, plus per-request RHS."""
 
     def __init__(self, pool, n_requests, seed=5003, tol=1e-8, precision=ck.CK_PREC_MIXED,
-                 budget_bytes=64 << 30, max_slots=256, chunk_iters=32, small_n=8192,
+                 budget_bytes=64 << 30, max_slots=256, chunk_iters=8, small_n=8192,
                  large_workers=8, restart=30, max_iter=100000):
         import torch
         self.pool = pool

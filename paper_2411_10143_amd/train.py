@@ -12,9 +12,14 @@ decision tree per stage and export the trees as the library's model file.
             cascade therefore reaches the fastest configuration.
   fit     : a CART tree per stage (scikit-learn), exported as node tables;
             plus a "start" tree over the five inputs known without a pass
-            over the entries (nrows, ncols, nnz, density, mean), labelled
-            with the fastest configuration that needs no copy of the matrix
-            (ids 0..8), for the configuration a solve starts from.
+            over the entries (nrows, ncols, nnz, density, mean) that picks
+            the configuration a solve starts from among those that need no
+            copy of the matrix (ids 0..8): a regression tree on the log
+            slowdowns log(t_c / min_{c<9} t) of all nine, whose leaf names
+            the configuration with the smallest mean log slowdown over the
+            leaf's matrices (the geometric-mean-optimal pick for the leaf;
+            a classifier on the argmin labels instead ignores how much a
+            wrong pick costs).
 
 The corpus is synthetic (stencil, power-law, block-diagonal and uniform-random
 families, disjoint seeds from the 48 held-out evaluation matrices, plus
@@ -93,13 +98,6 @@ def labels(times, tie=0.0):
     return fmt, alg, lanes
 
 
-def start_label(times, tie=0.0):
-    """Fastest configuration among those that need no copy (ids 0..8)."""
-    t = np.full(CONFIGS, np.inf)
-    t[:len(times)] = np.asarray(times, dtype=np.float64)
-    return _first_within(t[:NO_COPY], tie)
-
-
 def default_id(n, nnz):
     """Configuration id of the library's default: CSR-vector with
     clamp(2^floor(log2(max(1, nnz/n))), 2, 64) lanes."""
@@ -173,13 +171,19 @@ def fit_trees(X, T, max_depth=8, min_leaf=2, seed=0, tie=0.0):
     return trees, Y
 
 
-def fit_start(X, T, max_depth=5, min_leaf=1, seed=0, tie=0.0):
-    from sklearn.tree import DecisionTreeClassifier
-    y = np.array([start_label(t, tie) for t in T])
-    clf = DecisionTreeClassifier(max_depth=max_depth, min_samples_leaf=min_leaf,
-                                 random_state=seed)
-    clf.fit(X[:, :KNOWN].astype(np.float32), y)
-    return clf
+def fit_start(X, T, max_depth=8, min_leaf=3, seed=0):
+    from sklearn.tree import DecisionTreeRegressor
+    t = np.asarray(T, dtype=np.float64)[:, :NO_COPY]
+    slow = np.log(t / t.min(axis=1, keepdims=True))
+    reg = DecisionTreeRegressor(max_depth=max_depth, min_samples_leaf=min_leaf,
+                                random_state=seed)
+    reg.fit(X[:, :KNOWN].astype(np.float32), slow)
+    return reg
+
+
+def start_predict(reg, X):
+    """Configuration ids (0..8) the start tree picks for feature rows."""
+    return np.argmin(reg.predict(np.asarray(X)[:, :KNOWN].astype(np.float32)), axis=1)
 
 
 def export(trees, path, note=""):
@@ -195,7 +199,12 @@ def export(trees, path, note=""):
             f.write(f"tree {name} {tr.node_count}\n")
             for t in range(tr.node_count):
                 leaf = tr.children_left[t] < 0
-                cls = int(clf.classes_[int(np.argmax(tr.value[t, 0, :]))]) if leaf else -1
+                if not leaf:
+                    cls = -1
+                elif hasattr(clf, "classes_"):       # classifier: majority class
+                    cls = int(clf.classes_[int(np.argmax(tr.value[t, 0, :]))])
+                else:                                # start tree: smallest mean log slowdown
+                    cls = int(np.argmin(tr.value[t, :, 0]))
                 feat = -1 if leaf else int(tr.feature[t])
                 thr = 0.0 if leaf else float(tr.threshold[t])
                 f.write(f"{feat} {thr.hex()} {int(tr.children_left[t])} "
@@ -231,6 +240,8 @@ def main(argv=None):
     fa.add_argument("--model", required=True)
     fa.add_argument("--max-depth", type=int, default=5)
     fa.add_argument("--min-leaf", type=int, default=1)
+    fa.add_argument("--start-depth", type=int, default=8)
+    fa.add_argument("--start-min-leaf", type=int, default=3)
     fa.add_argument("--tie", type=float, default=0.02,
                     help="times within this fraction of the fastest count as ties")
     a = p.parse_args(argv)
@@ -244,11 +255,11 @@ def main(argv=None):
             Ts.append(T)
         X, T = np.concatenate(Xs), np.concatenate(Ts)
         trees, Y = fit_trees(X, T, a.max_depth, a.min_leaf, tie=a.tie)
-        start = fit_start(X, T, a.max_depth, a.min_leaf, tie=a.tie)
+        start = fit_start(X, T, a.start_depth, a.start_min_leaf)
         picks = np.array([cascade_predict(trees, x) for x in X])
         rows = np.arange(len(T))
         slow = T[rows, picks] / T.min(axis=1)
-        s_pick = start.predict(X[:, :KNOWN].astype(np.float32)).astype(int)
+        s_pick = start_predict(start, X)
         d_pick = np.array([default_id(int(x[0]), int(x[2])) for x in X])
         gm = lambda r: math.exp(np.mean(np.log(r)))
         best9 = T[:, :NO_COPY].min(axis=1)

@@ -72,3 +72,31 @@ def test_shipped_model_is_well_formed():
     assert {c for c in trees[0]["cls"] if c >= 0} <= {0, 1, 2, 3, 4}
     assert {c for c in trees[1]["cls"] if c >= 0} <= {0, 1, 2, 3}
     assert {c for c in trees[2]["cls"] if c >= 0} <= set(range(7))
+
+
+def test_start_tree_export_matches_sklearn_and_minimises_leaf_slowdown(orc, tmp_path):
+    """The start tree exported as a node table picks, under the oracle's tree
+    walk, what the fitted regressor's argmin picks; on its own training rows
+    each leaf's pick has the smallest geometric-mean slowdown of the nine."""
+    from helpers import parse_start_tree
+    rng = np.random.default_rng(1)
+    X = np.exp(rng.normal(0, 2, size=(400, 15)))
+    T = rng.uniform(1, 10, size=(400, 14))
+    T[X[:, 2] > 5, 8] = 0.5             # merge wins for large nnz
+    T[X[:, 4] < 0.3, 7] = 0.4           # scalar for short rows
+    T[X[:, 0] > 20, 3] = 0.3
+    trees, _ = train.fit_trees(X, T, max_depth=3)
+    reg = train.fit_start(X, T, max_depth=4, min_leaf=3)
+    path = tmp_path / "model.txt"
+    train.export(trees + [reg], str(path))
+    start = parse_start_tree(str(path))
+    assert max(start["feature"]) < train.KNOWN
+    want = train.start_predict(reg, X)
+    got = np.array([orc.tree_eval(start, x) for x in X])
+    assert np.array_equal(got, want)
+    leaf = reg.apply(X[:, :train.KNOWN].astype(np.float32))
+    slow = np.log(T[:, :train.NO_COPY] / T[:, :train.NO_COPY].min(axis=1, keepdims=True))
+    for l in np.unique(leaf):
+        rows = leaf == l
+        assert slow[rows].mean(axis=0).argmin() == got[rows][0]
+        assert np.all(got[rows] == got[rows][0])

@@ -151,7 +151,7 @@ def bench_spmv_set(args):
             t0 = clk()
             Mx = ck.Matrix(d["rp"], d["col"], d["val"], A.ncols)
             t1 = clk()
-            F = ck.spmv_features(Mx.handle)
+            F = ck.spmv_features(Mx.handle, symmetry=False)   # the cascade's inputs only
             t2 = clk()
             cfg = ck.spmv_select(F)
             t3 = clk()

@@ -181,6 +181,14 @@ void spmv_destroy(ck_handle h);
  * computed by GPU kernels on stream s; blocks until *out is filled. */
 ck_status spmv_features(ck_handle h, ck_features *out, hipStream_t s);
 
+/* ck_features_ex -- spmv_features with flags.  CK_FEAT_NO_SYMMETRY skips the
+ * symmetry test (a search of row j for every stored (i, j), and the one pass
+ * that reads the values): is_symmetric is then -1 and every other field is
+ * the same.  The cascade does not use is_symmetric; the asynchronous
+ * executor's feature pass skips it in the same way. */
+#define CK_FEAT_NO_SYMMETRY 0x1u
+ck_status ck_features_ex(ck_handle h, ck_features *out, uint32_t flags, hipStream_t s);
+
 /* spmv_select -- host-only cascaded inference (Section III-C-1): stage 1
  * format, stage 2 CSR algorithm (only if CSR; scalar, vector, merge or
  * panel), stage 3 lanes (only if CSR-vector).  model_path: a cascade model

@@ -22,6 +22,7 @@ CK_ALG_SCALAR, CK_ALG_VECTOR, CK_ALG_MERGE, CK_ALG_PANEL = 0, 1, 2, 3
 CK_PREC_FP64, CK_PREC_MIXED = 0, 1
 CK_EXEC_DEFAULT, CK_EXEC_ASYNC, CK_EXEC_SEQUENTIAL = 0, 1, 2
 CK_KEEP_FP32 = 1
+CK_FEAT_NO_SYMMETRY = 1
 NUM_CONFIGS = 14
 CONFIG_NAMES = ["csr-vector-1", "csr-vector-2", "csr-vector-4", "csr-vector-8",
                 "csr-vector-16", "csr-vector-32", "csr-vector-64", "csr-scalar", "csr-merge",
@@ -147,6 +148,7 @@ SIGNATURES = {
     "spmv_select": (_i32, [C.POINTER(Features), C.c_char_p, C.POINTER(Config)]),
     "ck_select_stages": (_i32, [C.POINTER(Features), C.c_char_p, C.POINTER(_i32)]),
     "ck_default_config": (_i32, [_vp, C.POINTER(Config)]),
+    "ck_features_ex": (_i32, [_vp, C.POINTER(Features), C.c_uint32, _vp]),
     "ck_start_config": (_i32, [C.c_int64, C.c_int64, C.c_int64, C.c_char_p, C.POINTER(Config),
                                C.POINTER(_i32)]),
     "spmv_convert": (_i32, [_vp, C.POINTER(Config), _vp]),
@@ -260,9 +262,14 @@ def spmv_destroy(h):
     lib().spmv_destroy(h)
 
 
-def spmv_features(h, stream=None):
+def spmv_features(h, stream=None, symmetry=True):
+    """The feature record; symmetry=False skips the symmetry test
+    (is_symmetric = -1), which the cascade does not use."""
     f = Features()
-    _check(lib().spmv_features(h, C.byref(f), _stream(stream)))
+    if symmetry:
+        _check(lib().spmv_features(h, C.byref(f), _stream(stream)))
+    else:
+        _check(lib().ck_features_ex(h, C.byref(f), CK_FEAT_NO_SYMMETRY, _stream(stream)))
     return f
 
 

@@ -367,6 +367,18 @@ ck_status spmv_features(ck_handle h, ck_features *out, hipStream_t s) {
     return compute_features(*h, *out, s, true);
 }
 
+ck_status ck_features_ex(ck_handle h, ck_features *out, uint32_t flags, hipStream_t s) {
+    if (!h || !out)
+        return fail(CK_E_INVALID, "NULL argument");
+    if (flags & ~CK_FEAT_NO_SYMMETRY)
+        return fail(CK_E_INVALID, "unknown feature flags 0x%x", flags);
+    const bool symmetry = !(flags & CK_FEAT_NO_SYMMETRY);
+    CK_TRY(compute_features(*h, *out, s, symmetry));
+    if (!symmetry)
+        out->is_symmetric = -1;
+    return CK_OK;
+}
+
 ck_status ck_select_stages(const ck_features *f, const char *model_path, int32_t stage[3]) {
     if (!f || !stage)
         return fail(CK_E_INVALID, "NULL argument");

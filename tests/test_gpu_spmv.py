@@ -187,6 +187,20 @@ def test_features_bit_exact(ck, orc, name):
     Mx.close()
 
 
+@pytest.mark.parametrize("name", ["powerlaw", "uniform", "lap2d_64", "empty"])
+def test_features_without_symmetry(ck, orc, name):
+    A = case(name)
+    say(f"features without symmetry {name}")
+    Mx = ck.Matrix.from_csr(A)
+    full = ck.spmv_features(Mx.handle)
+    part = ck.spmv_features(Mx.handle, symmetry=False)
+    assert part.is_symmetric == -1
+    assert part.ints()[:27] == full.ints()[:27]
+    assert np.array_equal(np.array(part.model_inputs()), np.array(full.model_inputs()))
+    assert ck.spmv_select(part).__repr__() == ck.spmv_select(full).__repr__()
+    Mx.close()
+
+
 def test_symmetric_flag(ck, orc):
     for A in [M.laplacian_2d(30), M.graph_laplacian_chung_lu(5000, 11, wmax=500),
               M.convection_diffusion_2d(30), M.diagonally_dominant(M.uniform_random(3000, 2))]:

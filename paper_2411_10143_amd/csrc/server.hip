@@ -27,6 +27,7 @@
 #include <thread>
 #include <vector>
 
+#include "admit.hpp"
 #include "batched.hpp"
 #include "matrix.hpp"
 #include "predictor.hpp"
@@ -208,8 +209,6 @@ int lanes_for(const MatEntry &e) {
     return default_config(e.n, e.nnz).lanes;
 }
 
-enum Admit { ADMITTED, WAIT_CLASS, WAIT_MEMORY };
-
 // Tries to admit a request.  WAIT_CLASS: every slot (small) or worker (large)
 // is taken; WAIT_MEMORY: the matrix or the workspace does not fit the budget
 // (or an allocation failed), so no later request may pass it.
@@ -321,33 +320,14 @@ void scheduler(ck_server *Sp) {
             }
             S.st.queued = (int64_t)S.pending.size();
         }
-        // admit in arrival order while slots, workers and memory allow; a
-        // class whose oldest request waits for a slot or a worker admits
-        // nothing more, the other class goes on, and a request waiting for
-        // memory stops both
-        bool blocked[2] = {false, false};
-        for (auto it = S.pending.begin(); it != S.pending.end() && !(blocked[0] && blocked[1]);) {
-            Request *r = *it;
-            Admit a;
-            int cls;
-            {
-                std::lock_guard<std::mutex> lk(S.mu);
-                cls = S.mats.at(r->matrix).n <= S.o.small_n ? 0 : 1;
-                a = blocked[cls] ? WAIT_CLASS : admit_one(S, r);
-            }
-            if (blocked[cls]) {
-                ++it;
-                continue;
-            }
-            if (a == ADMITTED)
-                it = S.pending.erase(it);
-            else if (a == WAIT_MEMORY)
-                break;
-            else {
-                blocked[cls] = true;
-                ++it;
-            }
-        }
+        // admit in arrival order while slots, workers and memory allow (each
+        // path first-come first-served; a request waiting for memory stops
+        // both)
+        admit_scan(S.pending, [&](Request *r, const bool *blocked) {
+            std::lock_guard<std::mutex> lk(S.mu);
+            const int cls = S.mats.at(r->matrix).n <= S.o.small_n ? 0 : 1;
+            return std::make_pair(cls, blocked[cls] ? WAIT_CLASS : admit_one(S, r));
+        });
         // one batched launch over the occupied slots
         int na = 0;
         for (int i = 0; i < S.o.max_slots; ++i)

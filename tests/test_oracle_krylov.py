@@ -168,3 +168,36 @@ def test_gmres_budget_and_zero_rhs(orc):
     assert r["status"] == orc.NOT_CONVERGED and r["iters"] == 40
     r = orc.gmres(A, np.zeros(A.n))
     assert r["status"] == orc.OK and r["iters"] == 0
+
+
+def test_cg_true_residual_restart_branch(orc):
+    """The restart branch of CG: started from a huge x0 (1e10 times a random
+    vector) on a well-conditioned tridiagonal system, the rounding left in x
+    keeps the true residual near 1e-6 while the recurred residual falls past
+    tol = 1e-10.  At that stop the true residual (computed here with a dense
+    numpy product) must be above tol, CG must restart from the current x with
+    the true residual as its first direction -- the next step is a
+    steepest-descent step, alpha = r.r / r.Ar, x moves along r -- and the
+    restarted run must reach tol."""
+    n = 64
+    D = 4.0 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+    A = M.from_dense(D)
+    xs = M.vector(n, 1)
+    b = D @ xs
+    x0 = 1e10 * M.vector(n, 2)
+    tol = 1e-10
+    full = orc.cg(A, b, x0=x0, tol=tol, hist=400)
+    res = full["res"]
+    crossed = np.flatnonzero(res[~np.isnan(res)] <= tol)
+    assert crossed.size > 0
+    k = int(crossed[0])                             # first stop on the recurred residual
+    xk = orc.cg(A, b, x0=x0, tol=tol, maxit=k)["x"]  # the iterate at that stop
+    rk = b - D @ xk
+    assert np.linalg.norm(rk) / np.linalg.norm(b) > 100 * tol   # the branch is taken
+    alpha_sd = (rk @ rk) / (rk @ (D @ rk))
+    assert abs(full["alpha"][k] - alpha_sd) <= 1e-8 * alpha_sd
+    x1 = orc.cg(A, b, x0=x0, tol=tol, maxit=k + 1)["x"]
+    step = x1 - xk
+    assert np.linalg.norm(step - alpha_sd * rk) <= 1e-6 * np.linalg.norm(alpha_sd * rk)
+    assert full["status"] == orc.OK and full["iters"] > k
+    assert np.linalg.norm(b - D @ full["x"]) / np.linalg.norm(b) <= tol

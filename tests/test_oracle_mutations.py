@@ -37,6 +37,13 @@ MUTANTS = {
     "cascade_gate": ("if (out[1] == 1)", "if (out[1] == 0)"),
     "cg_beta_inverted": ("double beta = rho_new / rho;", "double beta = rho / rho_new;"),
     "cg_residual_sign": ("r[i] = r[i] - alpha * q[i];", "r[i] = r[i] + alpha * q[i];"),
+    "cg_restart_stale_p": ("        memcpy(p, r, bytes);\n        double rho = dot(n, r, r);",
+                           "        if (restart == 0)\n            memcpy(p, r, bytes);\n"
+                           "        double rho = dot(n, r, r);"),
+    "cg_restart_stale_r": ("        memcpy(r, b, bytes);\n        orc_spmv(n, rp, col, val, -1.0, x, 1.0, r);\n        memcpy(p, r, bytes);",
+                           "        if (restart == 0) {\n            memcpy(r, b, bytes);\n"
+                           "            orc_spmv(n, rp, col, val, -1.0, x, 1.0, r);\n        }\n"
+                           "        memcpy(p, r, bytes);"),
     "mgs_wrong_vector": ("w[t] = w[t] - h * V[i * n + t];", "w[t] = w[t] - h * V[t];"),
     "givens_sign": ("hj[i + 1] = -sn[i] * a + cs[i] * c;", "hj[i + 1] = sn[i] * a + cs[i] * c;"),
     "gmres_update_transposed": ("x[t] = x[t] + y[i] * V[i * n + t];",

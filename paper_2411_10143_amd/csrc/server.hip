@@ -4,8 +4,10 @@
 // A scheduler thread owns the device-side state:
 //   - requests wait in arrival order until their matrix is resident and
 //     their workspace fits the memory budget (least-recently-used idle
-//     matrices are evicted to make room; a request that still does not fit
-//     waits, and nothing behind it is admitted meanwhile).  Small and large
+//     matrices are evicted to make room, for the matrix, for its converted
+//     copy and for the workspace; a request that still does not fit waits,
+//     and nothing behind it is admitted meanwhile, unless nothing is in
+//     flight: then it can never fit and completes with CK_E_NOMEM).  Small and large
 //     requests are FIFO within their class, but a request waiting only for a
 //     slot (small) or a worker (large) does not hold back the other class;
 //   - the first request on a matrix runs GPU features + the cascade once; the
@@ -30,6 +32,7 @@
 #include "admit.hpp"
 #include "batched.hpp"
 #include "matrix.hpp"
+#include "panel.hpp"
 #include "predictor.hpp"
 #include "solvers.hpp"
 
@@ -54,7 +57,10 @@ struct MatEntry {
     int in_flight = 0;
     bool predicted = false;
     bool symmetric = false;
-    ck_config cfg{};
+    ck_config cfg{};                // cached cascade decision
+    int64_t conv_bytes = 0;         // estimated bytes of its converted copy
+    ck_config run_cfg{};            // what the resident copy runs (cfg, or the
+                                    // default when cfg's copy did not fit)
     uint64_t last_use = 0;
 };
 
@@ -93,7 +99,11 @@ struct ck_server {
     std::map<int, MatEntry> mats;
     int64_t bytes_in_use = 0;
     uint64_t use_clock = 0;
+    uint64_t epoch = 0;             // completions so far (wakes the scheduler)
     ck_server_stats st{};
+    // latency window (since creation or ck_server_reset_stats)
+    std::vector<double> lat_us;
+    double win_first_submit = 0, win_last_done = 0;
     // large-system workers
     std::deque<Request *> large_q;
     std::mutex lq_mu;
@@ -124,6 +134,35 @@ int64_t handle_bytes(const ck_matrix &M) {
     return b;
 }
 
+int64_t csr_bytes(const ck_server &S, const MatEntry &e) {
+    return 4 * (e.n + 1) + (S.o.precision == CK_PREC_MIXED ? 16 : 12) * e.nnz;
+}
+
+// Bytes a conversion to c adds to the handle (upper estimates from the
+// features; 0 for a configuration that needs no copy or is refused), plus
+// the conversion's own temporaries.
+int64_t converted_bytes(const ck_features &F, const ck_config &c, bool fp32) {
+    const int64_t n = F.nrows, nnz = F.nnz;
+    const int64_t pitch = ceil_div(std::max<int64_t>(n, 1), 64) * 64;
+    const int64_t vb = fp32 ? 12 : 8;          // value bytes per slot (FP64 + FP32 copy)
+    const int64_t tmp = 8 * (n + F.ncols) + 4096;
+    if (c.format == CK_FMT_ELL)
+        return F.max_r * pitch > 8 * nnz ? 0 : F.max_r * pitch * (4 + vb) + tmp;
+    if (c.format == CK_FMT_COO)
+        return 4 * nnz + tmp;
+    if (c.format == CK_FMT_DIA)
+        return F.ndiag * pitch > 8 * nnz ? 0 : F.ndiag * pitch * vb + 4 * F.ndiag + tmp;
+    if (c.format == CK_FMT_HYB)   // width K <= 3 nnz / n
+        return (3 * nnz + pitch) * (4 + vb) + 4 * n + tmp;
+    if (c.format == CK_FMT_CSR && c.algorithm == CK_ALG_PANEL) {
+        const int64_t P = panel_count_for(F.ncols, 8);
+        return 4 * (P * n + 1) + nnz * (4 + vb) + 8 * (P * n + 1) + tmp;
+    }
+    if (c.format == CK_FMT_CSR && c.algorithm == CK_ALG_MERGE)
+        return 4 * ((n + nnz) / 1024 + 2) + tmp;
+    return 0;
+}
+
 int64_t request_bytes(const ck_server &S, const MatEntry &e, bool small) {
     const int m = S.o.restart > 0 ? S.o.restart : 30;
     const int64_t ld = ceil_div(std::max<int64_t>(e.n, 1), 64) * 64;
@@ -134,8 +173,8 @@ int64_t request_bytes(const ck_server &S, const MatEntry &e, bool small) {
     return e.symmetric ? (8 + 6 * s) * ld : (int64_t)(m + 1) * s * ld + 24 * ld;
 }
 
-void complete(ck_server &S, Request *r, int status, int iters, double relres, int path,
-              int cfg) {
+// Posts a completion (S.mu held).
+void post(ck_server &S, Request *r, int status, int iters, double relres, int path, int cfg) {
     ck_completion c{};
     c.tag = r->tag;
     c.matrix_id = r->matrix;
@@ -147,71 +186,122 @@ void complete(ck_server &S, Request *r, int status, int iters, double relres, in
     c.t_submit_us = r->t_submit;
     c.t_admit_us = r->t_admit;
     c.t_done_us = S.now();
-    std::lock_guard<std::mutex> lk(S.mu);
     S.done.push_back(c);
     S.st.completed += 1;
-    S.st.in_flight -= 1;
-    S.bytes_in_use -= r->bytes;
-    S.mats[r->matrix].in_flight -= 1;
+    if (S.lat_us.empty() || c.t_submit_us < S.win_first_submit)
+        S.win_first_submit = c.t_submit_us;
+    S.win_last_done = std::max(S.win_last_done, c.t_done_us);
+    S.lat_us.push_back(c.t_done_us - c.t_submit_us);
+    S.epoch += 1;
     S.cv.notify_all();
 }
 
+void complete(ck_server &S, Request *r, int status, int iters, double relres, int path,
+              int cfg) {
+    std::lock_guard<std::mutex> lk(S.mu);
+    post(S, r, status, iters, relres, path, cfg);
+    S.st.in_flight -= 1;
+    S.bytes_in_use -= r->bytes;
+    S.mats[r->matrix].in_flight -= 1;
+}
+
+// Evicts least-recently-used idle matrices other than `keep` until `need`
+// more bytes fit the budget; false if they still do not.  Scheduler thread,
+// S.mu held.
+bool make_room(ck_server &S, const MatEntry *keep, int64_t need) {
+    while (S.bytes_in_use + need > S.o.budget_bytes) {
+        MatEntry *victim = nullptr;
+        for (auto &kv : S.mats) {
+            MatEntry &c = kv.second;
+            if (c.h && c.in_flight == 0 && &c != keep && (!victim || c.last_use < victim->last_use))
+                victim = &c;
+        }
+        if (!victim)
+            return false;   // in-flight work holds the memory
+        (void)hipStreamSynchronize(S.stream);
+        spmv_destroy(victim->h);
+        victim->h = nullptr;
+        S.bytes_in_use -= victim->bytes;
+        victim->bytes = 0;
+        S.st.evictions += 1;
+        S.st.resident_matrices -= 1;
+    }
+    return true;
+}
+
 // Makes the matrix resident (evicting idle ones if needed) and fills its
-// prediction cache.  Called by the scheduler thread only.
-ck_status ensure_resident(ck_server &S, MatEntry &e, int64_t extra) {
+// prediction cache; the cascade's configuration runs only if its converted
+// copy fits the budget too (else the default configuration).  CK_E_NOMEM:
+// it does not fit now.  Called by the scheduler thread only, S.mu held.
+ck_status ensure_resident(ck_server &S, MatEntry &e) {
     e.last_use = ++S.use_clock;
     if (e.h) {
         S.st.prediction_cache_hits += 1;   // resident, and predicted when first made so
         return CK_OK;
     }
-    const int64_t need = 16 * e.nnz + 4 * (e.n + 1) + extra;
-    // evict least-recently-used idle matrices until it fits
-    while (S.bytes_in_use + need > S.o.budget_bytes) {
-        MatEntry *victim = nullptr;
-        for (auto &kv : S.mats) {
-            MatEntry &c = kv.second;
-            if (c.h && c.in_flight == 0 && &c != &e && (!victim || c.last_use < victim->last_use))
-                victim = &c;
-        }
-        if (!victim)
-            return CK_E_NOMEM;   // wait: in-flight work holds the memory
-        (void)hipStreamSynchronize(S.stream);
-        spmv_destroy(victim->h);
-        victim->h = nullptr;
-        S.bytes_in_use -= victim->bytes;
-        S.st.evictions += 1;
-        S.st.resident_matrices -= 1;
-    }
-    CK_TRY(spmv_create(&e.h, e.n, e.n, e.nnz, e.rp, e.col, e.val,
-                       S.o.precision == CK_PREC_MIXED ? CK_KEEP_FP32 : 0u, S.stream));
+    const bool fp32 = S.o.precision == CK_PREC_MIXED;
+    // the CSR copy, plus the feature pass's scratch the first time
+    const int64_t feat = e.predicted ? 0 : 2 * e.n + 4096;
+    if (!make_room(S, &e, csr_bytes(S, e) + feat))
+        return CK_E_NOMEM;
+    CK_TRY(spmv_create(&e.h, e.n, e.n, e.nnz, e.rp, e.col, e.val, fp32 ? CK_KEEP_FP32 : 0u,
+                       nullptr, S.stream));
+    e.bytes = handle_bytes(*e.h);
+    S.bytes_in_use += e.bytes;
+    S.st.resident_matrices += 1;
     if (!e.predicted) {
         S.st.prediction_cache_misses += 1;
         ck_features F;
-        CK_TRY(compute_features(*e.h, F, S.stream, true));
-        e.symmetric = F.is_symmetric != 0;
-        if (spmv_select(&F, nullptr, &e.cfg) != CK_OK)
+        if (compute_features(*e.h, F, S.stream, true) == CK_OK) {
+            e.symmetric = F.is_symmetric != 0;
+            if (spmv_select(&F, nullptr, &e.cfg) != CK_OK)
+                e.cfg = default_config(e.n, e.nnz);
+            e.conv_bytes = converted_bytes(F, e.cfg, fp32);
+        } else {   // no features: the default kernel, and GMRES (no symmetry known)
+            e.symmetric = false;
             e.cfg = default_config(e.n, e.nnz);
+            e.conv_bytes = 0;
+        }
         e.predicted = true;
     } else {
         S.st.prediction_cache_hits += 1;
     }
-    if (e.n > S.o.small_n && convert_format(*e.h, e.cfg, S.stream) != CK_OK)
-        e.cfg = default_config(e.n, e.nnz);   // conversion refused: default kernel
-    e.bytes = handle_bytes(*e.h);
-    S.bytes_in_use += e.bytes;
-    S.st.resident_matrices += 1;
+    e.run_cfg = e.cfg;
+    if (e.n > S.o.small_n) {
+        // the copy must leave room for a request's workspace beside it
+        if (!make_room(S, &e, e.conv_bytes + request_bytes(S, e, false)) ||
+            convert_format(*e.h, e.cfg, S.stream) != CK_OK)
+            e.run_cfg = default_config(e.n, e.nnz);   // no room, or refused: default kernel
+        S.bytes_in_use -= e.bytes;
+        e.bytes = handle_bytes(*e.h);
+        S.bytes_in_use += e.bytes;
+    }
     return CK_OK;
 }
 
 int lanes_for(const MatEntry &e) {
-    if (e.cfg.format == CK_FMT_CSR && e.cfg.algorithm == CK_ALG_VECTOR && e.cfg.lanes >= 1)
-        return e.cfg.lanes;
+    if (e.run_cfg.format == CK_FMT_CSR && e.run_cfg.algorithm == CK_ALG_VECTOR &&
+        e.run_cfg.lanes >= 1)
+        return e.run_cfg.lanes;
     return default_config(e.n, e.nnz).lanes;
+}
+
+// A request that does not fit: it waits while in-flight work holds memory
+// that will come back; with nothing in flight it can never fit, and is
+// completed with CK_E_NOMEM (S.mu held).
+Admit no_room(ck_server &S, Request *r) {
+    if (S.st.in_flight > 0)
+        return WAIT_MEMORY;
+    r->t_admit = S.now();
+    post(S, r, CK_E_NOMEM, 0, -1.0, S.mats[r->matrix].n <= S.o.small_n ? 0 : 1, -1);
+    delete r;
+    return REJECTED;
 }
 
 // Tries to admit a request.  WAIT_CLASS: every slot (small) or worker (large)
 // is taken; WAIT_MEMORY: the matrix or the workspace does not fit the budget
-// (or an allocation failed), so no later request may pass it.
+// (or an allocation failed), so no later request may pass it; REJECTED: it
+// can never fit (completed with an error).  S.mu held.
 Admit admit_one(ck_server &S, Request *r) {
     MatEntry &e = S.mats[r->matrix];
     const bool small = e.n <= S.o.small_n;
@@ -228,11 +318,11 @@ Admit admit_one(ck_server &S, Request *r) {
         return WAIT_CLASS;
     }
     // prediction first (needs the matrix), then the request's own workspace
-    if (ensure_resident(S, e, 0) != CK_OK)
-        return WAIT_MEMORY;
+    if (ensure_resident(S, e) != CK_OK)
+        return no_room(S, r);
     const int64_t need = request_bytes(S, e, small);
-    if (S.bytes_in_use + need > S.o.budget_bytes)
-        return WAIT_MEMORY;
+    if (!make_room(S, &e, need))
+        return no_room(S, r);
     r->bytes = need;
     r->t_admit = S.now();
     S.bytes_in_use += need;
@@ -260,7 +350,7 @@ Admit admit_one(ck_server &S, Request *r) {
         S.bytes_in_use -= need;
         e.in_flight -= 1;
         S.st.in_flight -= 1;
-        return WAIT_MEMORY;
+        return no_room(S, r);
     }
     BSlot &b = S.slot_init[slot];
     std::memset(&b, 0, sizeof b);
@@ -293,7 +383,7 @@ Admit admit_one(ck_server &S, Request *r) {
         S.bytes_in_use -= need;
         e.in_flight -= 1;
         S.st.in_flight -= 1;
-        return WAIT_MEMORY;
+        return no_room(S, r);
     }
     S.slot_req[slot] = r;
     r->slot = slot;
@@ -304,14 +394,21 @@ void scheduler(ck_server *Sp) {
     ck_server &S = *Sp;
     (void)hipSetDevice(S.device);
     const bool fp32 = S.o.precision == CK_PREC_MIXED;
+    bool stalled = false;   // the last scan admitted nothing and no slot ran
     while (true) {
         {
             std::unique_lock<std::mutex> lk(S.mu);
             bool busy = false;
             for (Request *r : S.slot_req)
                 busy |= r != nullptr;
-            if (!busy && S.pending.empty() && S.submitted.empty() && !S.stop)
-                S.cv.wait_for(lk, std::chrono::microseconds(200));
+            // nothing to launch and nothing admissible: sleep until a request
+            // arrives or one completes (submit and complete notify cv)
+            if (!busy && S.submitted.empty() && !S.stop && (S.pending.empty() || stalled)) {
+                const uint64_t ep = S.epoch;
+                S.cv.wait_for(lk, std::chrono::milliseconds(20), [&] {
+                    return S.stop || !S.submitted.empty() || S.epoch != ep;
+                });
+            }
             if (S.stop)
                 break;
             while (!S.submitted.empty()) {
@@ -323,16 +420,20 @@ void scheduler(ck_server *Sp) {
         // admit in arrival order while slots, workers and memory allow (each
         // path first-come first-served; a request waiting for memory stops
         // both)
+        int moved = 0;
         admit_scan(S.pending, [&](Request *r, const bool *blocked) {
             std::lock_guard<std::mutex> lk(S.mu);
             const int cls = S.mats.at(r->matrix).n <= S.o.small_n ? 0 : 1;
-            return std::make_pair(cls, blocked[cls] ? WAIT_CLASS : admit_one(S, r));
+            const Admit a = blocked[cls] ? WAIT_CLASS : admit_one(S, r);
+            moved += a == ADMITTED || a == REJECTED;
+            return std::make_pair(cls, a);
         });
         // one batched launch over the occupied slots
         int na = 0;
         for (int i = 0; i < S.o.max_slots; ++i)
             if (S.slot_req[i])
                 S.active_host[na++] = i;
+        stalled = moved == 0 && na == 0;
         if (na > 0) {
             if (hipMemcpyAsync(S.active_dev, S.active_host, na * sizeof(int),
                                hipMemcpyHostToDevice, S.stream) != hipSuccess ||
@@ -368,8 +469,12 @@ void scheduler(ck_server *Sp) {
                                                             : CK_E_NOT_CONVERGED;
                 (void)hipFreeAsync(r->work, S.stream);
                 (void)hipFreeAsync(r->r64, S.stream);
-                const MatEntry &e = S.mats[r->matrix];
-                complete(S, r, status, bs.iter, bs.relres, 0, ck_config_id(&e.cfg));
+                int cid;
+                {
+                    std::lock_guard<std::mutex> lk(S.mu);
+                    cid = ck_config_id(&S.mats[r->matrix].run_cfg);
+                }
+                complete(S, r, status, bs.iter, bs.relres, 0, cid);
                 delete r;
             }
         }
@@ -392,9 +497,11 @@ void large_worker(ck_server *Sp) {
             S.large_q.pop_front();
         }
         MatEntry *e;
+        ck_config run_cfg;
         {
             std::lock_guard<std::mutex> lk(S.mu);
             e = &S.mats[r->matrix];
+            run_cfg = e->run_cfg;
         }
         ck_solve_opts o{};
         o.tol = S.o.tol;
@@ -403,7 +510,7 @@ void large_worker(ck_server *Sp) {
         o.precision = S.o.precision;
         o.check_every = 8;
         o.use_config = 1;
-        o.config = e->cfg;
+        o.config = run_cfg;
         ck_solve_result res{};
         ck_status st = launch_fill<double>(e->n, r->x, 0.0, s);   // x0 = 0
         if (st == CK_OK)
@@ -413,7 +520,7 @@ void large_worker(ck_server *Sp) {
             std::lock_guard<std::mutex> lk(S.mu);
             S.large_running -= 1;
         }
-        complete(S, r, st, res.iterations, res.true_relres, 1, ck_config_id(&e->cfg));
+        complete(S, r, st, res.iterations, res.true_relres, 1, ck_config_id(&run_cfg));
         delete r;
     }
     (void)hipStreamSynchronize(s);
@@ -521,12 +628,43 @@ ck_status ck_server_drain(ck_server_t S, double timeout_s) {
     return ok ? CK_OK : fail(CK_E_NOT_CONVERGED, "drain timed out");
 }
 
+// q-quantile of sorted v by linear interpolation between closest ranks
+static double quantile(const std::vector<double> &v, double q) {
+    if (v.empty())
+        return 0.0;
+    const double pos = q * (double)(v.size() - 1);
+    const size_t lo = (size_t)pos;
+    const size_t hi = std::min(lo + 1, v.size() - 1);
+    return v[lo] + (pos - (double)lo) * (v[hi] - v[lo]);
+}
+
 ck_status ck_server_get_stats(ck_server_t S, ck_server_stats *out) {
     if (!S || !out)
         return fail(CK_E_INVALID, "NULL argument");
+    std::vector<double> lat;
+    double span;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        *out = S->st;
+        out->bytes_in_use = S->bytes_in_use;
+        lat = S->lat_us;
+        span = S->win_last_done - S->win_first_submit;
+    }
+    std::sort(lat.begin(), lat.end());
+    out->window_completed = (int64_t)lat.size();
+    out->p50_latency_us = quantile(lat, 0.50);
+    out->p99_latency_us = quantile(lat, 0.99);
+    out->solves_per_s = span > 0 ? (double)lat.size() / (span * 1e-6) : 0.0;
+    return CK_OK;
+}
+
+ck_status ck_server_reset_stats(ck_server_t S) {
+    if (!S)
+        return fail(CK_E_INVALID, "NULL server");
     std::lock_guard<std::mutex> lk(S->mu);
-    *out = S->st;
-    out->bytes_in_use = S->bytes_in_use;
+    S->lat_us.clear();
+    S->win_first_submit = 0;
+    S->win_last_done = 0;
     return CK_OK;
 }
 
@@ -549,14 +687,14 @@ void ck_server_destroy(ck_server_t S) {
     for (auto &w : S->workers)
         if (w.joinable())
             w.join();
-    if (S->stream)
-        (void)hipStreamSynchronize(S->stream);
     for (Request *r : S->slot_req)
-        if (r) {
-            (void)hipFree(r->work);
-            (void)hipFree(r->r64);
+        if (r) {   // stream-ordered, like every other slot workspace
+            (void)hipFreeAsync(r->work, S->stream);
+            (void)hipFreeAsync(r->r64, S->stream);
             delete r;
         }
+    if (S->stream)
+        (void)hipStreamSynchronize(S->stream);
     for (Request *r : S->pending)
         delete r;
     for (Request *r : S->submitted)

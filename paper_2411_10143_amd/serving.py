@@ -63,6 +63,7 @@ class ServingWorkload:
         idx = list(range(len(self.mid))) if which is None else list(which)
         arr = np.zeros(len(idx)) if arrivals_s is None else np.asarray(arrivals_s)
         done = []
+        ck.server_reset_stats(self.srv)    # the server's latency window = this run
         t0 = time.perf_counter()
         last = [t0]
 
@@ -91,6 +92,7 @@ class ServingWorkload:
         return done
 
     def stats(self):
+        """Counters since creation; p50/p99 latency and solves/s of the last run."""
         return ck.server_stats(self.srv)
 
     def close(self):

@@ -32,6 +32,10 @@ int main() {
         ck::admit_scan(q, [&](const Req &r, const bool *blocked) {
             if (blocked[r.path] || slots[r.path] == 0)
                 return std::make_pair(r.path, ck::WAIT_CLASS);
+            if (r.bytes < 0) {                // can never fit: rejected
+                printf("x%d ", r.id);
+                return std::make_pair(r.path, ck::REJECTED);
+            }
             if (r.bytes > mem)
                 return std::make_pair(r.path, ck::WAIT_MEMORY);
             slots[r.path] -= 1;
@@ -63,6 +67,10 @@ CASES = [
     ((8, 8, 100, [(0, 1), (1, 1), (0, 1), (1, 1)]), ([0, 1, 2, 3], [])),
     # empty queue
     ((1, 1, 1, []), ([], [])),
+    # a request that can never fit is rejected and leaves the queue; the scan goes on
+    ((4, 4, 10, [(0, -1), (0, 1), (1, -1), (1, 2)]), (["x0", 1, "x2", 3], [])),
+    # a rejection does not take a slot
+    ((1, 1, 10, [(0, -1), (0, 1), (0, 1)]), (["x0", 1], [2])),
 ]
 
 
@@ -91,5 +99,5 @@ def test_admission_scan_cases(driver):
     assert len(out) == len(CASES)
     for line, (_, (adm, left)) in zip(out, CASES):
         a, l = line.split("| left")
-        assert [int(v) for v in a.split()] == adm, line
+        assert [v if v.startswith("x") else int(v) for v in a.split()] == adm, line
         assert [int(v) for v in l.split()] == left, line

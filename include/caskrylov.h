@@ -157,6 +157,22 @@ typedef struct {
 /* Flags for spmv_create */
 #define CK_KEEP_FP32 0x1u  /* also keep an FP32 copy of the values (mixed)   */
 
+/* Device memory for a handle, supplied by the caller (e.g. a framework's
+ * caching allocator).  alloc(bytes, s, ctx) returns `bytes` of device memory
+ * on the current device, aligned to at least 256 bytes, to be used in stream
+ * order on s (and, once that use has finished, on any stream), or NULL on
+ * failure (the call that needed it then returns CK_E_NOMEM).  free(p, s, ctx)
+ * gives back a block; s is the stream it was allocated for, and the library
+ * calls free only when no work that uses the block can still be pending, so
+ * it may be reused at once.  Both may be called from threads the library
+ * creates (the asynchronous executor's side thread) and on streams it
+ * creates, concurrently with the caller's thread. */
+typedef struct {
+    void *(*alloc)(size_t bytes, hipStream_t s, void *ctx);
+    void (*free)(void *p, hipStream_t s, void *ctx);
+    void *ctx;
+} ck_allocator;
+
 /* ------------------------------------------------------------------------ */
 
 /* spmv_create -- ingest a CSR matrix (problem statement A x = b, Introduction;
@@ -166,15 +182,20 @@ typedef struct {
  * rowptr[0] = 0, nondecreasing, rowptr[nrows] = nnz, 0 <= col < ncols,
  * columns strictly increasing inside each row.  Malformed input gives
  * CK_E_INVALID and *out = NULL.  Blocks until the copy is validated.
- * The active configuration starts as ck_default_config(). */
+ * The active configuration starts as ck_default_config().
+ * alloc: where every device block the handle needs comes from -- its copies
+ * of the matrix in every format, feature and conversion temporaries, product
+ * carries, and the workspaces of solves on it.  The struct is copied; its
+ * functions and ctx must stay valid until spmv_destroy returns.  NULL: a
+ * per-device cache of blocks inside the library (hipMalloc'd, kept across
+ * handles up to 16 GiB, so ingest and destroy map no new pages). */
 ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
                       const int32_t *d_rowptr, const int32_t *d_col, const double *d_val,
-                      uint32_t flags, hipStream_t s);
+                      uint32_t flags, const ck_allocator *alloc, hipStream_t s);
 
-/* spmv_destroy -- release every device copy.  The caller must have finished
- * all work that uses the handle (the memory goes back to a per-device cache,
- * up to 16 GiB, from which later handles are served without mapping new
- * pages; it is not synchronised again).  NULL is ignored. */
+/* spmv_destroy -- release every device copy (to the handle's allocator, or
+ * to the library's cache).  The caller must have finished all work that uses
+ * the handle; nothing is synchronised again.  NULL is ignored. */
 void spmv_destroy(ck_handle h);
 
 /* spmv_features -- the 15 features of the feature table (Section III-B-1),
@@ -373,7 +394,11 @@ ck_status ck_time_spmv(ck_handle h, const ck_config *cfg, int32_t fp32, const vo
  * solved with CG, the others with GMRES(restart).  x0 = 0.  Admission is in
  * arrival order within each of the two paths; a request waiting only for a
  * free slot or worker does not hold back the other path, and one waiting for
- * memory holds back both. */
+ * memory holds back both.  The budget covers resident matrices (with their
+ * converted copies: a decision whose copy does not fit runs the default
+ * configuration) and request workspaces; idle matrices are evicted least
+ * recently used first.  A request that does not fit even when nothing else
+ * is in flight completes at once with status CK_E_NOMEM. */
 typedef struct ck_server *ck_server_t;
 
 typedef struct {
@@ -400,10 +425,18 @@ typedef struct {
 
 /* prediction_cache_hits counts admissions that found the matrix's features
  * and cascade decision already cached; prediction_cache_misses counts the
- * feature extractions and predictions actually run. */
+ * feature extractions and predictions actually run.  The latency fields
+ * cover the completions since the server was created or since the last
+ * ck_server_reset_stats (window_completed of them): latency = t_done_us -
+ * t_submit_us of each completion; p50/p99 are its quantiles, interpolated
+ * linearly between the closest ranks; solves_per_s = window_completed /
+ * (latest t_done_us - earliest t_submit_us in the window).  Requests
+ * completed with an error (e.g. CK_E_NOMEM) count too. */
 typedef struct {
     int64_t submitted, completed, queued, in_flight, resident_matrices, evictions,
         bytes_in_use, batched_launches, prediction_cache_hits, prediction_cache_misses;
+    int64_t window_completed;
+    double p50_latency_us, p99_latency_us, solves_per_s;
 } ck_server_stats;
 
 /* ck_server_create -- start a request loop on the current device. */
@@ -423,6 +456,9 @@ int32_t ck_server_poll(ck_server_t s, ck_completion *out, int32_t cap);
 /* ck_server_drain -- wait until every submitted request has completed. */
 ck_status ck_server_drain(ck_server_t s, double timeout_s);
 ck_status ck_server_get_stats(ck_server_t s, ck_server_stats *out);
+/* ck_server_reset_stats -- start a new latency window (the counters of
+ * ck_server_stats are not reset). */
+ck_status ck_server_reset_stats(ck_server_t s);
 /* ck_server_clock_us -- microseconds since the server was created. */
 double ck_server_clock_us(ck_server_t s);
 /* ck_server_destroy -- stop the loop, free everything (pending requests are

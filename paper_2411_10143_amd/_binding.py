@@ -130,10 +130,60 @@ class ServerStats(C.Structure):
     _fields_ = [(n, C.c_int64) for n in ("submitted", "completed", "queued", "in_flight",
                                          "resident_matrices", "evictions", "bytes_in_use",
                                          "batched_launches", "prediction_cache_hits",
-                                         "prediction_cache_misses")]
+                                         "prediction_cache_misses", "window_completed")] + \
+               [(n, C.c_double) for n in ("p50_latency_us", "p99_latency_us", "solves_per_s")]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p, C.c_void_p)
+
+
+class AllocatorStruct(C.Structure):
+    """ck_allocator: alloc(bytes, stream, ctx) -> device pointer, free(ptr, stream, ctx)."""
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", C.c_void_p)]
+
+
+class CallbackAllocator:
+    """A ck_allocator whose functions are Python callables:
+    alloc(nbytes, stream) -> int device pointer (0 on failure) and
+    free(ptr, stream).  Keep the object alive while handles use it."""
+
+    def __init__(self, alloc, free):
+        def _alloc(nbytes, stream, _ctx):
+            try:
+                return int(alloc(int(nbytes), int(stream or 0))) or None
+            except Exception:          # NULL: the library reports CK_E_NOMEM
+                return None
+
+        def _free(ptr, stream, _ctx):
+            try:
+                free(int(ptr), int(stream or 0))
+            except Exception:
+                pass
+
+        self._alloc = ALLOC_FN(_alloc)
+        self._free = FREE_FN(_free)
+        self.struct = AllocatorStruct(self._alloc, self._free, None)
+
+
+_TORCH_ALLOCATORS = {}
+
+
+def torch_allocator(device=None):
+    """The ck_allocator backed by torch's caching allocator on `device`
+    (default: the current device); one per device, kept for the process."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else torch.device(device).index
+    if dev is None:
+        dev = torch.cuda.current_device()
+    if dev not in _TORCH_ALLOCATORS:
+        _TORCH_ALLOCATORS[dev] = CallbackAllocator(
+            lambda nbytes, stream: torch.cuda.caching_allocator_alloc(nbytes, dev, stream),
+            lambda ptr, stream: torch.cuda.caching_allocator_delete(ptr))
+    return _TORCH_ALLOCATORS[dev]
 
 
 _lib = None
@@ -142,7 +192,8 @@ _i32, _i64, _u32, _dbl, _flt = C.c_int32, C.c_int64, C.c_uint32, C.c_double, C.c
 
 # name -> (restype, argtypes); the C-ABI surface of include/caskrylov.h
 SIGNATURES = {
-    "spmv_create": (_i32, [C.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _vp, _u32, _vp]),
+    "spmv_create": (_i32, [C.POINTER(_vp), _i64, _i64, _i64, _vp, _vp, _vp, _u32,
+                           C.POINTER(AllocatorStruct), _vp]),
     "spmv_destroy": (None, [_vp]),
     "spmv_features": (_i32, [_vp, C.POINTER(Features), _vp]),
     "spmv_select": (_i32, [C.POINTER(Features), C.c_char_p, C.POINTER(Config)]),
@@ -179,6 +230,7 @@ SIGNATURES = {
     "ck_server_poll": (_i32, [_vp, C.POINTER(Completion), _i32]),
     "ck_server_drain": (_i32, [_vp, _dbl]),
     "ck_server_get_stats": (_i32, [_vp, C.POINTER(ServerStats)]),
+    "ck_server_reset_stats": (_i32, [_vp]),
     "ck_server_clock_us": (_dbl, [_vp]),
     "ck_server_destroy": (None, [_vp]),
     "ck_last_error": (C.c_char_p, []),
@@ -246,15 +298,29 @@ def kernel_name(c, fp32=False):
     return buf.value.decode()
 
 
-def spmv_create(rp, col, val, ncols=None, keep_fp32=False, stream=None):
-    """Copy a device CSR (int32 rowptr/col, float64 val) into a new handle."""
+def _allocator(allocator, device):
+    if allocator is None:
+        return None
+    if allocator == "torch":
+        return torch_allocator(device)
+    if isinstance(allocator, CallbackAllocator):
+        return allocator
+    raise TypeError("allocator must be 'torch', None or a CallbackAllocator")
+
+
+def spmv_create(rp, col, val, ncols=None, keep_fp32=False, stream=None, allocator="torch"):
+    """Copy a device CSR (int32 rowptr/col, float64 val) into a new handle.
+    allocator: "torch" (torch's caching allocator supplies every device
+    block of the handle), None (the library's own cache) or a
+    CallbackAllocator; it must outlive the handle."""
     import torch
     n = rp.numel() - 1
     h = _vp()
+    a = _allocator(allocator, rp.device)
     _check(lib().spmv_create(C.byref(h), n, n if ncols is None else ncols, col.numel(),
                              _ptr(rp, torch.int32), _ptr(col, torch.int32),
                              _ptr(val, torch.float64), CK_KEEP_FP32 if keep_fp32 else 0,
-                             _stream(stream)))
+                             C.byref(a.struct) if a is not None else None, _stream(stream)))
     return h.value
 
 
@@ -500,6 +566,10 @@ def server_stats(srv):
     return s.as_dict()
 
 
+def server_reset_stats(srv):
+    _check(lib().ck_server_reset_stats(srv))
+
+
 def server_clock_us(srv):
     return float(lib().ck_server_clock_us(srv))
 
@@ -511,19 +581,22 @@ def server_destroy(srv):
 class Matrix:
     """Owns a handle; a convenience wrapper over the C calls."""
 
-    def __init__(self, rp, col, val, ncols=None, keep_fp32=False, stream=None):
+    def __init__(self, rp, col, val, ncols=None, keep_fp32=False, stream=None,
+                 allocator="torch"):
         self.n = rp.numel() - 1
         self.ncols = self.n if ncols is None else ncols
         self.nnz = col.numel()
-        self.handle = spmv_create(rp, col, val, ncols, keep_fp32, stream)
+        self.allocator = _allocator(allocator, rp.device)   # outlives the handle
+        self.handle = spmv_create(rp, col, val, ncols, keep_fp32, stream,
+                                  self.allocator if self.allocator is not None else None)
 
     @classmethod
-    def from_csr(cls, A, keep_fp32=False, device="cuda", stream=None):
+    def from_csr(cls, A, keep_fp32=False, device="cuda", stream=None, allocator="torch"):
         import torch
         rp = torch.from_numpy(A.rp).to(device)
         col = torch.from_numpy(A.col).to(device)
         val = torch.from_numpy(A.val).to(device)
-        return cls(rp, col, val, A.ncols, keep_fp32, stream)
+        return cls(rp, col, val, A.ncols, keep_fp32, stream, allocator)
 
     def close(self):
         if getattr(self, "handle", None):

@@ -44,29 +44,29 @@ ck_status launch_to_coo(const ck_matrix &M, int *row, hipStream_t s);
 static void release(ck_matrix *M) {
     if (!M)
         return;
-    dev_cache_free(M->rp);
-    dev_cache_free(M->col);
-    dev_cache_free(M->val);
-    dev_cache_free(M->val32);
-    dev_cache_free(M->ell_col);
-    dev_cache_free(M->ell_val);
-    dev_cache_free(M->ell_val32);
-    dev_cache_free(M->coo_row);
-    dev_cache_free(M->dia_off);
-    dev_cache_free(M->dia_val);
-    dev_cache_free(M->dia_val32);
-    dev_cache_free(M->hyb_col);
-    dev_cache_free(M->hyb_val);
-    dev_cache_free(M->hyb_val32);
-    dev_cache_free(M->hyb_rows);
-    dev_cache_free(M->panel_rp);
-    dev_cache_free(M->panel_col);
-    dev_cache_free(M->panel_val);
-    dev_cache_free(M->panel_val32);
-    dev_cache_free(M->merge_part);
-    dev_cache_free(M->panel_part);
+    mat_free(*M, M->rp);
+    mat_free(*M, M->col);
+    mat_free(*M, M->val);
+    mat_free(*M, M->val32);
+    mat_free(*M, M->ell_col);
+    mat_free(*M, M->ell_val);
+    mat_free(*M, M->ell_val32);
+    mat_free(*M, M->coo_row);
+    mat_free(*M, M->dia_off);
+    mat_free(*M, M->dia_val);
+    mat_free(*M, M->dia_val32);
+    mat_free(*M, M->hyb_col);
+    mat_free(*M, M->hyb_val);
+    mat_free(*M, M->hyb_val32);
+    mat_free(*M, M->hyb_rows);
+    mat_free(*M, M->panel_rp);
+    mat_free(*M, M->panel_col);
+    mat_free(*M, M->panel_val);
+    mat_free(*M, M->panel_val32);
+    mat_free(*M, M->merge_part);
+    mat_free(*M, M->panel_part);
     for (auto &kv : M->carry)
-        dev_cache_free(kv.second);
+        mat_free(*M, kv.second);
     delete M;
 }
 
@@ -77,8 +77,8 @@ static void release(ck_matrix *M) {
 ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s, bool symmetry) {
     std::memset(&F, 0, sizeof F);
     const int64_t bytes = features_scratch_bytes(M.n, M.ncols);
-    void *scratch = nullptr;
-    CK_TRY(dev_cache_alloc(&scratch, (size_t)bytes));
+    char *scratch = nullptr;
+    CK_TRY(mat_alloc(M, &scratch, bytes, s));
     ck_status st = launch_features(M, scratch, symmetry, s);
     char acc[512];
     if (st == CK_OK) {
@@ -88,7 +88,7 @@ ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s, bool sym
             st = fail(CK_E_HIP, "feature copy failed: %s", hipGetErrorString(e));
     }
     const hipError_t es = hipStreamSynchronize(s);
-    dev_cache_free(scratch);   // the pass has finished with it
+    mat_free(M, scratch);   // the pass has finished with it
     CK_TRY(st);
     if (es != hipSuccess)
         return fail(CK_E_HIP, "feature pass failed: %s", hipGetErrorString(es));
@@ -125,7 +125,7 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
         // every workgroup of every product
         if (M.has_merge_part.load())
             return CK_OK;
-        CK_TRY(dev_alloc(&M.merge_part, merge_part_entries(M)));
+        CK_TRY(mat_alloc(M, &M.merge_part, merge_part_entries(M), s));
         CK_TRY(launch_merge_partition(M, M.merge_part, s));
         return mark_built(M.has_merge_part, s);
     }
@@ -137,26 +137,26 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
         const int64_t N = (int64_t)P * M.n;
         if (N + 1 > (int64_t)std::numeric_limits<int32_t>::max())
             return fail(CK_E_UNSUPPORTED, "too many panel rows");
-        CK_TRY(dev_alloc(&M.panel_rp, N + 1));
-        CK_TRY(dev_alloc(&M.panel_col, M.nnz));
-        CK_TRY(dev_alloc(&M.panel_val, M.nnz));
+        CK_TRY(mat_alloc(M, &M.panel_rp, N + 1, s));
+        CK_TRY(mat_alloc(M, &M.panel_col, M.nnz, s));
+        CK_TRY(mat_alloc(M, &M.panel_val, M.nnz, s));
         if (M.val32)
-            CK_TRY(dev_alloc(&M.panel_val32, M.nnz));
+            CK_TRY(mat_alloc(M, &M.panel_val32, M.nnz, s));
         int *tmp = nullptr;
         const int64_t tmp_elems = N + panel_scan_tmp_elems(N);
-        CK_TRY(dev_alloc(&tmp, tmp_elems));
+        CK_TRY(mat_alloc(M, &tmp, tmp_elems, s));
         ck_status st = launch_to_panel(M, P, W, tmp, tmp + N, M.panel_rp, M.panel_col,
                                        M.panel_val, M.panel_val32, s);
         M.panel_P = P;
         M.panel_W = W;
         if (st == CK_OK)
-            st = dev_alloc(&M.panel_part, merge_part_entries_rows(N, M.nnz));
+            st = mat_alloc(M, &M.panel_part, merge_part_entries_rows(N, M.nnz), s);
         if (st == CK_OK)
             st = launch_merge_partition_rows(N, M.nnz, M.panel_rp, M.panel_part, s);
         if (st == CK_OK)
             st = mark_built(M.has_panel, s);
         (void)hipStreamSynchronize(s);   // the conversion has finished with tmp
-        dev_cache_free(tmp);
+        mat_free(M, tmp);
         return st;
     }
     if (c.format == CK_FMT_DIA) {
@@ -165,9 +165,9 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
         const ck_status st = convert_to_dia(M, s);
         if (st != CK_OK) {   // refused for fill, or out of memory: leave no partial copy
             (void)hipStreamSynchronize(s);
-            dev_cache_free(M.dia_off);
-            dev_cache_free(M.dia_val);
-            dev_cache_free(M.dia_val32);
+            mat_free(M, M.dia_off);
+            mat_free(M, M.dia_val);
+            mat_free(M, M.dia_val32);
             M.dia_off = nullptr;
             M.dia_val = nullptr;
             M.dia_val32 = nullptr;
@@ -181,10 +181,10 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
         const ck_status st = convert_to_hyb(M, s);
         if (st != CK_OK) {
             (void)hipStreamSynchronize(s);
-            dev_cache_free(M.hyb_col);
-            dev_cache_free(M.hyb_val);
-            dev_cache_free(M.hyb_val32);
-            dev_cache_free(M.hyb_rows);
+            mat_free(M, M.hyb_col);
+            mat_free(M, M.hyb_val);
+            mat_free(M, M.hyb_val32);
+            mat_free(M, M.hyb_rows);
             M.hyb_col = nullptr;
             M.hyb_val = nullptr;
             M.hyb_val32 = nullptr;
@@ -196,7 +196,7 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
     if (c.format == CK_FMT_COO) {
         if (M.has_coo.load())
             return CK_OK;
-        CK_TRY(dev_alloc(&M.coo_row, M.nnz));
+        CK_TRY(mat_alloc(M, &M.coo_row, M.nnz, s));
         CK_TRY(launch_to_coo(M, M.coo_row, s));
         return mark_built(M.has_coo, s);
     }
@@ -205,12 +205,16 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
     if (M.max_row < 0) {
         unsigned long long *d = nullptr;
         unsigned long long h = 0;
-        CK_HIP(hipMallocAsync((void **)&d, sizeof h, s));
-        CK_TRY(launch_fill<int>(2, (int *)d, 0, s));
-        CK_TRY(launch_row_max(M.n, M.rp, d, s));
-        CK_HIP(hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, s));
-        CK_HIP(hipFreeAsync(d, s));
-        CK_HIP(hipStreamSynchronize(s));
+        CK_TRY(mat_alloc(M, &d, 1, s));
+        ck_status st = launch_fill<int>(2, (int *)d, 0, s);
+        if (st == CK_OK)
+            st = launch_row_max(M.n, M.rp, d, s);
+        if (st == CK_OK && hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, s) != hipSuccess)
+            st = fail(CK_E_HIP, "row-length read-back failed");
+        if (hipStreamSynchronize(s) != hipSuccess && st == CK_OK)
+            st = fail(CK_E_HIP, "row-length pass failed");
+        mat_free(M, d);
+        CK_TRY(st);
         M.max_row = (int64_t)h;
     }
     const int64_t K = M.max_row;
@@ -218,10 +222,10 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
     if (K * pitch > 8 * M.nnz)
         return fail(CK_E_UNSUPPORTED, "ELL refused: %lld slots for %lld stored entries",
                     (long long)(K * pitch), (long long)M.nnz);
-    CK_TRY(dev_alloc(&M.ell_col, K * pitch));
-    CK_TRY(dev_alloc(&M.ell_val, K * pitch));
+    CK_TRY(mat_alloc(M, &M.ell_col, K * pitch, s));
+    CK_TRY(mat_alloc(M, &M.ell_val, K * pitch, s));
     if (M.val32)
-        CK_TRY(dev_alloc(&M.ell_val32, K * pitch));
+        CK_TRY(mat_alloc(M, &M.ell_val32, K * pitch, s));
     CK_TRY(launch_to_ell(M, K, pitch, M.ell_col, M.ell_val, M.ell_val32, s));
     M.ell_K = K;
     M.ell_pitch = pitch;
@@ -292,7 +296,7 @@ ck_status ck_kernel_name(const ck_config *cfg, int32_t fp32, char *buf, size_t c
 
 ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
                       const int32_t *d_rowptr, const int32_t *d_col, const double *d_val,
-                      uint32_t flags, hipStream_t s) {
+                      uint32_t flags, const ck_allocator *alloc, hipStream_t s) {
     if (!out)
         return fail(CK_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -303,7 +307,13 @@ ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
         return fail(CK_E_INVALID, "NULL CSR array");
     if (flags & ~CK_KEEP_FP32)
         return fail(CK_E_INVALID, "unknown flags");
+    if (alloc && (!alloc->alloc || !alloc->free))
+        return fail(CK_E_INVALID, "allocator without alloc or free function");
     ck_matrix *M = new ck_matrix();
+    if (alloc) {
+        M->mem.a = *alloc;
+        M->mem.user = true;
+    }
     M->n = nrows;
     M->ncols = ncols;
     M->nnz = nnz;
@@ -313,9 +323,9 @@ ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
     unsigned *bad = nullptr;
     unsigned hbad = 0;
     do {
-        if ((st = dev_alloc(&M->rp, nrows + 1)) != CK_OK) break;
-        if ((st = dev_alloc(&M->col, nnz)) != CK_OK) break;
-        if ((st = dev_alloc(&M->val, nnz)) != CK_OK) break;
+        if ((st = mat_alloc(*M, &M->rp, nrows + 1, s)) != CK_OK) break;
+        if ((st = mat_alloc(*M, &M->col, nnz, s)) != CK_OK) break;
+        if ((st = mat_alloc(*M, &M->val, nnz, s)) != CK_OK) break;
         hipError_t e = hipMemcpyAsync(M->rp, d_rowptr, sizeof(int32_t) * (nrows + 1),
                                       hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess && nnz > 0)
@@ -327,11 +337,11 @@ ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
             break;
         }
         if (flags & CK_KEEP_FP32) {
-            if ((st = dev_alloc(&M->val32, nnz)) != CK_OK) break;
+            if ((st = mat_alloc(*M, &M->val32, nnz, s)) != CK_OK) break;
             if (nnz > 0 && (st = launch_copy<float, double>(nnz, M->val32, M->val, nullptr, s)) != CK_OK)
                 break;
         }
-        if ((st = dev_alloc(&bad, 1)) != CK_OK) break;
+        if ((st = mat_alloc(*M, &bad, 1, s)) != CK_OK) break;
         if ((st = launch_fill<int>(1, (int *)bad, 0, s)) != CK_OK) break;
         if ((st = launch_validate(nrows, ncols, nnz, M->rp, M->col, bad, s)) != CK_OK) break;
         e = hipMemcpyAsync(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, s);
@@ -349,7 +359,7 @@ ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
         }
     } while (false);
     (void)hipStreamSynchronize(s);   // nothing may still write the arrays
-    dev_cache_free(bad);
+    mat_free(*M, bad);
     if (st != CK_OK) {
         release(M);
         return st;
@@ -505,7 +515,7 @@ static ck_status carry_for(ck_handle h, const ck_config &c, hipStream_t s, void 
                  std::max(spmv_carry_bytes(*h, ck_config{CK_FMT_COO, 0, 0, 0}, false),
                           spmv_carry_bytes(*h, ck_config{CK_FMT_CSR, CK_ALG_PANEL, 0, 0}, false)));
     char *p = nullptr;
-    CK_TRY(dev_alloc(&p, bytes));
+    CK_TRY(mat_alloc(*h, &p, bytes, s));
     h->carry[s] = p;
     *out = p;
     return CK_OK;

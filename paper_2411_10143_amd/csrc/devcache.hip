@@ -92,4 +92,36 @@ void dev_cache_free(void *p) {
     g_cached[b.device] += b.bytes;
 }
 
+ck_status mem_alloc(MemSource &m, void **p, size_t bytes, hipStream_t s) {
+    *p = nullptr;
+    if (!m.user)
+        return dev_cache_alloc(p, bytes);
+    void *q = m.a.alloc(bytes > 0 ? bytes : 1, s, m.a.ctx);
+    if (!q)
+        return fail(CK_E_NOMEM, "the caller's allocator returned NULL for %zu bytes", bytes);
+    std::lock_guard<std::mutex> lk(m.mu);
+    m.streams[q] = s;
+    *p = q;
+    return CK_OK;
+}
+
+void mem_free(MemSource &m, void *p) {
+    if (!p)
+        return;
+    if (!m.user) {
+        dev_cache_free(p);
+        return;
+    }
+    hipStream_t s = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(m.mu);
+        auto it = m.streams.find(p);
+        if (it == m.streams.end())
+            return;
+        s = it->second;
+        m.streams.erase(it);
+    }
+    m.a.free(p, s, m.a.ctx);
+}
+
 }  // namespace ck

@@ -1,6 +1,8 @@
 // Device memory of matrix handles: a per-device cache of freed blocks.
 #pragma once
 
+#include <unordered_map>
+
 #include "common.hpp"
 
 namespace ck {
@@ -24,5 +26,20 @@ ck_status dev_alloc(T **p, int64_t count) {
     *p = (T *)q;
     return st;
 }
+
+// Where one handle's device memory comes from: the caller's allocator
+// (spmv_create's `alloc`), or the per-device cache above when there is none.
+// Every block of the handle -- its format copies, feature and conversion
+// temporaries, product carries and solver workspaces -- comes from here.
+// A block is given back only once no work that uses it can be pending.
+struct MemSource {
+    ck_allocator a{};
+    bool user = false;
+    std::mutex mu;
+    std::unordered_map<void *, hipStream_t> streams;   // user blocks -> allocation stream
+};
+
+ck_status mem_alloc(MemSource &m, void **p, size_t bytes, hipStream_t s);
+void mem_free(MemSource &m, void *p);   // NULL is ignored
 
 }  // namespace ck

@@ -236,16 +236,18 @@ ck_status launch_to_ell(const ck_matrix &M, int64_t K, int64_t pitch, int *ecol,
 
 namespace {
 
-// Temporary device memory of one conversion, returned to the handle-memory
-// cache once the conversion's stream has finished with it.
+// Temporary device memory of one conversion, from the handle's memory
+// source, given back once the conversion's stream has finished with it.
 struct Tmp {
+    ck_matrix &M;
     hipStream_t s;
     void *p = nullptr;
-    explicit Tmp(hipStream_t st) : s(st) {}
+    Tmp(ck_matrix &m, hipStream_t st) : M(m), s(st) {}
+    ck_status get(size_t bytes) { return mem_alloc(M.mem, &p, bytes, s); }
     ~Tmp() {
         if (p) {
             (void)hipStreamSynchronize(s);
-            dev_cache_free(p);
+            mat_free(M, p);
         }
     }
 };
@@ -263,12 +265,12 @@ int lanes_for_mean(int64_t total, int64_t rows) {
 ck_status convert_to_dia(ck_matrix &M, hipStream_t s) {
     const int64_t n = M.n, pitch = ceil_div(n, 64) * 64;
     int64_t nd = 0;
-    Tmp tmp(s);
+    Tmp tmp(M, s);
     int *flags = nullptr, *pos = nullptr;
     const int64_t N = n + M.ncols - 1;   // offsets -(n-1) .. ncols-1
     if (n > 0 && M.nnz > 0) {
         const int64_t scan_tmp = panel_scan_tmp_elems(N);
-        CK_TRY(dev_cache_alloc(&tmp.p, (size_t)(2 * N + 1 + scan_tmp) * sizeof(int)));
+        CK_TRY(tmp.get((size_t)(2 * N + 1 + scan_tmp) * sizeof(int)));
         flags = (int *)tmp.p;
         pos = flags + N;
         CK_TRY(launch_fill<int>(N, flags, 0, s));
@@ -283,10 +285,10 @@ ck_status convert_to_dia(ck_matrix &M, hipStream_t s) {
     if (nd * pitch > 8 * M.nnz)
         return fail(CK_E_UNSUPPORTED, "DIA refused: %lld diagonals x %lld rows for %lld entries",
                     (long long)nd, (long long)pitch, (long long)M.nnz);
-    CK_TRY(dev_alloc(&M.dia_off, nd));
-    CK_TRY(dev_alloc(&M.dia_val, nd * pitch));
+    CK_TRY(mat_alloc(M, &M.dia_off, nd, s));
+    CK_TRY(mat_alloc(M, &M.dia_val, nd * pitch, s));
     if (M.val32)
-        CK_TRY(dev_alloc(&M.dia_val32, nd * pitch));
+        CK_TRY(mat_alloc(M, &M.dia_val32, nd * pitch, s));
     if (nd > 0) {
         hipLaunchKernelGGL(dia_offsets, dim3(std::min<int64_t>(ceil_div(N, 256), 8192)), dim3(256),
                            0, s, N, n, flags, pos, M.dia_off);
@@ -316,8 +318,8 @@ ck_status convert_to_hyb(ck_matrix &M, hipStream_t s) {
         if (Kcap + 1 > (int64_t)INT_MAX)
             return fail(CK_E_UNSUPPORTED, "HYB: rows too long");
         const int B = (int)(Kcap + 1);
-        Tmp tmp(s);
-        CK_TRY(dev_cache_alloc(&tmp.p, (size_t)B * sizeof(unsigned)));
+        Tmp tmp(M, s);
+        CK_TRY(tmp.get((size_t)B * sizeof(unsigned)));
         unsigned *hist = (unsigned *)tmp.p;
         CK_TRY(launch_fill<int>(B, (int *)hist, 0, s));
         hipLaunchKernelGGL(hyb_hist, dim3(std::min<int64_t>(ceil_div(n, 256), 2048)), dim3(256), 0,
@@ -340,16 +342,16 @@ ck_status convert_to_hyb(ck_matrix &M, hipStream_t s) {
         tail_nnz = M.nnz - ell_entries;
         nt = ge[K + 1];
     }
-    CK_TRY(dev_alloc(&M.hyb_col, K * pitch));
-    CK_TRY(dev_alloc(&M.hyb_val, K * pitch));
+    CK_TRY(mat_alloc(M, &M.hyb_col, K * pitch, s));
+    CK_TRY(mat_alloc(M, &M.hyb_val, K * pitch, s));
     if (M.val32)
-        CK_TRY(dev_alloc(&M.hyb_val32, K * pitch));
-    CK_TRY(dev_alloc(&M.hyb_rows, nt));
+        CK_TRY(mat_alloc(M, &M.hyb_val32, K * pitch, s));
+    CK_TRY(mat_alloc(M, &M.hyb_rows, nt, s));
     CK_TRY(launch_to_ell(M, K, pitch, M.hyb_col, M.hyb_val, M.hyb_val32, s));
     if (nt > 0) {
-        Tmp tmp(s);
+        Tmp tmp(M, s);
         const int64_t scan_tmp = panel_scan_tmp_elems(n);
-        CK_TRY(dev_cache_alloc(&tmp.p, (size_t)(2 * n + 1 + scan_tmp) * sizeof(int)));
+        CK_TRY(tmp.get((size_t)(2 * n + 1 + scan_tmp) * sizeof(int)));
         int *flag = (int *)tmp.p, *pos = flag + n;
         hipLaunchKernelGGL(hyb_long_flags, dim3(ceil_div(n, 256)), dim3(256), 0, s, n, (int)K,
                            M.rp, flag);

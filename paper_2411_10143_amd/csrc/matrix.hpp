@@ -6,6 +6,7 @@
 #include <map>
 #include <mutex>
 
+#include "devcache.hpp"
 #include "krylov.hpp"
 
 struct ck_matrix {
@@ -61,12 +62,23 @@ struct ck_matrix {
     int64_t max_row = -1;             // longest row, once known
     ck_config active{};
     std::mutex mu;                    // guards conversions, `active` and `carry`
+    ck::MemSource mem;                // where every device block of the handle comes from
     // merge-path / COO carry workspace of spmv_apply, one per stream (work on
     // one stream is ordered, so reuse on that stream is safe)
     std::map<hipStream_t, void *> carry;
 };
 
 namespace ck {
+
+// A block of `count` T for handle M, allocated for use on stream s.
+template <typename T>
+ck_status mat_alloc(ck_matrix &M, T **p, int64_t count, hipStream_t s) {
+    void *q = nullptr;
+    const ck_status st = mem_alloc(M.mem, &q, (size_t)(count > 0 ? count : 1) * sizeof(T), s);
+    *p = (T *)q;
+    return st;
+}
+inline void mat_free(ck_matrix &M, void *p) { mem_free(M.mem, p); }
 
 // Arguments of one product y = alpha*A*x + beta*y.
 //  skip   : if non-null and *skip != 0 when the launch starts, it does nothing

@@ -38,18 +38,20 @@ double us_since(Clock::time_point t0) {
 }
 
 // ---------------------------------------------------------------------------
-// Device workspace owned by one solve, from the handle-memory cache; it goes
-// back once the solve's stream has finished with it.
+// Device workspace owned by one solve, from the handle's memory source (the
+// caller's allocator, or the handle-memory cache); it goes back once the
+// solve's stream has finished with it.
 struct Workspace {
+    ck_matrix &M;
     hipStream_t s;
     std::vector<void *> blocks;
-    explicit Workspace(hipStream_t st) : s(st) {}
+    Workspace(ck_matrix &m, hipStream_t st) : M(m), s(st) {}
     template <typename T>
     ck_status get(T **p, int64_t count) {
-        void *q = nullptr;
-        CK_TRY(dev_cache_alloc(&q, (size_t)std::max<int64_t>(count, 1) * sizeof(T)));
+        T *q = nullptr;
+        CK_TRY(mat_alloc(M, &q, std::max<int64_t>(count, 1), s));
         blocks.push_back(q);
-        *p = (T *)q;
+        *p = q;
         return CK_OK;
     }
     ~Workspace() {
@@ -57,7 +59,7 @@ struct Workspace {
             return;
         (void)hipStreamSynchronize(s);
         for (void *q : blocks)
-            dev_cache_free(q);
+            mat_free(M, q);
     }
 };
 
@@ -524,7 +526,7 @@ ck_status cg_core(SolveCtx &c, T *x, T *r, T *p, T *q, T *partials, CgDev<T> *de
 
 ck_status cg_fp64(SolveCtx &c, const double *b, double *x) {
     ck_matrix &M = c.M;
-    Workspace ws(c.s);
+    Workspace ws(c.M, c.s);
     double *r, *p, *q, *partials;
     CgDev<double> *dev;
     Fp64Scratch f;
@@ -573,7 +575,7 @@ ck_status cg_fp64(SolveCtx &c, const double *b, double *x) {
 // or after max(50, 4 sqrt(n)) iterations.
 ck_status cg_mixed(SolveCtx &c, const double *b, double *x) {
     ck_matrix &M = c.M;
-    Workspace ws(c.s);
+    Workspace ws(c.M, c.s);
     double *r64, *scal;
     float *r, *p, *q, *d, *partials;
     CgDev<float> *dev;
@@ -643,7 +645,7 @@ ck_status gmres_run(SolveCtx &c, const double *b, double *x) {
     const int m = c.o.restart > 0 ? c.o.restart : 30;
     if (m > kMaxRestart)
         return fail(CK_E_INVALID, "restart length %d above %d", m, kMaxRestart);
-    Workspace ws(c.s);
+    Workspace ws(c.M, c.s);
     const int64_t ldv = ceil_div(std::max<int64_t>(M.n, 1), 64) * 64;
     T *V, *partials;
     double *r64;
@@ -740,7 +742,7 @@ constexpr int64_t kSmallN = 16384;
 
 // FP64 CG of a system of at most kWgCgMaxN rows in one single-workgroup launch
 ck_status wg_cg_solve(SolveCtx &c, const double *b, double *x) {
-    Workspace ws(c.s);
+    Workspace ws(c.M, c.s);
     WgCgOut *out;
     CK_TRY(ws.get(&out, 1));
     const int max_iter = c.o.max_iter > 0 ? c.o.max_iter : 100000;
@@ -764,7 +766,7 @@ ck_status small_solve(SolveCtx &c, const double *b, double *x, bool cg, int m) {
     const bool fp32 = c.o.precision == CK_PREC_MIXED;
     const int kind = cg ? B_CG : B_GMRES;
     const int64_t ld = ceil_div(M.n, 64) * 64;
-    Workspace ws(c.s);
+    Workspace ws(c.M, c.s);
     BSlot *slot;
     BStat *stat;
     int *active;
@@ -914,7 +916,7 @@ ck_status solve(ck_handle hnd, const double *b, double *x, const ck_solve_opts *
         res->t_total_us = us_since(t0);
         return st;
     }
-    Workspace ws(s);
+    Workspace ws(M, s);
     int64_t carry = std::max(spmv_carry_bytes(M, ck_config{CK_FMT_CSR, CK_ALG_MERGE, 0, 0}, false),
                              std::max(spmv_carry_bytes(M, ck_config{CK_FMT_COO, 0, 0, 0}, false),
                                       spmv_carry_bytes(M, ck_config{CK_FMT_CSR, CK_ALG_PANEL, 0, 0},

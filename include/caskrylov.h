@@ -281,6 +281,23 @@ ck_status ck_get_active(ck_handle h, ck_config *out);
 ck_status spmv_apply(ck_handle h, const ck_config *cfg, double alpha, const double *d_x,
                      double beta, double *d_y, hipStream_t s);
 
+/* spmv_apply_noalloc -- spmv_apply that allocates nothing, for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation).  Same arguments, result and
+ * kernels as spmv_apply.  The workspace of the configurations that need one
+ * (CSR-merge and COO carries, CSR-panel partial vectors) comes from a fixed
+ * 64 MiB device array inside the library, one per GPU, held until the
+ * process ends; a product that would need more returns CK_E_UNSUPPORTED
+ * (CSR-merge and COO always fit; CSR-panel fits while panels x nrows x 8
+ * bytes stays well under 64 MiB).  The first call on a device looks the
+ * array's address up (no allocation).  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (on different streams, or from
+ * different threads without ordering) race and must not be issued.  The
+ * format `cfg` names must have been converted beforehand (spmv_convert
+ * allocates). */
+ck_status spmv_apply_noalloc(ck_handle h, const ck_config *cfg, double alpha, const double *d_x,
+                             double beta, double *d_y, hipStream_t s);
+
 /* spmv_apply_f32 -- the same product on the FP32 copy of the values (handle
  * created with CK_KEEP_FP32), FP32 vectors and FP32 accumulation. */
 ck_status spmv_apply_f32(ck_handle h, const ck_config *cfg, float alpha, const float *d_x,

@@ -207,6 +207,7 @@ SIGNATURES = {
     "ck_get_active": (_i32, [_vp, C.POINTER(Config)]),
     "spmv_apply": (_i32, [_vp, C.POINTER(Config), _dbl, _vp, _dbl, _vp, _vp]),
     "spmv_apply_f32": (_i32, [_vp, C.POINTER(Config), _flt, _vp, _flt, _vp, _vp]),
+    "spmv_apply_noalloc": (_i32, [_vp, C.POINTER(Config), _dbl, _vp, _dbl, _vp, _vp]),
     "cg_solve": (_i32, [_vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveResult), _vp]),
     "gmres_solve": (_i32, [_vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveResult), _vp]),
     "ck_export_ell": (_i32, [_vp, _vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp]),
@@ -405,6 +406,14 @@ def spmv_apply(h, x, y, alpha=1.0, beta=0.0, cfg=None, stream=None):
     _check(lib().spmv_apply(h, C.byref(cfg) if cfg is not None else None, float(alpha),
                             _ptr(x, torch.float64), float(beta), _ptr(y, torch.float64),
                             _stream(stream)))
+
+
+def spmv_apply_noalloc(h, x, y, alpha=1.0, beta=0.0, cfg=None, stream=None):
+    """spmv_apply whose workspace is the library's fixed device array."""
+    import torch
+    _check(lib().spmv_apply_noalloc(h, C.byref(cfg) if cfg is not None else None, float(alpha),
+                                    _ptr(x, torch.float64), float(beta), _ptr(y, torch.float64),
+                                    _stream(stream)))
 
 
 def spmv_apply_f32(h, x, y, alpha=1.0, beta=0.0, cfg=None, stream=None):

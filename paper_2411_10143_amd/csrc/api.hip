@@ -535,6 +535,61 @@ ck_status spmv_apply(ck_handle h, const ck_config *cfg, double alpha, const doub
     return launch_spmv<double>(*h, c, a, s);
 }
 
+// ---- allocation-free product ------------------------------------------------
+// The carry workspace of spmv_apply_noalloc (merge-path and COO carries,
+// CSR-panel partial vectors) lives in this fixed device array, one copy per
+// GPU for the life of the process.  In host code `scratch` only names the
+// symbol; its device address on the current GPU comes from
+// hipGetSymbolAddress, looked up once per device and kept.
+constexpr int64_t kNoAllocScratchBytes = int64_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+static std::mutex g_scratch_mu;
+static std::map<int, void *> g_scratch_ptr;   // device -> address of its `scratch`
+
+static ck_status scratch_ptr(void **out) {
+    int dev = 0;
+    CK_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it == g_scratch_ptr.end()) {
+        void *p = nullptr;
+        CK_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p)
+            return fail(CK_E_HIP, "no device address for the scratch array on device %d", dev);
+        it = g_scratch_ptr.emplace(dev, p).first;
+    }
+    *out = it->second;
+    return CK_OK;
+}
+
+ck_status spmv_apply_noalloc(ck_handle h, const ck_config *cfg, double alpha, const double *d_x,
+                             double beta, double *d_y, hipStream_t s) {
+    if (!h || (h->n > 0 && !d_y) || (h->ncols > 0 && !d_x))
+        return fail(CK_E_INVALID, "NULL argument");
+    SpmvArgs<double> a;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.x = d_x;
+    a.y = d_y;
+    const ck_config c = cfg ? *cfg : active_of(h);
+    if (!config_valid(c))
+        return fail(CK_E_INVALID, "invalid SpMV configuration");
+    const bool carries = c.format == CK_FMT_COO ||
+                         (c.format == CK_FMT_CSR &&
+                          (c.algorithm == CK_ALG_MERGE || c.algorithm == CK_ALG_PANEL));
+    if (carries && h->n > 0) {
+        const int64_t need = spmv_carry_bytes(*h, c, false);
+        if (need > kNoAllocScratchBytes)
+            return fail(CK_E_UNSUPPORTED,
+                        "spmv_apply_noalloc: %s needs %lld bytes of workspace for this matrix, "
+                        "above the fixed %lld-byte scratch array (use spmv_apply)",
+                        kernel_name(c, false), (long long)need, (long long)kNoAllocScratchBytes);
+        CK_TRY(scratch_ptr(&a.carry));
+    }
+    return launch_spmv<double>(*h, c, a, s);
+}
+
 ck_status spmv_apply_f32(ck_handle h, const ck_config *cfg, float alpha, const float *d_x,
                          float beta, float *d_y, hipStream_t s) {
     if (!h || (h->n > 0 && !d_y) || (h->ncols > 0 && !d_x))

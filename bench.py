@@ -67,6 +67,17 @@ class KernelLedger:
         return max(self.k, key=lambda name: self.k[name][1])
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
 def flush_cache(buf):
     buf.fill_(1.0)   # 1 GiB streaming write evicts the 256 MB last-level cache
 
@@ -239,21 +250,28 @@ def bench_spmv_set(args):
     if not args.no_cpu_baseline:
         import oracle
         xs = [d["x"].cpu().numpy() for d in dev]
-        # whole passes over the set (one product per matrix each) until about
-        # 10 s of CPU time have been spent
-        passes = 0
-        tc = time.perf_counter()
-        while passes == 0 or (time.perf_counter() - tc < 10.0 and passes < 200):
-            for A, x in zip(mats, xs):
-                oracle.spmv(A, x)
-            passes += 1
-        dt = time.perf_counter() - tc
-        cpu = dict(value=round(passes * sum(nbytes) / dt / 1e9, 3), unit="GB/s", cores=1,
+
+        def passes_for(seconds, parallel):
+            # whole passes over the set (one product per matrix each)
+            passes = 0
+            tc = time.perf_counter()
+            while passes == 0 or (time.perf_counter() - tc < seconds and passes < 400):
+                for A, x in zip(mats, xs):
+                    oracle.spmv(A, x, parallel=parallel)
+                passes += 1
+            return passes, time.perf_counter() - tc
+
+        pa, dta = passes_for(8.0, True)
+        p1, dt1 = passes_for(8.0, False)
+        threads = oracle.threads(parallel=True)
+        cpu = dict(value=round(pa * sum(nbytes) / dta / 1e9, 3), unit="GB/s", cores=threads,
                    kind="oracle",
-                   sample=f"{passes} passes of one FP64 product per matrix of the "
+                   sample=f"{pa} passes of one FP64 product per matrix of the "
                           f"{len(mats)}-matrix set ({sum(nbytes) / 1e9:.2f} GB algorithmic per "
-                          f"pass), single-threaded plain C, {dt:.1f} s; host has "
-                          f"{os.cpu_count()} logical CPUs")
+                          f"pass), plain C with OpenMP over rows on {threads} threads, "
+                          f"{dta:.1f} s; host has {os.cpu_count()} logical CPUs ({_cpu_model()})",
+                   single_core=dict(value=round(p1 * sum(nbytes) / dt1 / 1e9, 3), unit="GB/s",
+                                    cores=1, sample=f"{p1} passes, {dt1:.1f} s"))
 
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
@@ -312,6 +330,12 @@ def bench_spmv_set(args):
             "geomean_t_default_over_t_best": round(geomean(t_def / best), 4),
             "picked_best": int(np.sum(ratio <= 1.0)), "within_10pct": int(np.sum(ratio <= 1.10)),
             "of": len(mats), "cold_large": cold})
+    if not args.no_solvers:
+        try:
+            out["solvers"] = solver_summary(args)
+        except Exception as e:            # the SpMV line stands on its own
+            log(f"[solvers] failed: {e!r}")
+            out["solvers"] = {"error": repr(e)}
     if args.table and not args.no_table:
         rows = []
         for m, A in enumerate(mats):
@@ -662,6 +686,174 @@ def bench_serve(args):
                 None, dtype="f32+f64")
 
 
+def _timed_solves(ck, fn, Mx, b, count, warmup=1, **kw):
+    """Wall time of `count` solves from the call to the result on the host
+    (the matrix resident), after `warmup` untimed ones; the last x and result."""
+    import torch
+    lat, r, x = [], None, None
+    for i in range(warmup + count):
+        x = torch.zeros_like(b)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn(Mx.handle, b, x, **kw)
+        dt = time.perf_counter() - t
+        assert r["status"] == ck.CK_OK, r
+        if i >= warmup:
+            lat.append(dt)
+    return lat, r, x
+
+
+def _lat(lat):
+    return {"solves_per_s": round(len(lat) / sum(lat), 3),
+            "p50_ms": round(1e3 * float(np.percentile(lat, 50)), 3),
+            "p99_ms": round(1e3 * float(np.percentile(lat, 99)), 3), "solves": len(lat)}
+
+
+def solver_summary(args):
+    """The metric's solver half in the default run: CG on the 64x64 Laplacian
+    (default path and the default CSR-vector kernel), async CG and mixed vs
+    FP64 CG on the 3D Poisson and graph Laplacian systems, mixed vs FP64
+    GMRES(30) on convection-diffusion 1024^2, and a shortened request-loop
+    trace at tol 1e-10.  Each result's true residual is checked against the
+    oracle's (all-core build)."""
+    import torch
+
+    import oracle
+    import paper_2411_10143_amd as ck
+    from paper_2411_10143_amd.serving import ServingWorkload, latency_summary, poisson_arrivals
+    from synth import workloads as W
+    out = {}
+    fe = lambda x, xs: float(np.linalg.norm(x.cpu().numpy() - xs) / np.linalg.norm(xs))
+
+    # -- CG, 2D Laplacian 64^2 ------------------------------------------------
+    A, xs = W.lap2d_64()
+    Mx = ck.Matrix.from_csr(A)
+    b = _rhs(ck, Mx, xs)
+    lat, r, x = _timed_solves(ck, ck.cg_solve, Mx, b, 100, 5, tol=1e-10)
+    assert oracle.relres(A, b.cpu().numpy(), x.cpu().numpy()) <= 1e-10
+    row = {"default_path": {**_lat(lat), "iterations": r["iterations"],
+                            "kernel": "cg_wg<4>: whole solve in one workgroup, one lane per row"}}
+    cfg = ck.default_config(Mx.handle)
+    lat, r, x = _timed_solves(ck, ck.cg_solve, Mx, b, 100, 5, tol=1e-10, config=cfg)
+    assert oracle.relres(A, b.cpu().numpy(), x.cpu().numpy()) <= 1e-10
+    row["default_csr_vector"] = {**_lat(lat), "iterations": r["iterations"],
+                                 "kernel": f"batched_chunk, {ck.CONFIG_NAMES[ck.config_id(cfg)]} "
+                                           "product, whole solve in one launch"}
+    if not args.no_cpu_baseline:
+        bh = b.cpu().numpy()
+        for par in (True, False):
+            n, tc = 0, time.perf_counter()
+            while n < 5 or time.perf_counter() - tc < 3.0:
+                oracle.cg(A, bh, tol=1e-10, parallel=par)
+                n += 1
+            dt = time.perf_counter() - tc
+            row["cpu_oracle_all_cores" if par else "cpu_oracle_one_core"] = {
+                "solves_per_s": round(n / dt, 2), "cores": oracle.threads(par),
+                "sample": f"{n} complete oracle CG solves"}
+    out["cg_lap2d_64"] = row
+    Mx.close()
+    log("[solvers] cg_lap2d_64 done")
+
+    # -- CG on 3D Poisson 128^3 and the 2^20 graph Laplacian --------------------
+    rows = {}
+    for name, (A, xs) in (("poisson3d_128", W.poisson3d_128()),
+                          ("graph_laplacian_2^20", W.graph_laplacian_1m())):
+        Mx = ck.Matrix.from_csr(A, keep_fp32=True)
+        b = _rhs(ck, Mx, xs)
+        bh = b.cpu().numpy()
+        cnt = 5 if A.n <= 2_200_000 and name.startswith("poisson") else 3
+        lat, ra, x = _timed_solves(ck, ck.cg_solve, Mx, b, cnt, 1, tol=1e-10,
+                                   async_=ck.CK_EXEC_ASYNC)
+        rr = oracle.relres(A, bh, x.cpu().numpy(), parallel=True)
+        assert rr <= 1e-10, (name, rr)
+        row = {"n": A.n, "nnz": A.nnz,
+               "async": {**_lat(lat), "iterations": ra["iterations"],
+                         "switch_iter": ra["switch_iter"],
+                         "final_config": ck.CONFIG_NAMES[ra["final_config"]],
+                         "oracle_true_relres": rr, "forward_error": fe(x, xs)}}
+        # mixed vs FP64 on the configuration the cascade predicts, kept fixed
+        cfg = ck.spmv_select(ck.spmv_features(Mx.handle))
+        try:
+            ck.spmv_convert(Mx.handle, cfg)
+        except ck.CkError as e:
+            if e.status != ck.CK_E_UNSUPPORTED:
+                raise
+            cfg = ck.default_config(Mx.handle)
+        for prec, key in ((ck.CK_PREC_FP64, "fp64"), (ck.CK_PREC_MIXED, "mixed")):
+            lat, r, x = _timed_solves(ck, ck.cg_solve, Mx, b, 2 if cnt == 3 else 4, 1,
+                                      tol=1e-10, precision=prec, config=cfg)
+            rr = oracle.relres(A, bh, x.cpu().numpy(), parallel=True)
+            assert rr <= 1e-10, (name, key, rr)
+            row[key] = {**_lat(lat), "iterations": r["iterations"],
+                        "outer_steps": r["outer_steps"], "oracle_true_relres": rr,
+                        "forward_error": fe(x, xs)}
+        row["predicted_config"] = ck.CONFIG_NAMES[ck.config_id(cfg)]
+        row["mixed_speedup"] = round(row["mixed"]["solves_per_s"] / row["fp64"]["solves_per_s"], 3)
+        rows[name] = row
+        Mx.close()
+        del b
+        log(f"[solvers] {name} done")
+    out["cg_async_and_mixed"] = rows
+
+    # -- GMRES(30), convection-diffusion 1024^2 ----------------------------------
+    A, xs = W.convdiff_1024()
+    Mx = ck.Matrix.from_csr(A, keep_fp32=True)
+    b = _rhs(ck, Mx, xs)
+    cfg = ck.spmv_select(ck.spmv_features(Mx.handle))
+    try:
+        ck.spmv_convert(Mx.handle, cfg)
+    except ck.CkError as e:
+        if e.status != ck.CK_E_UNSUPPORTED:
+            raise
+        cfg = ck.default_config(Mx.handle)
+    row = {"predicted_config": ck.CONFIG_NAMES[ck.config_id(cfg)]}
+    xres = {}
+    for prec, key in ((ck.CK_PREC_FP64, "fp64"), (ck.CK_PREC_MIXED, "mixed")):
+        lat, r, x = _timed_solves(ck, ck.gmres_solve, Mx, b, 1, 1, tol=1e-10, restart=30,
+                                  max_iter=200000, precision=prec, config=cfg)
+        rr = oracle.relres(A, b.cpu().numpy(), x.cpu().numpy(), parallel=True)
+        assert rr <= 1e-10, (key, rr)
+        xres[key] = x.cpu().numpy()
+        row[key] = {**_lat(lat), "iterations": r["iterations"], "outer_steps": r["outer_steps"],
+                    "oracle_true_relres": rr, "forward_error": fe(x, xs)}
+    row["mixed_speedup"] = round(row["mixed"]["solves_per_s"] / row["fp64"]["solves_per_s"], 3)
+    row["mixed_vs_fp64_rel_diff"] = float(np.linalg.norm(xres["mixed"] - xres["fp64"]) /
+                                          np.linalg.norm(xres["fp64"]))
+    out["gmres_convdiff_1024"] = row
+    Mx.close()
+    del b
+    log("[solvers] gmres_convdiff_1024 done")
+
+    # -- request loop, shortened trace at tol 1e-10 ------------------------------
+    pool = W.serving_pool()
+    nreq = args.serve_requests
+    Wl = ServingWorkload(pool, nreq, tol=1e-10)
+    cap = latency_summary(Wl.run())
+    done = Wl.run(arrivals_s=poisson_arrivals(nreq, 0.8 * cap["solves_per_s"], seed=5001))
+    st = Wl.stats()
+    worst = 0.0
+    for c in done:
+        t = c["tag"]
+        Ap = pool[Wl.mid[t]][0]
+        worst = max(worst, oracle.relres(Ap, Wl.b[t].cpu().numpy(), Wl.x[t].cpu().numpy(),
+                                         parallel=True))
+    out["serve"] = {"requests": nreq, "tol": 1e-10,
+                    "closed_loop_solves_per_s": round(cap["solves_per_s"], 3),
+                    "arrival_rate_per_s": round(0.8 * cap["solves_per_s"], 3),
+                    "solves_per_s": round(st["solves_per_s"], 3),
+                    "p50_ms": round(st["p50_latency_us"] * 1e-3, 3),
+                    "p99_ms": round(st["p99_latency_us"] * 1e-3, 3),
+                    "ok": int(sum(c["status"] == ck.CK_OK for c in done)),
+                    "worst_oracle_true_relres": worst,
+                    "batched_fraction": round(sum(c["path"] == 0 for c in done) / len(done), 3),
+                    "workload": "64-matrix pool (n log-uniform 1e3-1e6), Poisson arrivals at "
+                                "0.8x closed-loop capacity, mixed FP32/FP64, CG if symmetric "
+                                "else GMRES(30); latency and rate from ck_server_get_stats"}
+    Wl.close()
+    log("[solvers] serve done")
+    return out
+
+
 # ---------------------------------------------------------------------------
 def main():
     p = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
@@ -679,6 +871,10 @@ def main():
     p.add_argument("--table", default=None, help="write the per-matrix timing table (JSON)")
     p.add_argument("--no-table", action="store_true",
                    help="spmv_set: skip the untimed exhaustive and cold tables (profiler runs)")
+    p.add_argument("--no-solvers", action="store_true",
+                   help="spmv_set: skip the untimed solver and serving summary (profiler runs)")
+    p.add_argument("--serve-requests", type=int, default=300,
+                   help="spmv_set: requests in the solver summary's serving trace")
     p.add_argument("--grid", type=int, default=1024, help="gmres_mixed grid side")
     p.add_argument("--requests", type=int, default=2000, help="serve: requests per trace")
     p.add_argument("--tol", type=float, default=1e-8, help="serve: tolerance")

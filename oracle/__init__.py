@@ -19,27 +19,43 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_LIB_OMP = os.path.join(_HERE, "liboracle_omp.so")   # the same source built with OpenMP
 
 OK, INVALID, NOT_CONVERGED, BREAKDOWN, UNSUPPORTED = 0, -1, -4, -5, -6
 
 GCC_FLAGS = ["-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-             "-fno-fast-math", "-Wall", "-Wno-unused-function"]
+             "-fno-fast-math", "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas"]
+
+
+def _build_one(out, extra, force):
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", *GCC_FLAGS, *extra, _SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, out)
+    return out
 
 
 def build(force: bool = True) -> str:
-    """Compile ``oracle.c`` with gcc into ``liboracle.so``."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.run(["gcc", *GCC_FLAGS, _SRC, "-o", tmp, "-lm"], check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+    """Compile ``oracle.c`` with gcc into ``liboracle.so`` (single-threaded)
+    and ``liboracle_omp.so`` (OpenMP over the rows of the SpMV)."""
+    _build_one(_LIB_OMP, ["-fopenmp"], force)
+    return _build_one(_LIB, [], force)
 
 
 _lib = None
+_lib_omp = None
 
 
-def lib():
-    global _lib
+def lib(parallel: bool = False):
+    """The single-threaded oracle, or with parallel=True its OpenMP build
+    (same bits; SpMV rows on all threads)."""
+    global _lib, _lib_omp
+    if parallel:
+        if _lib_omp is None:
+            _build_one(_LIB_OMP, ["-fopenmp"], False)
+            _lib_omp = C.CDLL(_LIB_OMP)
+            _declare(_lib_omp)
+        return _lib_omp
     if _lib is None:
         alt = os.environ.get("ORACLE_LIB")   # a separately built variant (mutation tests)
         if alt:
@@ -51,6 +67,11 @@ def lib():
     return _lib
 
 
+def threads(parallel: bool = True) -> int:
+    """Threads the oracle's SpMV uses in that build."""
+    return int(lib(parallel).orc_threads())
+
+
 _i64 = C.c_int64
 _pd = C.POINTER(C.c_double)
 _pi32 = C.POINTER(C.c_int32)
@@ -58,6 +79,8 @@ _pi64 = C.POINTER(C.c_int64)
 
 
 def _declare(L):
+    L.orc_threads.argtypes = []
+    L.orc_threads.restype = C.c_int
     L.orc_spmv.argtypes = [_i64, _pi32, _pi32, _pd, C.c_double, _pd, C.c_double, _pd]
     L.orc_spmv.restype = None
     L.orc_relres.argtypes = [_i64, _pi32, _pi32, _pd, _pd, _pd]
@@ -111,20 +134,20 @@ def _csr(A):
     return rp, col, val
 
 
-def spmv(A, x, alpha=1.0, beta=0.0, y=None):
+def spmv(A, x, alpha=1.0, beta=0.0, y=None, parallel=False):
     rp, col, val = _csr(A)
     x = np.ascontiguousarray(x, dtype=np.float64)
     out = np.zeros(A.n) if y is None else np.array(y, dtype=np.float64, copy=True)
-    lib().orc_spmv(A.n, _p(rp, C.c_int32), _p(col, C.c_int32), _p(val, C.c_double),
+    lib(parallel).orc_spmv(A.n, _p(rp, C.c_int32), _p(col, C.c_int32), _p(val, C.c_double),
                    float(alpha), _p(x, C.c_double), float(beta), _p(out, C.c_double))
     return out
 
 
-def relres(A, b, x):
+def relres(A, b, x, parallel=False):
     rp, col, val = _csr(A)
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.ascontiguousarray(x, dtype=np.float64)
-    return lib().orc_relres(A.n, _p(rp, C.c_int32), _p(col, C.c_int32), _p(val, C.c_double),
+    return lib(parallel).orc_relres(A.n, _p(rp, C.c_int32), _p(col, C.c_int32), _p(val, C.c_double),
                             _p(b, C.c_double), _p(x, C.c_double))
 
 
@@ -271,7 +294,7 @@ def cascade(trees, f15):
     return [int(v) for v in out]
 
 
-def cg(A, b, x0=None, tol=1e-10, maxit=100000, hist=0, nrec=0):
+def cg(A, b, x0=None, tol=1e-10, maxit=100000, hist=0, nrec=0, parallel=False):
     rp, col, val = _csr(A)
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
@@ -282,7 +305,7 @@ def cg(A, b, x0=None, tol=1e-10, maxit=100000, hist=0, nrec=0):
     rh = np.full(hist, np.nan) if hist else None
     R = np.zeros((nrec, A.n)) if nrec else None
     P = np.zeros((nrec, A.n)) if nrec else None
-    st = lib().orc_cg(A.n, _p(rp, C.c_int32), _p(col, C.c_int32), _p(val, C.c_double),
+    st = lib(parallel).orc_cg(A.n, _p(rp, C.c_int32), _p(col, C.c_int32), _p(val, C.c_double),
                       _p(b, C.c_double), _p(x, C.c_double), float(tol), int(maxit),
                       C.byref(it), C.byref(rr), _p(ah, C.c_double), _p(bh, C.c_double),
                       _p(rh, C.c_double), int(hist), _p(R, C.c_double), _p(P, C.c_double),
@@ -303,14 +326,14 @@ def arnoldi(A, v0, m):
     return st, V.T.copy(), H.T.copy(), steps.value
 
 
-def gmres(A, b, x0=None, m=30, tol=1e-10, maxit=100000, hist=0):
+def gmres(A, b, x0=None, m=30, tol=1e-10, maxit=100000, hist=0, parallel=False):
     rp, col, val = _csr(A)
     b = np.ascontiguousarray(b, dtype=np.float64)
     x = np.zeros(A.n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
     it = C.c_int64()
     rr = C.c_double()
     rh = np.full(hist, np.nan) if hist else None
-    st = lib().orc_gmres(A.n, _p(rp, C.c_int32), _p(col, C.c_int32), _p(val, C.c_double),
+    st = lib(parallel).orc_gmres(A.n, _p(rp, C.c_int32), _p(col, C.c_int32), _p(val, C.c_double),
                          _p(b, C.c_double), _p(x, C.c_double), int(m), float(tol), int(maxit),
                          C.byref(it), C.byref(rr), _p(rh, C.c_double), int(hist))
     return dict(status=st, x=x, iters=it.value, relres=rr.value, res=rh)

@@ -7,9 +7,12 @@
  * includes this file; it is used by the test-suite, by the smoke check and by
  * the CPU-baseline leg of the benchmark.  It shares no code with the GPU path.
  *
- * Everything is sequential IEEE double precision, compiled without FMA
- * contraction and without fast-math, so every result is reproducible.  The
- * code favours being checkable by eye over speed.
+ * Everything is IEEE double precision, compiled without FMA contraction and
+ * without fast-math, so every result is reproducible.  The code favours
+ * being checkable by eye over speed.  Built with OpenMP (the all-core CPU
+ * baseline), only the rows of orc_spmv are shared out among threads; each
+ * row is still summed alone in ascending order, so both builds give the same
+ * bits.
  *
  * Contents and the passage each follows:
  *   orc_spmv            y = alpha*A*x + beta*y over CSR (the kernel the whole
@@ -44,6 +47,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define ORC_OK 0
 #define ORC_INVALID (-1)
@@ -61,6 +67,7 @@
 void orc_spmv(int64_t n, const int32_t *rp, const int32_t *col, const double *val,
               double alpha, const double *x, double beta, double *y)
 {
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         double s = 0.0;
         for (int64_t k = rp[i]; k < rp[i + 1]; ++k)
@@ -70,6 +77,16 @@ void orc_spmv(int64_t n, const int32_t *rp, const int32_t *col, const double *va
         else
             y[i] = alpha * s + beta * y[i];
     }
+}
+
+/* Threads orc_spmv runs on (1 without OpenMP). */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 static double dot(int64_t n, const double *a, const double *b)

@@ -65,6 +65,8 @@ static void release(ck_matrix *M) {
     mat_free(*M, M->panel_val32);
     mat_free(*M, M->merge_part);
     mat_free(*M, M->panel_part);
+    mat_free(*M, M->panel_row);
+    mat_free(*M, M->panel_boff);
     for (auto &kv : M->carry)
         mat_free(*M, kv.second);
     delete M;
@@ -149,10 +151,14 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
                                        M.panel_val, M.panel_val32, s);
         M.panel_P = P;
         M.panel_W = W;
+        M.panel_rows = N;
         if (st == CK_OK)
-            st = mat_alloc(M, &M.panel_part, merge_part_entries_rows(N, M.nnz), s);
+            st = panel_make_rows(M, tmp, s);   // only the non-empty panel rows, if that pays
+        const int64_t R = M.panel_rows;
         if (st == CK_OK)
-            st = launch_merge_partition_rows(N, M.nnz, M.panel_rp, M.panel_part, s);
+            st = mat_alloc(M, &M.panel_part, merge_part_entries_rows(R, M.nnz), s);
+        if (st == CK_OK)
+            st = launch_merge_partition_rows(R, M.nnz, M.panel_rp, M.panel_part, s);
         if (st == CK_OK)
             st = mark_built(M.has_panel, s);
         (void)hipStreamSynchronize(s);   // the conversion has finished with tmp

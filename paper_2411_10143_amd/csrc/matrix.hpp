@@ -27,10 +27,18 @@ struct ck_matrix {
     // COO (after conversion): row index per stored entry; col/val shared with CSR
     int32_t *coo_row = nullptr;
     std::atomic<bool> has_coo{false};
-    // CSR-panel (after conversion): P column panels of width W, panel-major;
-    // panel_rp[p*n + i] = start of row i in panel p (P*n + 1 entries)
+    // CSR-panel (after conversion): P column panels of width W, panel-major.
+    // Dense layout (panel_row == nullptr): panel_rows = P*n, panel_rp[p*n + i]
+    // = start of row i in panel p.  Row-list layout: only the panel_rows
+    // non-empty panel rows, in panel-major order; panel_row[k] = the matrix
+    // row of panel row k, panel_rp[k] its start, and panel_boff[p*(B+1) + j]
+    // = the first panel row of panel p whose row is >= 256 j (B = ceil(n/256))
     int panel_P = 0;
     int64_t panel_W = 0;
+    int64_t panel_rows = 0;
+    int64_t panel_B = 0;
+    int32_t *panel_row = nullptr;
+    int32_t *panel_boff = nullptr;
     int32_t *panel_rp = nullptr;
     int32_t *panel_col = nullptr;
     double *panel_val = nullptr;

@@ -129,6 +129,94 @@ __global__ __launch_bounds__(256) void scan_add(int64_t N, int *__restrict__ out
         out[g] += offs[g / 2048];
 }
 
+// flag[k] = 1 if panel row k holds entries (in place over the counts)
+__global__ __launch_bounds__(256) void panel_nonempty(int64_t N, int *__restrict__ cnt) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k < N)
+        cnt[k] = cnt[k] > 0 ? 1 : 0;
+}
+
+// Row list of the non-empty panel rows: panel row k = p*n + i with entries
+// becomes list entry pos[k] (row i, start prp[k]); the list ends at nnz.
+__global__ __launch_bounds__(256) void panel_compact(int64_t N, int64_t n, int64_t NE, int nnz,
+                                                     const int *__restrict__ prp,
+                                                     const int *__restrict__ pos,
+                                                     int *__restrict__ prow,
+                                                     int *__restrict__ prp_ne) {
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (k == 0)
+        prp_ne[NE] = nnz;
+    if (k >= N)
+        return;
+    const int start = prp[k];
+    if (prp[k + 1] > start) {
+        const int j = pos[k];
+        prow[j] = (int)(k % n);
+        prp_ne[j] = start;
+    }
+}
+
+// boff[p*(B+1) + j] = list position of panel p's first row >= 256 j (rows
+// past n clamp to n, so boff[p*(B+1) + B] ends panel p)
+__global__ __launch_bounds__(256) void panel_block_offsets(int64_t n, int P, int64_t B,
+                                                           const int *__restrict__ pos,
+                                                           int *__restrict__ boff) {
+    const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (t >= (int64_t)P * (B + 1))
+        return;
+    const int64_t p = t / (B + 1), j = t % (B + 1);
+    boff[t] = pos[p * n + min(j * 256, n)];
+}
+
+// Row-list combine: workgroup row block [256 blk, 256 blk + 256) adds, panel
+// by panel in order, the partials of its rows' non-empty panel rows into an
+// LDS accumulator (a row appears at most once per panel, so the threads of
+// one panel step never share a slot); rows absent from a panel add nothing,
+// which gives the dense combine's sum bit for bit (a partial is never -0).
+template <typename T, bool BETA, bool DOT>
+__global__ __launch_bounds__(256) void panel_combine_rows(
+    int64_t n, int P, int64_t B, int64_t G, const int *__restrict__ boff,
+    const int *__restrict__ prow, const T *__restrict__ ypart, T alpha, T beta,
+    T *__restrict__ y, const T *__restrict__ x, T *__restrict__ partials,
+    const int *__restrict__ skip) {
+    if (skip != nullptr && *skip != 0)
+        return;
+    const int64_t b = ck::xcd_block(G);
+    if (b < 0)
+        return;
+    __shared__ T acc[256];
+    const int tid = threadIdx.x;
+    T mine = 0;
+    for (int64_t blk = b; blk < B; blk += G) {
+        const int64_t r0 = blk * 256;
+        acc[tid] = 0;
+        __syncthreads();
+        for (int p = 0; p < P; ++p) {
+            const int lo = boff[(int64_t)p * (B + 1) + blk];
+            const int hi = boff[(int64_t)p * (B + 1) + blk + 1];
+            for (int k = lo + tid; k < hi; k += 256)
+                acc[prow[k] - r0] += ypart[k];
+            __syncthreads();
+        }
+        const int64_t i = r0 + tid;
+        if (i < n) {
+            T out = alpha * acc[tid];
+            if (BETA)
+                out += beta * y[i];
+            y[i] = out;
+            if (DOT)
+                mine += out * x[i];
+        }
+        __syncthreads();   // acc is cleared for the next block only after every read
+    }
+    if constexpr (DOT) {
+        __shared__ T lds[4];
+        const T d = ck::block_sum(mine, lds);
+        if (threadIdx.x == 0)
+            partials[b] = d;
+    }
+}
+
 // y = alpha * sum_p ypart[p] + beta * y   (+ per-block partial of y.x for CG)
 template <typename T, bool BETA, bool DOT>
 __global__ __launch_bounds__(256) void panel_combine(int64_t n, int P, int64_t G,
@@ -212,6 +300,58 @@ ck_status launch_to_panel(const ck_matrix &M, int P, int64_t W, int *cnt, int *t
     return CK_OK;
 }
 
+ck_status panel_make_rows(ck_matrix &M, int *cnt, hipStream_t s) {
+    const int64_t n = M.n, N = (int64_t)M.panel_P * n;
+    M.panel_rows = N;
+    if (N == 0)
+        return CK_OK;
+    int *pos = nullptr;
+    CK_TRY(mat_alloc(M, &pos, N + 1 + panel_scan_tmp_elems(N), s));
+    hipLaunchKernelGGL(panel_nonempty, dim3(ceil_div(N, 256)), dim3(256), 0, s, N, cnt);
+    ck_status st = launch_scan_exclusive(N, cnt, pos, pos + N + 1, s);
+    int ne = 0;
+    if (st == CK_OK && (hipMemcpyAsync(&ne, pos + N, sizeof ne, hipMemcpyDeviceToHost, s) !=
+                            hipSuccess ||
+                        hipStreamSynchronize(s) != hipSuccess))
+        st = fail(CK_E_HIP, "panel row count read-back failed");
+    const int64_t NE = ne;
+    if (st != CK_OK || 4 * NE > 3 * N) {   // dense rows are cheaper (or failed)
+        (void)hipStreamSynchronize(s);
+        mat_free(M, pos);
+        return st;
+    }
+    const int64_t B = ceil_div(n, 256);
+    int *prow = nullptr, *prp_ne = nullptr, *boff = nullptr;
+    st = mat_alloc(M, &prow, NE, s);
+    if (st == CK_OK)
+        st = mat_alloc(M, &prp_ne, NE + 1, s);
+    if (st == CK_OK)
+        st = mat_alloc(M, &boff, (int64_t)M.panel_P * (B + 1), s);
+    if (st == CK_OK) {
+        hipLaunchKernelGGL(panel_compact, dim3(ceil_div(N, 256)), dim3(256), 0, s, N, n, NE,
+                           (int)M.nnz, M.panel_rp, pos, prow, prp_ne);
+        hipLaunchKernelGGL(panel_block_offsets, dim3(ceil_div((int64_t)M.panel_P * (B + 1), 256)),
+                           dim3(256), 0, s, n, M.panel_P, B, pos, boff);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+            st = fail(CK_E_HIP, "panel row list failed");
+    }
+    (void)hipStreamSynchronize(s);
+    mat_free(M, pos);
+    if (st != CK_OK) {
+        mat_free(M, prow);
+        mat_free(M, prp_ne);
+        mat_free(M, boff);
+        return st;
+    }
+    mat_free(M, M.panel_rp);
+    M.panel_rp = prp_ne;
+    M.panel_row = prow;
+    M.panel_boff = boff;
+    M.panel_rows = NE;
+    M.panel_B = B;
+    return CK_OK;
+}
+
 template <typename T>
 ck_status launch_panel_combine(const ck_matrix &M, const SpmvArgs<T> &a, const T *ypart,
                                int64_t G_dot, hipStream_t s) {
@@ -219,6 +359,23 @@ ck_status launch_panel_combine(const ck_matrix &M, const SpmvArgs<T> &a, const T
     const bool dot = a.cg != nullptr;
     const int64_t G = dot ? G_dot : std::min<int64_t>(ceil_div(M.n, 256), kRowBlocks);
     const dim3 grid(xcd_grid(G));
+    if (M.panel_row != nullptr) {
+        const int64_t B = M.panel_B;
+        if (dot)
+            hipLaunchKernelGGL((panel_combine_rows<T, false, true>), grid, dim3(256), 0, s, M.n,
+                               M.panel_P, B, G, M.panel_boff, M.panel_row, ypart, a.alpha, a.beta,
+                               a.y, a.x, a.dot_partials, a.skip);
+        else if (beta)
+            hipLaunchKernelGGL((panel_combine_rows<T, true, false>), grid, dim3(256), 0, s, M.n,
+                               M.panel_P, B, G, M.panel_boff, M.panel_row, ypart, a.alpha, a.beta,
+                               a.y, a.x, a.dot_partials, a.skip);
+        else
+            hipLaunchKernelGGL((panel_combine_rows<T, false, false>), grid, dim3(256), 0, s, M.n,
+                               M.panel_P, B, G, M.panel_boff, M.panel_row, ypart, a.alpha, a.beta,
+                               a.y, a.x, a.dot_partials, a.skip);
+        CK_HIP(hipGetLastError());
+        return CK_OK;
+    }
     if (dot)
         hipLaunchKernelGGL((panel_combine<T, false, true>), grid, dim3(256), 0, s, M.n, M.panel_P,
                            G, ypart, a.alpha, a.beta, a.y, a.x, a.dot_partials, a.skip);

@@ -14,6 +14,10 @@ int64_t panel_scan_tmp_elems(int64_t N);
 ck_status launch_scan_exclusive(int64_t N, const int *in, int *out, int *tmp, hipStream_t s);
 ck_status launch_to_panel(const ck_matrix &M, int P, int64_t W, int *cnt, int *tmp, int *prp,
                           int *pcol, double *pval, float *pval32, hipStream_t s);
+// After launch_to_panel (cnt = its per-panel-row counts, M.panel_rp the
+// dense row pointers): switch M to the row-list layout when at most 3/4 of
+// the P*n panel rows are non-empty (cnt is overwritten).  Returns when done.
+ck_status panel_make_rows(ck_matrix &M, int *cnt, hipStream_t s);
 // y = alpha * (sum of the P partial vectors, in panel order) + beta * y
 template <typename T>
 ck_status launch_panel_combine(const ck_matrix &M, const SpmvArgs<T> &a, const T *ypart,

@@ -130,7 +130,8 @@ int64_t handle_bytes(const ck_matrix &M) {
     if (M.has_hyb.load())
         b += 4 * M.hyb_nt + M.hyb_K * M.hyb_pitch * (12 + (M.hyb_val32 ? 4 : 0));
     if (M.has_panel.load())
-        b += 4 * ((int64_t)M.panel_P * M.n + 1) + M.nnz * (12 + (M.panel_val32 ? 4 : 0));
+        b += 4 * (M.panel_rows + 1) + M.nnz * (12 + (M.panel_val32 ? 4 : 0)) +
+             (M.panel_row ? 4 * M.panel_rows + 4 * (int64_t)M.panel_P * (M.panel_B + 1) : 0);
     return b;
 }
 

@@ -642,7 +642,9 @@ static int64_t carry_blocks(const ck_matrix &M, const ck_config &c) {
 int64_t spmv_carry_bytes(const ck_matrix &M, const ck_config &c, bool fp32) {
     if (c.format == CK_FMT_CSR && c.algorithm == CK_ALG_PANEL) {
         // per-panel partial sums, then (merge-path panels) the carries of the
-        // merge over the P*n panel rows
+        // merge over the panel rows; sized for the dense P*n layout (an upper
+        // bound: the row-list layout has fewer rows, and the size is also
+        // needed before the conversion decides)
         const int64_t rows = (int64_t)panel_count_for(M.ncols, 8) * M.n;
         const int64_t Gt = ceil_div(rows + M.nnz, 256 * kMergeIPT);
         return ((rows * (fp32 ? 4 : 8) + 255) / 256) * 256 +
@@ -837,16 +839,18 @@ static ck_status panel_merge_spmv(const ck_matrix &M, const SpmvArgs<T> &a, void
         pv = M.panel_val32;
     else
         pv = M.panel_val;
-    const int64_t rows = (int64_t)M.panel_P * M.n;
+    const int64_t rows = M.panel_rows;   // P*n, or the non-empty panel rows
     const int64_t Gt = ceil_div(rows + M.nnz, 256 * kMergeIPT);
     T *ypart = (T *)ws;
     int *crow = (int *)((char *)ws + ((rows * (int64_t)sizeof(T) + 255) / 256) * 256);
     T *cval = (T *)((char *)crow + ((Gt * (int64_t)sizeof(int) + 255) / 256) * 256);
-    hipLaunchKernelGGL((spmv_panel_merge<T>), dim3(xcd_grid(Gt)), dim3(256), 0, s, (int)rows,
-                       (int)M.nnz, Gt, M.panel_rp, M.panel_col, pv, a.x, ypart, crow, cval,
-                       M.panel_part, a.skip);
-    hipLaunchKernelGGL((carry_fixup<T>), dim3(ceil_div(Gt, 256)), dim3(256), 0, s, Gt, crow,
-                       cval, T(1), ypart, a.skip);
+    if (Gt > 0) {   // no panel rows at all (no entries, row-list layout): combine only
+        hipLaunchKernelGGL((spmv_panel_merge<T>), dim3(xcd_grid(Gt)), dim3(256), 0, s, (int)rows,
+                           (int)M.nnz, Gt, M.panel_rp, M.panel_col, pv, a.x, ypart, crow, cval,
+                           M.panel_part, a.skip);
+        hipLaunchKernelGGL((carry_fixup<T>), dim3(ceil_div(Gt, 256)), dim3(256), 0, s, Gt, crow,
+                           cval, T(1), ypart, a.skip);
+    }
     CK_HIP(hipGetLastError());
     return launch_panel_combine<T>(M, a, ypart, G_dot, s);
 }

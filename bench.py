@@ -152,6 +152,9 @@ def bench_spmv_set(args):
             f" {T[m].min():.2f}us default={T[m, default_id[-1]]:.2f}us")
 
     # ---- timed steps: ingest -> features -> select -> convert -> R products ---
+    # every device block of the step's handles from torch's caching allocator
+    # (the binding's default), or from the library's own cache
+    alloc = None if args.allocator == "library" else "torch"
     phase_ms = dict(ingest=0.0, features=0.0, select=0.0, convert=0.0, products=0.0,
                     release=0.0)
 
@@ -160,7 +163,7 @@ def bench_spmv_set(args):
         clk = time.perf_counter
         for m, (A, d) in enumerate(zip(mats, dev)):
             t0 = clk()
-            Mx = ck.Matrix(d["rp"], d["col"], d["val"], A.ncols)
+            Mx = ck.Matrix(d["rp"], d["col"], d["val"], A.ncols, allocator=alloc)
             t1 = clk()
             F = ck.spmv_features(Mx.handle, symmetry=False)   # the cascade's inputs only
             t2 = clk()
@@ -871,6 +874,8 @@ def main():
     p.add_argument("--table", default=None, help="write the per-matrix timing table (JSON)")
     p.add_argument("--no-table", action="store_true",
                    help="spmv_set: skip the untimed exhaustive and cold tables (profiler runs)")
+    p.add_argument("--allocator", default="torch", choices=["torch", "library"],
+                   help="spmv_set: where the timed steps' handles take device memory from")
     p.add_argument("--no-solvers", action="store_true",
                    help="spmv_set: skip the untimed solver and serving summary (profiler runs)")
     p.add_argument("--serve-requests", type=int, default=300,

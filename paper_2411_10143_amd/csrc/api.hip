@@ -30,8 +30,9 @@ ck_status fail(ck_status st, const char *fmt, ...) {
 
 // features.hip
 ck_status launch_validate(int64_t n, int64_t ncols, int64_t nnz, const int *rp, const int *col,
-                          unsigned *bad, hipStream_t s);
-int64_t features_scratch_bytes(int64_t n, int64_t ncols);
+                          unsigned *state, hipStream_t s);
+int64_t validate_state_elems(int64_t nnz);
+int64_t features_scratch_bytes(int64_t n, int64_t ncols, int64_t nnz);
 ck_status launch_features(const ck_matrix &M, void *scratch, bool symmetry, hipStream_t s);
 void features_from_acc(const void *acc_host, const ck_matrix &M, int64_t *out28);
 int64_t features_acc_offset(int64_t n, int64_t ncols);
@@ -78,7 +79,7 @@ static void release(ck_matrix *M) {
 // leaves it out.
 ck_status compute_features(ck_matrix &M, ck_features &F, hipStream_t s, bool symmetry) {
     std::memset(&F, 0, sizeof F);
-    const int64_t bytes = features_scratch_bytes(M.n, M.ncols);
+    const int64_t bytes = features_scratch_bytes(M.n, M.ncols, M.nnz);
     char *scratch = nullptr;
     CK_TRY(mat_alloc(M, &scratch, bytes, s));
     ck_status st = launch_features(M, scratch, symmetry, s);
@@ -347,8 +348,8 @@ ck_status spmv_create(ck_handle *out, int64_t nrows, int64_t ncols, int64_t nnz,
             if (nnz > 0 && (st = launch_copy<float, double>(nnz, M->val32, M->val, nullptr, s)) != CK_OK)
                 break;
         }
-        if ((st = mat_alloc(*M, &bad, 1, s)) != CK_OK) break;
-        if ((st = launch_fill<int>(1, (int *)bad, 0, s)) != CK_OK) break;
+        if ((st = mat_alloc(*M, &bad, validate_state_elems(nnz), s)) != CK_OK) break;
+        if ((st = launch_fill<int>(2, (int *)bad, 0, s)) != CK_OK) break;
         if ((st = launch_validate(nrows, ncols, nnz, M->rp, M->col, bad, s)) != CK_OK) break;
         e = hipMemcpyAsync(&hbad, bad, sizeof hbad, hipMemcpyDeviceToHost, s);
         if (e == hipSuccess)

@@ -6,8 +6,11 @@
 // the floating-point features from them.  Passes:
 //   feat_rows : one lane per row  -> sum r, sum r^2, max r, min r, span,
 //               row-length histogram                           (reads rowptr, 2 cols/row)
-//   feat_nnz  : 8 lanes per row   -> longest run of consecutive columns,
+//   feat_nnz  : rows of at most kLongRow entries, 8 lanes per row striding
+//               the row (coalesced) -> longest run of consecutive columns,
 //               diagonal flags, main-diagonal count, symmetry  (reads col [+ val])
+//   feat_long : the same for longer rows (listed by feat_rows), one
+//               workgroup per row
 //   feat_ndiag: count set diagonal flags
 #include <algorithm>
 
@@ -18,6 +21,7 @@ namespace {
 struct FeatAcc {
     unsigned long long sum_r, sum_r2, max_r, min_r, span, cluster, diag_nnz, ndiag, asym;
     unsigned long long hist[16];
+    unsigned long long nlong;   // rows longer than kLongRow, listed by feat_rows
 };
 
 __device__ __forceinline__ int hist_bin(long long r) {
@@ -48,33 +52,53 @@ __device__ __forceinline__ T wave_min_u64(T v) {
 
 }  // namespace
 
-__global__ __launch_bounds__(256) void fill_u8(int64_t n, unsigned char *__restrict__ f) {
-    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < n;
+// Clears n16 16-byte words.
+__global__ __launch_bounds__(256) void fill_u128(int64_t n16, uint4 *__restrict__ f) {
+    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < n16;
          d += (int64_t)gridDim.x * 256)
-        f[d] = 0;
+        f[d] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 __global__ void feat_init(FeatAcc *acc) {
     if (threadIdx.x == 0) {
         acc->sum_r = acc->sum_r2 = acc->max_r = acc->span = acc->cluster = 0;
-        acc->diag_nnz = acc->ndiag = acc->asym = 0;
+        acc->diag_nnz = acc->ndiag = acc->asym = acc->nlong = 0;
         acc->min_r = ~0ull;
         for (int b = 0; b < 16; ++b)
             acc->hist[b] = 0;
     }
 }
 
-// Grid-stride over rows; each block folds its rows in registers and LDS and
-// adds one value per field to the global accumulators, so no address sees
-// more atomics than there are blocks.
-__global__ __launch_bounds__(256) void feat_rows(int64_t n, const int *__restrict__ rp,
-                                                 const int *__restrict__ col, FeatAcc *acc) {
+// Every pass folds its block's share in registers and LDS and writes one
+// slot of partial counts per block; feat_finish sums the slots (thousands of
+// blocks adding to the same global counters serialised at the memory side).
+constexpr int kRowFields = 21;   // sum r, sum r^2, span, max r, min r, histogram[16]
+// Rows longer than this go to the whole-workgroup passes (feat_long,
+// csr_validate_long), which take them from a list; at most nnz / 513 of them.
+constexpr int kLongRow = 512;
+__host__ __device__ constexpr int64_t long_list_cap(int64_t nnz) { return nnz / (kLongRow + 1) + 1; }
+constexpr int kNnzFields = 2;    // longest-run sum, main-diagonal count
+
+// Grid-stride over rows.
+// The row-length histogram is counted in registers (16 counters per lane,
+// summed once at the end): LDS atomics on the one bin that most rows share
+// serialised every wave.
+__global__ __launch_bounds__(256) void feat_rows(int64_t n, int64_t nnz,
+                                                 const int *__restrict__ rp,
+                                                 const int *__restrict__ col,
+                                                 unsigned long long *__restrict__ part_rows,
+                                                 FeatAcc *acc, int *__restrict__ long_list) {
+    unsigned long long *slot = part_rows + (int64_t)blockIdx.x * kRowFields;
     __shared__ unsigned long long h[16];
     __shared__ unsigned long long part[5][4];
     if (threadIdx.x < 16)
         h[threadIdx.x] = 0;
     __syncthreads();
     unsigned long long r = 0, r2 = 0, mx = 0, mn = ~0ull, span = 0;
+    unsigned hc[16];
+#pragma unroll
+    for (int b = 0; b < 16; ++b)
+        hc[b] = 0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * 256) {
         const int k0 = rp[i], k1 = rp[i + 1];
@@ -85,7 +109,21 @@ __global__ __launch_bounds__(256) void feat_rows(int64_t n, const int *__restric
         mn = ri < mn ? ri : mn;
         if (k1 > k0)
             span += (unsigned long long)(col[k1 - 1] - col[k0]);
-        atomicAdd(&h[hist_bin((long long)ri)], 1ull);
+        if (ri > (unsigned long long)kLongRow) {   // a validated CSR has at most the cap
+            const unsigned long long at = atomicAdd(&acc->nlong, 1ull);
+            if ((int64_t)at < long_list_cap(nnz))
+                long_list[at] = (int)i;
+        }
+        const int bin = hist_bin((long long)ri);
+#pragma unroll
+        for (int b = 0; b < 16; ++b)
+            hc[b] += bin == b ? 1u : 0u;
+    }
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+        const unsigned long long t = ck::wave_sum((unsigned long long)hc[b]);
+        if ((threadIdx.x & 63) == 0 && t)
+            atomicAdd(&h[b], t);
     }
     r = ck::wave_sum(r);
     r2 = ck::wave_sum(r2);
@@ -110,138 +148,108 @@ __global__ __launch_bounds__(256) void feat_rows(int64_t n, const int *__restric
             t[3] = part[3][v] > t[3] ? part[3][v] : t[3];
             t[4] = part[4][v] < t[4] ? part[4][v] : t[4];
         }
-        atomicAdd(&acc->sum_r, t[0]);
-        atomicAdd(&acc->sum_r2, t[1]);
-        atomicAdd(&acc->span, t[2]);
-        atomicMax(&acc->max_r, t[3]);
-        atomicMin(&acc->min_r, t[4]);
+        for (int f = 0; f < 5; ++f)
+            slot[f] = t[f];
     }
-    if (threadIdx.x < 16 && h[threadIdx.x])
-        atomicAdd(&acc->hist[threadIdx.x], h[threadIdx.x]);
+    if (threadIdx.x < 16)
+        slot[5 + threadIdx.x] = h[threadIdx.x];
 }
 
-// Longest run of consecutive column indices in a row, as a fold over
-// contiguous chunks.  Chunk summary: len, pre (run at the chunk start),
-// suf (run at the chunk end), best, first and last column.
-struct Run {
-    int len, pre, suf, best, first, last;
+// Longest run of consecutive column indices in a row.  Entry k of a row
+// "continues" when it is not the row's first and col[k] = col[k-1] + 1; the
+// longest run of columns is 1 + the longest stretch of continuing entries.
+// The lanes that read a step of W consecutive entries hand their continue
+// bits to a wave ballot, and the stretch state (cur: continuing entries
+// ending at the previous step's last entry, best: longest so far) is folded
+// over the W-bit mask in entry order.
+struct Stretch {
+    int cur, best;
 };
 
-__device__ __forceinline__ Run run_join(const Run &A, const Run &B) {
-    if (A.len == 0)
-        return B;
-    if (B.len == 0)
-        return A;
-    const bool join = B.first == A.last + 1;
-    Run R;
-    R.len = A.len + B.len;
-    R.best = max(A.best, B.best);
-    if (join)
-        R.best = max(R.best, A.suf + B.pre);
-    R.pre = (join && A.pre == A.len) ? A.len + B.pre : A.pre;
-    R.suf = (join && B.suf == B.len) ? B.len + A.suf : B.suf;
-    R.first = A.first;
-    R.last = B.last;
-    return R;
+// longest run of set bits in x
+__device__ __forceinline__ int longest_ones(unsigned long long x) {
+    int len = 0;
+    while (x) {
+        x &= x >> 1;
+        ++len;
+    }
+    return len;
+}
+
+// fold a step of W (<= 64) continue bits, bit j = the step's entry j
+template <int W>
+__device__ __forceinline__ void fold_step(Stretch &st, unsigned long long m) {
+    constexpr unsigned long long full = W == 64 ? ~0ull : ((1ull << W) - 1);
+    m &= full;
+    if (m == full) {
+        st.cur += W;
+        st.best = max(st.best, st.cur);
+        return;
+    }
+    const unsigned long long z = ~m & full;            // positions that break a stretch
+    const int pre = __ffsll((long long)z) - 1;        // set bits below the first break
+    const int top = 63 - __clzll(z);                   // last break
+    st.best = max(st.best, st.cur + pre);
+    st.best = max(st.best, longest_ones(m));
+    st.cur = W - 1 - top;                              // set bits above the last break
 }
 
 // Diagonal flags: a thread remembers the last kDiagMemo diagonals it set, so
-// a banded matrix (whose k-th entry of every row lies on the same diagonal)
-// touches its few flag bytes once per thread instead of once per entry; every
-// other entry reads its flag before setting it.  Without this, all entries of
-// a stencil matrix hammer the same few cache lines.
+// a banded matrix (whose entries at one position of every row lie on the
+// same diagonal) writes its few flag bytes once per thread instead of once
+// per entry.  Other entries store their flag without reading it first (the
+// value only ever goes from 0 to 1, so racing stores agree).
 constexpr int kDiagMemo = 4;
 
-template <bool SYM>
-__global__ __launch_bounds__(256) void feat_nnz(int64_t n, const int *__restrict__ rp,
-                                                const int *__restrict__ col,
-                                                const double *__restrict__ val,
-                                                unsigned char *__restrict__ diag_flag,
-                                                FeatAcc *acc) {
-    constexpr int L = 8;
-    __shared__ unsigned long long part[3][4];
-    const int lane = threadIdx.x & (L - 1);
-    const int base = (threadIdx.x & 63) & ~(L - 1);
-    unsigned long long dcount = 0, asym = 0, cl = 0;
-    int64_t memo[kDiagMemo];
+struct DiagMemo {
+    int64_t d[kDiagMemo];
+    int slot;
+    __device__ void init() {
 #pragma unroll
-    for (int m = 0; m < kDiagMemo; ++m)
-        memo[m] = -1;
-    int slot = 0;
-    // once any block has found an unmatched entry the answer is fixed, so
-    // later blocks skip the transposed-entry searches
-    const bool search = SYM && __builtin_nontemporal_load(&acc->asym) == 0;
-    const int64_t groups = (n + 256 / L - 1) / (256 / L);
-    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {
-        const int64_t i = g * (256 / L) + threadIdx.x / L;
-        Run mine{0, 0, 0, 0, 0, 0};
-        if (i < n) {
-            const int k0 = rp[i], k1 = rp[i + 1];
-            const int r = k1 - k0;
-            const int chunk = (r + L - 1) / L;
-            const int a = k0 + lane * chunk;
-            const int e = min(k1, a + chunk);
-            for (int k = a; k < e; ++k) {
-                const int c = col[k];
-                if (k == a) {
-                    mine = Run{1, 1, 1, 1, c, c};
-                } else {
-                    const bool cont = c == mine.last + 1;
-                    mine.suf = cont ? mine.suf + 1 : 1;
-                    if (cont && mine.pre == mine.len)
-                        mine.pre += 1;
-                    mine.len += 1;
-                    mine.best = max(mine.best, mine.suf);
-                    mine.last = c;
-                }
-                const int64_t d = (int64_t)c - i + (n - 1);
-                bool seen = false;
-#pragma unroll
-                for (int m = 0; m < kDiagMemo; ++m)
-                    seen |= memo[m] == d;
-                if (!seen) {
-                    if (diag_flag[d] == 0)
-                        diag_flag[d] = 1;
-#pragma unroll
-                    for (int m = 0; m < kDiagMemo; ++m)
-                        if (m == slot)
-                            memo[m] = d;
-                    slot = slot + 1 == kDiagMemo ? 0 : slot + 1;
-                }
-                if (c == i)
-                    dcount += 1;
-                if (search && asym == 0) {
-                    // transposed entry (c, i) must be stored with the same value
-                    int lo = rp[c], hi = rp[c + 1];
-                    while (lo < hi) {
-                        const int mid = (lo + hi) >> 1;
-                        if (col[mid] < (int)i)
-                            lo = mid + 1;
-                        else
-                            hi = mid;
-                    }
-                    if (lo >= rp[c + 1] || col[lo] != (int)i || val[lo] != val[k])
-                        asym = 1;
-                }
-            }
-        }
-        // fold the L chunk summaries of a row in lane order (lane 0 of the group)
-        Run tot = mine;
-#pragma unroll
-        for (int t = 1; t < L; ++t) {
-            Run o;
-            o.len = __shfl(mine.len, base + t, 64);
-            o.pre = __shfl(mine.pre, base + t, 64);
-            o.suf = __shfl(mine.suf, base + t, 64);
-            o.best = __shfl(mine.best, base + t, 64);
-            o.first = __shfl(mine.first, base + t, 64);
-            o.last = __shfl(mine.last, base + t, 64);
-            tot = run_join(tot, o);
-        }
-        if (lane == 0 && i < n)
-            cl += (unsigned long long)tot.best;
+        for (int m = 0; m < kDiagMemo; ++m)
+            d[m] = -1;
+        slot = 0;
     }
-    // one atomic per block and counter
+    __device__ __forceinline__ void mark(int64_t dg, unsigned char *__restrict__ flag) {
+        bool seen = false;
+#pragma unroll
+        for (int m = 0; m < kDiagMemo; ++m)
+            seen |= d[m] == dg;
+        if (!seen) {
+            flag[dg] = 1;
+#pragma unroll
+            for (int m = 0; m < kDiagMemo; ++m)
+                if (m == slot)
+                    d[m] = dg;
+            slot = slot + 1 == kDiagMemo ? 0 : slot + 1;
+        }
+    }
+};
+
+// The stored transposed entry (c, i) with the same value, else asymmetric.
+template <bool SYM>
+__device__ __forceinline__ bool unmatched(int64_t i, int c, double v, const int *__restrict__ rp,
+                                          const int *__restrict__ col,
+                                          const double *__restrict__ val) {
+    int lo = rp[c], hi = rp[c + 1];
+    const int end = hi;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (col[mid] < (int)i)
+            lo = mid + 1;
+        else
+            hi = mid;
+    }
+    return lo >= end || col[lo] != (int)i || val[lo] != v;
+}
+
+// The block's slot of partial counts; an unmatched transposed entry is
+// flagged at once in the global accumulator (later blocks then skip the
+// searches), which happens at most once per block.
+__device__ __forceinline__ void add_block_counts(unsigned long long cl, unsigned long long dcount,
+                                                 unsigned long long asym, FeatAcc *acc,
+                                                 unsigned long long *__restrict__ slot) {
+    __shared__ unsigned long long part[3][4];
     cl = ck::wave_sum(cl);
     dcount = ck::wave_sum(dcount);
     asym = ck::wave_sum(asym);
@@ -253,35 +261,236 @@ __global__ __launch_bounds__(256) void feat_nnz(int64_t n, const int *__restrict
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const unsigned long long t0 = part[0][0] + part[0][1] + part[0][2] + part[0][3];
-        const unsigned long long t1 = part[1][0] + part[1][1] + part[1][2] + part[1][3];
-        const unsigned long long t2 = part[2][0] + part[2][1] + part[2][2] + part[2][3];
-        if (t0)
-            atomicAdd(&acc->cluster, t0);
-        if (t1)
-            atomicAdd(&acc->diag_nnz, t1);
-        if (t2)
-            atomicAdd(&acc->asym, t2);
+        slot[0] = part[0][0] + part[0][1] + part[0][2] + part[0][3];
+        slot[1] = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+        if (part[2][0] + part[2][1] + part[2][2] + part[2][3])
+            atomicAdd(&acc->asym, 1ull);
     }
 }
 
-__global__ __launch_bounds__(256) void feat_ndiag(int64_t nd, const unsigned char *__restrict__ f,
-                                                  FeatAcc *acc) {
+// Rows of at most kLongRow entries: L = 8 lanes per row, lane l reading
+// entries l, l + 8, ... of the row (eight consecutive columns per step,
+// coalesced); the wave steps together up to its longest row.
+template <bool SYM>
+__global__ __launch_bounds__(256) void feat_nnz(int64_t n, const int *__restrict__ rp,
+                                                const int *__restrict__ col,
+                                                const double *__restrict__ val,
+                                                unsigned char *__restrict__ diag_flag,
+                                                FeatAcc *acc,
+                                                unsigned long long *__restrict__ part_nnz) {
+    constexpr int L = 8;
+    const int lane = threadIdx.x & (L - 1);
+    const int gbase = (threadIdx.x & 63) & ~(L - 1);   // the group's first lane in the wave
+    unsigned long long dcount = 0, asym = 0, cl = 0;
+    DiagMemo memo;
+    memo.init();
+    // once any block has found an unmatched entry the answer is fixed, so
+    // later blocks skip the transposed-entry searches
+    const bool search = SYM && __builtin_nontemporal_load(&acc->asym) == 0;
+    const int64_t groups = (n + 256 / L - 1) / (256 / L);
+    for (int64_t g = blockIdx.x; g < groups; g += gridDim.x) {   // uniform per block
+        const int64_t i = g * (256 / L) + threadIdx.x / L;
+        int k0 = 0, r = 0;
+        if (i < n) {
+            k0 = rp[i];
+            r = rp[i + 1] - k0;
+            if (r > kLongRow)
+                r = 0;                      // feat_long's row
+        }
+        int rmax = r;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            rmax = max(rmax, __shfl_xor(rmax, off, 64));
+        Stretch st{0, 0};
+        int prev_last = 0;
+        for (int t = 0; t < rmax; t += L) {
+            const bool in = t + lane < r;
+            const int k = k0 + t + lane;
+            const int c = in ? col[k] : 0;
+            int cprev = __shfl_up(c, 1, L);
+            if (lane == 0)
+                cprev = prev_last;
+            const bool cont = in && t + lane > 0 && c == cprev + 1;
+            const unsigned long long bal = __ballot(cont);
+            fold_step<L>(st, bal >> gbase);
+            prev_last = __shfl(c, gbase + L - 1, 64);
+            if (in) {
+                memo.mark((int64_t)c - i + (n - 1), diag_flag);
+                if (c == i)
+                    dcount += 1;
+                if (search && asym == 0 && unmatched<SYM>(i, c, val[k], rp, col, val))
+                    asym = 1;
+            }
+        }
+        if (lane == 0 && r > 0)
+            cl += (unsigned long long)(st.best + 1);
+    }
+    add_block_counts(cl, dcount, asym, acc, part_nnz + (int64_t)blockIdx.x * kNnzFields);
+}
+
+// Rows longer than kLongRow (listed by feat_rows): a block runs each with
+// all 256 lanes, lane t reading entry t of each 256-entry step; the four
+// waves' continue masks are folded in wave order.
+
+template <bool SYM>
+__global__ __launch_bounds__(256) void feat_long(int64_t n, const int *__restrict__ rp,
+                                                 const int *__restrict__ col,
+                                                 const double *__restrict__ val,
+                                                 unsigned char *__restrict__ diag_flag,
+                                                 FeatAcc *acc, const int *__restrict__ long_list,
+                                                 unsigned long long *__restrict__ part_long) {
+    __shared__ int s_col[256];
+    __shared__ unsigned long long s_mask[4];
+    const int tid = threadIdx.x;
+    unsigned long long dcount = 0, asym = 0, cl = 0;
+    DiagMemo memo;
+    memo.init();
+    const bool search = SYM && __builtin_nontemporal_load(&acc->asym) == 0;
+    const int64_t cnt =
+        min((int64_t)__builtin_nontemporal_load(&acc->nlong), long_list_cap(rp[n]));
+    for (int64_t q = blockIdx.x; q < cnt; q += gridDim.x) {
+        const int64_t i = long_list[q];
+        const int k0 = rp[i], r = rp[i + 1] - k0;
+        Stretch st{0, 0};
+        int prev_last = 0;
+        for (int t = 0; t < r; t += 256) {
+            const bool in = t + tid < r;
+            const int k = k0 + t + tid;
+            const int c = in ? col[k] : 0;
+            s_col[tid] = c;
+            __syncthreads();
+            const int cprev = tid > 0 ? s_col[tid - 1] : prev_last;
+            const bool cont = in && t + tid > 0 && c == cprev + 1;
+            const unsigned long long bal = __ballot(cont);
+            if ((tid & 63) == 0)
+                s_mask[tid >> 6] = bal;
+            if (in) {
+                memo.mark((int64_t)c - i + (n - 1), diag_flag);
+                if (c == i)
+                    dcount += 1;
+                if (search && asym == 0 && unmatched<SYM>(i, c, val[k], rp, col, val))
+                    asym = 1;
+            }
+            __syncthreads();
+            if (tid == 0)
+                for (int w = 0; w < 4; ++w)
+                    fold_step<64>(st, s_mask[w]);
+            prev_last = s_col[255];
+            __syncthreads();   // s_col and s_mask are rewritten by the next step
+        }
+        if (tid == 0)
+            cl += (unsigned long long)(st.best + 1);
+    }
+    add_block_counts(cl, dcount, asym, acc, part_long + (int64_t)blockIdx.x * kNnzFields);
+}
+
+// Counts the set flags, 16 bytes per lane (each byte is 0 or 1; bytes past
+// the n + ncols - 1 diagonals were cleared and stay 0).
+__global__ __launch_bounds__(256) void feat_ndiag(int64_t n16, const uint4 *__restrict__ f,
+                                                  unsigned long long *__restrict__ part_diag) {
     unsigned long long c = 0;
-    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < nd;
-         d += (int64_t)gridDim.x * 256)
-        c += f[d];
+    for (int64_t d = (int64_t)blockIdx.x * 256 + threadIdx.x; d < n16;
+         d += (int64_t)gridDim.x * 256) {
+        const uint4 w = f[d];
+        // bytes are 0/1: multiplying by 0x01010101 sums a word's four bytes into its top byte
+        c += ((w.x * 0x01010101u) >> 24) + ((w.y * 0x01010101u) >> 24) +
+             ((w.z * 0x01010101u) >> 24) + ((w.w * 0x01010101u) >> 24);
+    }
+    __shared__ unsigned long long part[4];
     c = ck::wave_sum(c);
-    if ((threadIdx.x & 63) == 0 && c)
-        atomicAdd(&acc->ndiag, c);
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        part_diag[blockIdx.x] = part[0] + part[1] + part[2] + part[3];
+}
+
+// Sums the partial slots of every pass (integer sums, max and min: exact
+// and order-free) into the accumulators.  One block of 1024 threads.
+__global__ __launch_bounds__(1024) void feat_finish(FeatAcc *acc, const unsigned long long *pr,
+                                                   int Gr, const unsigned long long *pn, int Gn,
+                                                   const unsigned long long *pl, int Gl,
+                                                   const unsigned long long *pd, int Gd) {
+    constexpr int F = kRowFields + kNnzFields + 1;   // + diagonals
+    unsigned long long v[F];
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+        v[f] = f == 4 ? ~0ull : 0ull;
+    for (int b = threadIdx.x; b < Gr; b += 1024) {
+        const unsigned long long *q = pr + (int64_t)b * kRowFields;
+        v[0] += q[0];
+        v[1] += q[1];
+        v[2] += q[2];
+        v[3] = q[3] > v[3] ? q[3] : v[3];
+        v[4] = q[4] < v[4] ? q[4] : v[4];
+        for (int h = 0; h < 16; ++h)
+            v[5 + h] += q[5 + h];
+    }
+    for (int b = threadIdx.x; b < Gn; b += 1024) {
+        v[21] += pn[2 * b];
+        v[22] += pn[2 * b + 1];
+    }
+    for (int b = threadIdx.x; b < Gl; b += 1024) {
+        v[21] += pl[2 * b];
+        v[22] += pl[2 * b + 1];
+    }
+    for (int b = threadIdx.x; b < Gd; b += 1024)
+        v[23] += pd[b];
+    __shared__ unsigned long long part[F][16];
+    const int w = threadIdx.x >> 6;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+        unsigned long long t;
+        if (f == 3)
+            t = wave_max_u64(v[f]);
+        else if (f == 4)
+            t = wave_min_u64(v[f]);
+        else
+            t = ck::wave_sum(v[f]);
+        if ((threadIdx.x & 63) == 0)
+            part[f][w] = t;
+    }
+    __syncthreads();
+    if (threadIdx.x < F) {
+        const int f = threadIdx.x;
+        unsigned long long t = part[f][0];
+        for (int u = 1; u < 16; ++u) {
+            const unsigned long long o = part[f][u];
+            t = f == 3 ? (o > t ? o : t) : f == 4 ? (o < t ? o : t) : t + o;
+        }
+        if (f == 0)
+            acc->sum_r = t;
+        else if (f == 1)
+            acc->sum_r2 = t;
+        else if (f == 2)
+            acc->span = t;
+        else if (f == 3)
+            acc->max_r = t;
+        else if (f == 4)
+            acc->min_r = t;
+        else if (f < 21)
+            acc->hist[f - 5] = t;
+        else if (f == 21)
+            acc->cluster = t;
+        else if (f == 22)
+            acc->diag_nnz = t;
+        else
+            acc->ndiag = t;
+    }
 }
 
 // ---- validation ---------------------------------------------------------------
+// Row pointers (each row's bounds checked before any of its columns is
+// read), then the columns of rows of at most kLongRow entries with 8 lanes
+// per row; longer rows with valid bounds go to a list (valid bounds make
+// the rows disjoint, so at most long_list_cap(nnz) of them) for
+// csr_validate_long.  state[0] = error bits, state[1] = listed rows.
 __global__ __launch_bounds__(256) void csr_validate(int64_t n, int64_t ncols, int64_t nnz,
                                                     const int *__restrict__ rp,
                                                     const int *__restrict__ col,
-                                                    unsigned *bad) {
+                                                    unsigned *state, int *__restrict__ long_list) {
     constexpr int L = 8;
+    unsigned *bad = state;
     const int lane = threadIdx.x & (L - 1);
     const int64_t i = (int64_t)blockIdx.x * (256 / L) + threadIdx.x / L;
     if (i > n)
@@ -299,11 +508,44 @@ __global__ __launch_bounds__(256) void csr_validate(int64_t n, int64_t ncols, in
             atomicOr(bad, 4u);
         return;
     }
+    if (k1 - k0 > kLongRow) {
+        if (lane == 0) {
+            // rows with valid bounds may still overlap when other rows are
+            // malformed: never write past the list (those rows are flagged)
+            const unsigned at = atomicAdd(&state[1], 1u);
+            if ((int64_t)at < long_list_cap(nnz))
+                long_list[at] = (int)i;
+            else
+                atomicOr(bad, 16u);
+        }
+        return;
+    }
     for (int64_t k = k0 + lane; k < k1; k += L) {
         const int c = col[k];
         if (c < 0 || c >= ncols || (k > k0 && c <= col[k - 1])) {
             atomicOr(bad, 8u);
             return;
+        }
+    }
+}
+
+// Columns of the listed long rows, each with all 256 lanes of a block.
+__global__ __launch_bounds__(256) void csr_validate_long(int64_t ncols, int64_t nnz,
+                                                         const int *__restrict__ rp,
+                                                         const int *__restrict__ col,
+                                                         unsigned *state,
+                                                         const int *__restrict__ long_list) {
+    const int64_t cnt =
+        min((int64_t)__builtin_nontemporal_load(&state[1]), long_list_cap(nnz));
+    for (int64_t q = blockIdx.x; q < cnt; q += gridDim.x) {
+        const int64_t i = long_list[q];
+        const int64_t k0 = rp[i], k1 = rp[i + 1];
+        for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) {
+            const int c = col[k];
+            if (c < 0 || c >= ncols || (k > k0 && c <= col[k - 1])) {
+                atomicOr(&state[0], 8u);
+                break;
+            }
         }
     }
 }
@@ -364,41 +606,71 @@ __global__ __launch_bounds__(256) void row_max(int64_t n, const int *__restrict_
 // ---------------------------------------------------------------------------
 namespace ck {
 
+// Ints of the validation state: error bits, list length, the long-row list.
+int64_t validate_state_elems(int64_t nnz) { return 2 + long_list_cap(nnz); }
+
+// `state` (validate_state_elems ints, the first two cleared) gets the error bits in state[0].
 ck_status launch_validate(int64_t n, int64_t ncols, int64_t nnz, const int *rp, const int *col,
-                          unsigned *bad, hipStream_t s) {
+                          unsigned *state, hipStream_t s) {
     const int64_t G = ceil_div(n + 1, 256 / 8);
-    hipLaunchKernelGGL(csr_validate, dim3(G), dim3(256), 0, s, n, ncols, nnz, rp, col, bad);
+    int *list = (int *)(state + 2);
+    hipLaunchKernelGGL(csr_validate, dim3(G), dim3(256), 0, s, n, ncols, nnz, rp, col, state, list);
+    hipLaunchKernelGGL(csr_validate_long, dim3(1024), dim3(256), 0, s, ncols, nnz, rp, col, state,
+                       list);
     CK_HIP(hipGetLastError());
     return CK_OK;
 }
 
-// Fills out[0..27] with the integer accumulators in the feature layout;
-// `scratch` must hold n + ncols - 1 bytes plus sizeof(FeatAcc) (+256).
-int64_t features_scratch_bytes(int64_t n, int64_t ncols) {
-    return ((n + ncols + 255) / 256) * 256 + 512;
+int64_t features_acc_offset(int64_t n, int64_t ncols);
+
+// Scratch of the feature pass: the diagonal flags (n + ncols - 1 bytes,
+// rounded up to 256), the accumulators (512 bytes), then the partial slots
+// of the passes (grids of at most kGridRows, kGridNnz, kGridLong and
+// kGridDiag blocks).
+constexpr int64_t kGridRows = 1024, kGridNnz = 2048, kGridLong = 1024, kGridDiag = 1024;
+constexpr int64_t kPartialWords =
+    kGridRows * kRowFields + (kGridNnz + kGridLong) * kNnzFields + kGridDiag;
+
+int64_t features_scratch_bytes(int64_t n, int64_t ncols, int64_t nnz) {
+    return ((n + ncols + 255) / 256) * 256 + 512 + 8 * kPartialWords + 4 * long_list_cap(nnz);
 }
 
 ck_status launch_features(const ck_matrix &M, void *scratch, bool symmetry, hipStream_t s) {
-    const int64_t nd = M.n + M.ncols - 1;
+    // the flag bytes occupy the first features_acc_offset() bytes (a multiple
+    // of 256 covering the n + ncols - 1 diagonals), all cleared and all counted
+    const int64_t n16 = features_acc_offset(M.n, M.ncols) / 16;
     unsigned char *flags = (unsigned char *)scratch;
-    FeatAcc *acc = (FeatAcc *)((char *)scratch + ((M.n + M.ncols + 255) / 256) * 256);
+    FeatAcc *acc = (FeatAcc *)((char *)scratch + features_acc_offset(M.n, M.ncols));
+    unsigned long long *pr = (unsigned long long *)((char *)acc + 512);
+    unsigned long long *pn = pr + kGridRows * kRowFields;
+    unsigned long long *pl = pn + kGridNnz * kNnzFields;
+    unsigned long long *pd = pl + kGridLong * kNnzFields;
+    int *long_list = (int *)(pd + kGridDiag);
     hipLaunchKernelGGL(feat_init, dim3(1), dim3(64), 0, s, acc);
-    if (nd > 0) {
-        const int64_t g = std::min<int64_t>(ceil_div(nd, 256), 8192);
-        hipLaunchKernelGGL((fill_u8), dim3(g), dim3(256), 0, s, nd, flags);
-    }
+    if (n16 > 0)
+        hipLaunchKernelGGL(fill_u128, dim3(std::min<int64_t>(ceil_div(n16, 256), 4096)), dim3(256),
+                           0, s, n16, (uint4 *)flags);
     if (M.n > 0) {
-        hipLaunchKernelGGL(feat_rows, dim3(std::min<int64_t>(ceil_div(M.n, 256), 2048)), dim3(256),
-                           0, s, M.n, M.rp, M.col, acc);
-        const int64_t G = std::min<int64_t>(ceil_div(M.n, 256 / 8), 8192);
-        if (symmetry && M.n == M.ncols)
+        const int64_t Gr = std::min<int64_t>(ceil_div(M.n, 256), kGridRows);
+        const int64_t G = std::min<int64_t>(ceil_div(M.n, 256 / 8), kGridNnz);
+        const int64_t GL = kGridLong;
+        const int64_t Gd = std::min<int64_t>(ceil_div(n16, 256), kGridDiag);
+        hipLaunchKernelGGL(feat_rows, dim3(Gr), dim3(256), 0, s, M.n, M.nnz, M.rp, M.col, pr, acc,
+                           long_list);
+        if (symmetry && M.n == M.ncols) {
             hipLaunchKernelGGL((feat_nnz<true>), dim3(G), dim3(256), 0, s, M.n, M.rp, M.col,
-                               M.val, flags, acc);
-        else
+                               M.val, flags, acc, pn);
+            hipLaunchKernelGGL((feat_long<true>), dim3(GL), dim3(256), 0, s, M.n, M.rp, M.col,
+                               M.val, flags, acc, long_list, pl);
+        } else {
             hipLaunchKernelGGL((feat_nnz<false>), dim3(G), dim3(256), 0, s, M.n, M.rp, M.col,
-                               M.val, flags, acc);
-        const int64_t g = std::min<int64_t>(ceil_div(nd, 256), 4096);
-        hipLaunchKernelGGL(feat_ndiag, dim3(g), dim3(256), 0, s, nd, flags, acc);
+                               M.val, flags, acc, pn);
+            hipLaunchKernelGGL((feat_long<false>), dim3(GL), dim3(256), 0, s, M.n, M.rp, M.col,
+                               M.val, flags, acc, long_list, pl);
+        }
+        hipLaunchKernelGGL(feat_ndiag, dim3(Gd), dim3(256), 0, s, n16, (const uint4 *)flags, pd);
+        hipLaunchKernelGGL(feat_finish, dim3(1), dim3(1024), 0, s, acc, pr, (int)Gr, pn, (int)G, pl,
+                           (int)GL, pd, (int)Gd);
     }
     CK_HIP(hipGetLastError());
     return CK_OK;

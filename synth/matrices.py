@@ -380,6 +380,29 @@ def random_integer(n: int, ncols: int, seed: int, density: float = 0.1,
     return _finish(n, ncols, rows, cols, vals, f"randint_{n}x{ncols}", presorted=True)
 
 
+def column_runs(n: int, ncols: int, seed: int) -> CSR:
+    """Rows made of runs of consecutive columns (run lengths 1..600, gaps
+    1..5), row lengths drawn from {0, 1, 7, 8, 9, 63, 64, 65, 255, 256, 257,
+    511, 512, 513, 700, 2000} so that runs and rows end at and across every
+    power-of-two boundary; small integer values."""
+    rng = np.random.default_rng(seed)
+    lengths = np.array([0, 1, 7, 8, 9, 63, 64, 65, 255, 256, 257, 511, 512, 513, 700, 2000])
+    rows, cols = [], []
+    for i in range(n):
+        r = int(min(rng.choice(lengths), ncols))
+        c = int(rng.integers(0, max(1, ncols - 3 * r)))
+        out = []
+        while len(out) < r and c < ncols:
+            run = int(rng.integers(1, 601))
+            take = min(run, r - len(out), ncols - c)
+            out.extend(range(c, c + take))
+            c += take + int(rng.integers(1, 6))
+        rows.extend([i] * len(out))
+        cols.extend(out)
+    vals = rng.integers(-9, 10, len(cols)).astype(np.float64)
+    return _finish(n, ncols, rows, cols, vals, f"runs_{n}x{ncols}", presorted=True)
+
+
 def diagonally_dominant(A: CSR, name: str | None = None) -> CSR:
     """Set a_ii = 1 + sum_{j != i} |a_ij| (inserting the diagonal if absent).
 

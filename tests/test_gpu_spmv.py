@@ -35,6 +35,7 @@ CASES = {
     "one_by_one": lambda: M.from_dense(np.array([[3.0]])),
     "single_row": lambda: M.from_dense(np.arange(1.0, 200.0)[None, :]),
     "single_col": lambda: M.from_dense(np.arange(1.0, 300.0)[:, None]),
+    "column_runs": lambda: M.column_runs(1500, 6000, 8),
 }
 
 _cache = {}
@@ -173,7 +174,7 @@ def test_dia_and_hyb_layouts_bit_exact(ck, orc, name):
 
 @pytest.mark.parametrize("name", ["int_ragged", "int_wide", "powerlaw", "banded27", "blockdiag",
                                   "uniform", "lap2d_64", "convdiff", "empty", "one_by_one",
-                                  "single_row", "single_col"])
+                                  "single_row", "single_col", "column_runs"])
 def test_features_bit_exact(ck, orc, name):
     A = case(name)
     say(f"features {name}")
@@ -201,12 +202,30 @@ def test_features_without_symmetry(ck, orc, name):
     Mx.close()
 
 
+def _hub_asymmetric(A):
+    """The graph Laplacian with one off-diagonal value of its longest row
+    changed: the pattern stays symmetric, the values do not."""
+    from synth.matrices import CSR
+    r = np.diff(A.rp)
+    i = int(np.argmax(r))
+    val = A.val.copy()
+    ks = [k for k in range(A.rp[i], A.rp[i + 1]) if A.col[k] != i]
+    val[ks[len(ks) // 2]] += 0.5
+    return CSR(A.n, A.ncols, A.rp, A.col, val, A.name + "_asym")
+
+
 def test_symmetric_flag(ck, orc):
+    hub = M.graph_laplacian_chung_lu(20000, 12, wmax=4000)     # rows well over 512 entries
+    assert np.diff(hub.rp).max() > 512
     for A in [M.laplacian_2d(30), M.graph_laplacian_chung_lu(5000, 11, wmax=500),
-              M.convection_diffusion_2d(30), M.diagonally_dominant(M.uniform_random(3000, 2))]:
+              M.convection_diffusion_2d(30), M.diagonally_dominant(M.uniform_random(3000, 2)),
+              hub, _hub_asymmetric(hub)]:
         say(f"symmetry {A.name}")
         Mx = ck.Matrix.from_csr(A)
-        assert ck.spmv_features(Mx.handle).is_symmetric == orc.features(A)[0][27]
+        F = ck.spmv_features(Mx.handle)
+        ints = orc.features(A)[0]
+        assert F.is_symmetric == ints[27], A.name
+        assert F.ints() == [int(v) for v in ints], A.name
         Mx.close()
 
 
@@ -334,6 +353,41 @@ def test_invalid_csr_rejected(ck):
     badrp[5] = rp[7]                      # row pointers not monotone
     with pytest.raises(ck.CkError):
         ck.spmv_create(badrp, col, val)
+    # rows longer than 512 entries are checked by their own pass: a repeated,
+    # an out-of-order and an out-of-range column deep inside a 2000-entry row
+    D = np.zeros((3, 4000))
+    D[1, ::2] = 1.0
+    D[0, 7] = D[2, 3999] = 2.0
+    L = M.from_dense(D)
+    assert np.diff(L.rp).max() == 2000
+    rp, col, val = upload(L)
+    ck.Matrix(rp, col, val, ncols=L.ncols).close()   # the valid one is accepted
+    k = int(L.rp[1]) + 1500
+    for what in ("repeat", "swap", "range"):
+        bad = col.clone()
+        if what == "repeat":
+            bad[k] = col[k - 1]
+        elif what == "swap":
+            bad[k], bad[k + 1] = col[k + 1], col[k]
+        else:
+            bad[k + 400] = 4000
+        say(f"invalid long row: {what}")
+        with pytest.raises(ck.CkError) as e:
+            ck.spmv_create(rp, bad, val, ncols=L.ncols)
+        assert e.value.status == ck.CK_E_INVALID, what
+    # row pointers that go up and down: every other row has valid bounds and
+    # 1000 entries, so more rows look long than 1000 entries can hold (the
+    # long-row list is sized for disjoint rows and must not overflow)
+    import torch
+    n = 64
+    rpl = torch.tensor([0 if t % 2 == 0 else 1000 for t in range(n)] + [1000],
+                       dtype=torch.int32, device="cuda")
+    coll = torch.arange(1000, dtype=torch.int32, device="cuda")
+    vall = torch.ones(1000, dtype=torch.float64, device="cuda")
+    say("invalid: overlapping long rows")
+    with pytest.raises(ck.CkError) as e:
+        ck.spmv_create(rpl, coll, vall, ncols=1000)
+    assert e.value.status == ck.CK_E_INVALID
 
 
 @pytest.mark.parametrize("cid", [8, 9, 10, 11, 12, 13])

@@ -27,6 +27,7 @@ Chung-Lu graph Laplacians, whose hub columns none of those families has),
 timed on this GPU.
 
   python -m paper_2411_10143_amd.train collect --out data.csv [--count 200]
+  python -m paper_2411_10143_amd.train retime --data data.csv --out new.csv --configs 11
   python -m paper_2411_10143_amd.train fit --data data.csv --model cascade_model.txt
 """
 from __future__ import annotations
@@ -143,6 +144,72 @@ def collect(out_csv, count=600, seed=9000, reps=None):
     f.close()
 
 
+def _gen_to_file(args):
+    """Worker: draw one training matrix and save it (npz) for the timing process."""
+    spec, path = args
+    from synth import workloads as W
+    name, fam, k, n, s = spec
+    A = W.family_matrix(fam, k, n, s)
+    np.savez(path, n=A.n, ncols=A.ncols, rp=A.rp, col=A.col, val=A.val)
+    return path
+
+
+def retime(in_csv, out_csv, configs, count=600, seed=9000, reps=None, jobs=8, tmpdir="/tmp"):
+    """Re-time the given configuration ids of every matrix already in in_csv
+    (after a kernel changed) and write the updated rows to out_csv; the
+    matrices are drawn again by `jobs` worker processes."""
+    import multiprocessing as mp
+    import tempfile
+
+    import torch
+
+    import paper_2411_10143_amd as ck
+    from synth import workloads as W
+    from synth.matrices import CSR
+
+    with open(in_csv) as f:
+        rows = list(csv.DictReader(f))
+    byname = {r["name"]: r for r in rows}
+    specs = [sp for sp in W.training_specs(count=count, seed=seed) if sp[0] in byname]
+    d = tempfile.mkdtemp(dir=tmpdir)
+    work = [(sp, os.path.join(d, f"m{i}.npz")) for i, sp in enumerate(specs)]
+    t0 = time.time()
+    with mp.get_context("spawn").Pool(jobs) as pool:
+        for i, path in enumerate(pool.imap(_gen_to_file, work)):
+            name, fam, k, n, s = specs[i]
+            z = np.load(path)
+            A = CSR(int(z["n"]), int(z["ncols"]), z["rp"], z["col"], z["val"], name)
+            os.remove(path)
+            Mx = ck.Matrix.from_csr(A)
+            x = torch.from_numpy(np.random.default_rng(s).uniform(-1, 1, A.ncols)).cuda()
+            y = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+            for cid in configs:
+                cfg = ck.config_from_id(cid)
+                try:
+                    ck.spmv_convert(Mx.handle, cfg)
+                except ck.CkError as e:
+                    if e.status != ck.CK_E_UNSUPPORTED:
+                        raise
+                    byname[name][f"t{cid}"] = repr(math.inf)
+                    continue
+                r = reps
+                if r is None:
+                    r = reps_for(ck.time_spmv(Mx.handle, cfg, x, y, warmup=10, reps=5))
+                old = float(byname[name][f"t{cid}"])
+                new = ck.time_spmv(Mx.handle, cfg, x, y, warmup=2, reps=r)
+                byname[name][f"t{cid}"] = repr(new)
+                print(f"[{i + 1}/{len(specs)}] {name} {ck.CONFIG_NAMES[cid]} {old:.2f} -> "
+                      f"{new:.2f} us elapsed={time.time() - t0:.0f}s", flush=True)
+            Mx.close()
+            del x, y
+    os.rmdir(d)
+    with open(out_csv, "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=list(rows[0].keys()))
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+
+
 def load(path):
     X, T, names = [], [], []
     with open(path) as f:
@@ -235,6 +302,14 @@ def main(argv=None):
     c.add_argument("--count", type=int, default=600)
     c.add_argument("--seed", type=int, default=9000)
     c.add_argument("--reps", type=int, default=None)
+    r = sub.add_parser("retime")
+    r.add_argument("--data", required=True)
+    r.add_argument("--out", required=True)
+    r.add_argument("--configs", type=int, nargs="+", required=True)
+    r.add_argument("--count", type=int, default=600)
+    r.add_argument("--seed", type=int, default=9000)
+    r.add_argument("--reps", type=int, default=None)
+    r.add_argument("--jobs", type=int, default=8)
     fa = sub.add_parser("fit")
     fa.add_argument("--data", required=True, nargs="+")
     fa.add_argument("--model", required=True)
@@ -247,6 +322,8 @@ def main(argv=None):
     a = p.parse_args(argv)
     if a.cmd == "collect":
         collect(a.out, a.count, a.seed, a.reps)
+    elif a.cmd == "retime":
+        retime(a.data, a.out, a.configs, a.count, a.seed, a.reps, a.jobs)
     else:
         Xs, Ts = [], []
         for d in a.data:

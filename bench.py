@@ -18,7 +18,8 @@ product per matrix.
 Other workloads (--workload): cg_lap2d (CG, 64x64 Laplacian), cg_async (async
 CG on 3D Poisson 128^3 and a 2^20-row power-law graph Laplacian),
 gmres_mixed (mixed vs FP64 GMRES(30), convection-diffusion 1024^2), serve
-(request loop).  Each prints one JSON line.
+(request loop), select_latency (host vs device-resident cascade).  Each
+prints one JSON line.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 """
@@ -689,6 +690,60 @@ def bench_serve(args):
                 None, dtype="f32+f64")
 
 
+def bench_select_latency(args):
+    """Prediction latency on the serving pool's 64 matrices (n 1e3-1e6),
+    resident handle, cold prediction: host cascade (GPU feature pass, read
+    back the accumulators, derive and walk the trees on the host) against the
+    device-resident cascade (feature pass, derivation and walk on the GPU,
+    read back the 8-int decision); both end with the decision on the host."""
+    import torch
+
+    import paper_2411_10143_amd as ck
+    from synth import workloads as W
+    pool = W.serving_pool()
+    out = torch.zeros(8, dtype=torch.int32, device="cuda")
+    rows = []
+    for A, _sym in pool:
+        Mx = ck.Matrix.from_csr(A)
+        ck.select_device(Mx.handle, out)        # uploads the model once; keeps the scratch
+        torch.cuda.synchronize()
+        th, td, te = [], [], []
+        for _ in range(args.steps + args.warmup):
+            t0 = time.perf_counter()
+            F = ck.spmv_features(Mx.handle, symmetry=False)
+            cfg = ck.spmv_select(F)
+            t1 = time.perf_counter()
+            ck.select_device(Mx.handle, out)
+            t2 = time.perf_counter()
+            dev = out.cpu().tolist()
+            t3 = time.perf_counter()
+            assert dev[7] == ck.config_id(cfg), (A.name, dev, cfg)
+            th.append(t1 - t0)
+            td.append(t3 - t1)
+            te.append(t2 - t1)
+        Mx.close()
+        k = args.warmup
+        rows.append(dict(matrix=A.name, n=A.n, nnz=A.nnz, config=ck.CONFIG_NAMES[dev[7]],
+                         host_us=round(1e6 * float(np.median(th[k:])), 1),
+                         device_us=round(1e6 * float(np.median(td[k:])), 1),
+                         device_enqueue_us=round(1e6 * float(np.median(te[k:])), 1)))
+        log(f"[select] {A.name} n={A.n} host {rows[-1]['host_us']} us device "
+            f"{rows[-1]['device_us']} us")
+    h = np.array([r["host_us"] for r in rows])
+    d = np.array([r["device_us"] for r in rows])
+    small = np.array([r["n"] <= 32768 for r in rows])
+    _solve_json(args, float(np.median(h / d)), "x (host / device prediction latency, median)",
+                float(np.sum(h) + np.sum(d)) / 1e3,
+                "select_latency: cold cascade prediction on the 64-matrix serving pool, "
+                "host cascade vs device-resident cascade, decision read back on the host",
+                {"median_host_us": float(np.median(h)), "median_device_us": float(np.median(d)),
+                 "median_host_us_n_le_32768": float(np.median(h[small])),
+                 "median_device_us_n_le_32768": float(np.median(d[small])),
+                 "matrices": rows},
+                {"bound": "hbm", "kernel": "feature pass + cascade_from_ints", "achieved": None,
+                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None}, None)
+
+
 def _timed_solves(ck, fn, Mx, b, count, warmup=1, **kw):
     """Wall time of `count` solves from the call to the result on the host
     (the matrix resident), after `warmup` untimed ones; the last x and result."""
@@ -864,7 +919,8 @@ def main():
     p.add_argument("--steps", type=int, default=5)
     p.add_argument("--warmup", type=int, default=1)
     p.add_argument("--workload", default="spmv_set",
-                   choices=["spmv_set", "cg_lap2d", "cg_async", "gmres_mixed", "serve"])
+                   choices=["spmv_set", "cg_lap2d", "cg_async", "gmres_mixed", "serve",
+                            "select_latency"])
     p.add_argument("--reps", type=int, default=200)
     p.add_argument("--max-n", type=int, default=None, help="drop set members above this n")
     p.add_argument("--only", default=None,
@@ -897,7 +953,8 @@ def main():
               file=sys.stderr)
         return 2
     {"spmv_set": bench_spmv_set, "cg_lap2d": bench_cg_lap2d, "cg_async": bench_cg_async,
-     "gmres_mixed": bench_gmres_mixed, "serve": bench_serve}[args.workload](args)
+     "gmres_mixed": bench_gmres_mixed, "serve": bench_serve,
+     "select_latency": bench_select_latency}[args.workload](args)
     return 0
 
 

@@ -232,6 +232,26 @@ ck_status ck_select_stages(const ck_features *f, const char *model_path, int32_t
 ck_status ck_eval_stage(const ck_features *f, const char *model_path, int32_t stage,
                         int32_t *cls);
 
+/* ck_select_device -- the device-resident cascade: the feature pass (no
+ * symmetry test), the derivation of the 15 model inputs and the walk of the
+ * default model's three trees (Section III-C-1, cascaded-prediction figure)
+ * all run on the GPU, stream-ordered on s, with no host round trip; the
+ * derivation is the host cascade's, so the outcome equals spmv_select on
+ * ck_features_ex(CK_FEAT_NO_SYMMETRY).  Writes 8 int32 to DEVICE memory
+ * d_out: format, algorithm, lanes, stages run (a ck_config), then the three
+ * raw stage classes as ck_select_stages reports them, then the
+ * configuration id.  Returns without blocking, except that the first call
+ * on a device uploads the model's node tables.  The feature scratch is kept
+ * with the handle (until spmv_destroy), so calls on one handle must be
+ * ordered (one stream, or synchronised). */
+ck_status ck_select_device(ck_handle h, int32_t *d_out, hipStream_t s);
+
+/* ck_cascade_eval_device -- the same tree walk for `count` rows of 15 model
+ * inputs (DEVICE array d_f15, row-major, feature-table order): d_ids[r] =
+ * the configuration id the cascade picks for row r.  Stream-ordered. */
+ck_status ck_cascade_eval_device(const double *d_f15, int64_t count, int32_t *d_ids,
+                                 hipStream_t s);
+
 /* ck_start_config -- the starting configuration from the inputs known
  * without a pass over the entries (nrows, ncols, nnz, density, mean row
  * length): the model's optional "start" tree, which names one of the CSR

@@ -208,6 +208,8 @@ SIGNATURES = {
     "spmv_apply": (_i32, [_vp, C.POINTER(Config), _dbl, _vp, _dbl, _vp, _vp]),
     "spmv_apply_f32": (_i32, [_vp, C.POINTER(Config), _flt, _vp, _flt, _vp, _vp]),
     "spmv_apply_noalloc": (_i32, [_vp, C.POINTER(Config), _dbl, _vp, _dbl, _vp, _vp]),
+    "ck_select_device": (_i32, [_vp, _vp, _vp]),
+    "ck_cascade_eval_device": (_i32, [_vp, _i64, _vp, _vp]),
     "cg_solve": (_i32, [_vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveResult), _vp]),
     "gmres_solve": (_i32, [_vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveResult), _vp]),
     "ck_export_ell": (_i32, [_vp, _vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp]),
@@ -338,6 +340,25 @@ def spmv_features(h, stream=None, symmetry=True):
     else:
         _check(lib().ck_features_ex(h, C.byref(f), CK_FEAT_NO_SYMMETRY, _stream(stream)))
     return f
+
+
+def select_device(h, out, stream=None):
+    """Device-resident cascade into `out` (int32 device tensor of 8): format,
+    algorithm, lanes, stages, the three stage classes, configuration id."""
+    import torch
+    if out.numel() < 8:
+        raise ValueError("out needs 8 int32 entries")
+    _check(lib().ck_select_device(h, _ptr(out, torch.int32), _stream(stream)))
+
+
+def cascade_eval_device(f15, ids, stream=None):
+    """Configuration ids for rows of 15 model inputs (float64 device tensor
+    of shape (count, 15)) into ids (int32 device tensor of count)."""
+    import torch
+    if f15.dim() != 2 or f15.shape[1] != 15 or ids.numel() < f15.shape[0]:
+        raise ValueError("f15 must be (count, 15) and ids hold count entries")
+    _check(lib().ck_cascade_eval_device(_ptr(f15, torch.float64), f15.shape[0],
+                                        _ptr(ids, torch.int32), _stream(stream)))
 
 
 def spmv_select(features, model_path=None):

@@ -17,7 +17,7 @@ ARCH = os.environ.get("PYTORCH_ROCM_ARCH", "gfx950").split(";")[0]
 
 SOURCES = ["api.hip", "spmv.hip", "vecops.hip", "gmres.hip", "features.hip", "solvers.hip",
            "predictor.cpp", "batched.hip", "server.hip", "panel.hip", "smallcg.hip",
-           "diahyb.hip", "devcache.hip"]
+           "diahyb.hip", "devcache.hip", "devcascade.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -67,6 +67,7 @@ static void release(ck_matrix *M) {
     mat_free(*M, M->merge_part);
     mat_free(*M, M->panel_part);
     mat_free(*M, M->panel_row);
+    mat_free(*M, M->devsel_scratch);
     mat_free(*M, M->panel_boff);
     for (auto &kv : M->carry)
         mat_free(*M, kv.second);

@@ -676,6 +676,38 @@ ck_status launch_features(const ck_matrix &M, void *scratch, bool symmetry, hipS
     return CK_OK;
 }
 
+// The 28 integer fields on the device (layout of ck_features' integer part;
+// is_symmetric from the accumulators only when the symmetry search ran).
+__global__ void feat_to_ints(const FeatAcc *acc, int64_t n, int64_t ncols, int64_t nnz,
+                             int symmetry, int64_t *out) {
+    if (threadIdx.x != 0)
+        return;
+    out[0] = n;
+    out[1] = ncols;
+    out[2] = nnz;
+    out[3] = (int64_t)acc->sum_r;
+    out[4] = (int64_t)acc->sum_r2;
+    out[5] = n > 0 ? (int64_t)acc->max_r : 0;
+    out[6] = n > 0 ? (int64_t)acc->min_r : 0;
+    out[7] = (int64_t)acc->span;
+    out[8] = (int64_t)acc->cluster;
+    out[9] = (int64_t)acc->ndiag;
+    out[10] = (int64_t)acc->diag_nnz;
+    for (int b = 0; b < 16; ++b)
+        out[11 + b] = (int64_t)acc->hist[b];
+    out[27] = symmetry ? ((n == ncols && acc->asym == 0) ? 1 : 0) : -1;
+}
+
+ck_status launch_feature_ints(const ck_matrix &M, const void *scratch, bool symmetry,
+                              int64_t *out28, hipStream_t s) {
+    const FeatAcc *acc =
+        (const FeatAcc *)((const char *)scratch + features_acc_offset(M.n, M.ncols));
+    hipLaunchKernelGGL(feat_to_ints, dim3(1), dim3(64), 0, s, acc, M.n, M.ncols, M.nnz,
+                       symmetry ? 1 : 0, out28);
+    CK_HIP(hipGetLastError());
+    return CK_OK;
+}
+
 // Copies the accumulators into the 28 int64 of ck_features' integer part.
 void features_from_acc(const void *acc_host, const ck_matrix &M, int64_t *out28) {
     const FeatAcc *a = (const FeatAcc *)acc_host;

@@ -68,6 +68,9 @@ struct ck_matrix {
     int hyb_L = 1;
     std::atomic<bool> has_hyb{false};
     int64_t max_row = -1;             // longest row, once known
+    // feature scratch of the device-resident cascade (kept with the handle)
+    char *devsel_scratch = nullptr;
+    int64_t *devsel_ints = nullptr;
     ck_config active{};
     std::mutex mu;                    // guards conversions, `active` and `carry`
     ck::MemSource mem;                // where every device block of the handle comes from

@@ -1,7 +1,7 @@
 // Cascaded SpMV-configuration predictor (Section III-C-1, cascaded-prediction
 // figure): three decision trees evaluated in sequence.
-//   stage 1 "format"    : CSR / ELL / COO
-//   stage 2 "algorithm" : (CSR only) scalar / vector / merge-path
+//   stage 1 "format"    : CSR / ELL / COO / DIA / HYB
+//   stage 2 "algorithm" : (CSR only) scalar / vector / merge-path / panel
 //   stage 3 "lanes"     : (CSR-vector only) log2 of lanes per row, 0..6
 // and optionally a "start" tree over the inputs known before any pass over
 // the entries (dimensions, nnz, density, mean row length), which picks the
@@ -21,6 +21,7 @@
 #include <dlfcn.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -29,6 +30,7 @@
 #include <string>
 #include <vector>
 
+#include "derive.hpp"
 #include "predictor.hpp"
 
 namespace ck {
@@ -162,42 +164,34 @@ int Tree::eval(const double *f) const {
     return cls[t];
 }
 
-// The 15 model inputs in feature-table order.
-#pragma clang fp contract(off)
+static_assert(offsetof(ck_features, density) == 28 * sizeof(int64_t),
+              "the 28 integer fields of ck_features come first, in order");
+
+// The floating-point features from the integer ones (derive.hpp: the same
+// derivation as the device-resident cascade's).
 void derive_features(ck_features &F) {
-    const double n = (double)F.nrows;
-    F.density = F.mean = F.sd = F.cov = F.maxavg = F.distavg = F.clusteravg = F.fill =
-        F.diagfill = 0.0;
-    if (F.nrows <= 0)
-        return;
-    F.density = F.ncols > 0 ? (double)F.nnz / (n * (double)F.ncols) : 0.0;
-    F.mean = (double)F.nnz / n;
-    const __int128 var = (__int128)F.nrows * (__int128)F.sum_r2 - (__int128)F.sum_r * (__int128)F.sum_r;
-    F.sd = std::sqrt((double)var) / n;
-    F.cov = F.mean > 0.0 ? F.sd / F.mean : 0.0;
-    F.maxavg = (double)F.max_r - F.mean;
-    F.distavg = (double)F.span_sum / n;
-    F.clusteravg = (double)F.cluster_sum / n;
-    F.fill = F.nnz > 0 ? (n * (double)F.max_r) / (double)F.nnz : 0.0;
-    F.diagfill = F.nnz > 0 ? (n * (double)F.ndiag) / (double)F.nnz : 0.0;
+    int64_t I[28];
+    std::memcpy(I, &F, sizeof I);
+    double d[9];
+    derive_inputs(I, d);
+    F.density = d[0];
+    F.mean = d[1];
+    F.sd = d[2];
+    F.cov = d[3];
+    F.maxavg = d[4];
+    F.distavg = d[5];
+    F.clusteravg = d[6];
+    F.fill = d[7];
+    F.diagfill = d[8];
 }
 
+// The 15 model inputs in feature-table order.
 void model_inputs(const ck_features &F, double *f) {
-    f[0] = (double)F.nrows;
-    f[1] = (double)F.ncols;
-    f[2] = (double)F.nnz;
-    f[3] = F.density;
-    f[4] = F.mean;
-    f[5] = F.sd;
-    f[6] = F.cov;
-    f[7] = (double)F.max_r;
-    f[8] = (double)F.min_r;
-    f[9] = F.maxavg;
-    f[10] = F.distavg;
-    f[11] = F.clusteravg;
-    f[12] = F.fill;
-    f[13] = (double)F.ndiag;
-    f[14] = F.diagfill;
+    int64_t I[28];
+    std::memcpy(I, &F, sizeof I);
+    const double d[9] = {F.density, F.mean, F.sd, F.cov, F.maxavg, F.distavg, F.clusteravg,
+                         F.fill, F.diagfill};
+    model_inputs_from(I, d, f);
 }
 
 int start_config_id(const Cascade &C, int64_t nrows, int64_t ncols, int64_t nnz) {

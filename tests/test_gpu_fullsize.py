@@ -2,8 +2,9 @@
 configurations the bench times:
 
 * every matrix of the 48-matrix SpMV set (n = 1e4 .. 2e6): integer features
-  and derived features bit-exact, the cascade's decision equal to the
-  oracle's, and every one of the 14 SpMV configurations element by element
+  and derived features bit-exact, the cascade's decision (host and
+  device-resident) equal to the oracle's, and every one of the 14 SpMV
+  configurations element by element
   against the oracle's FP64 product (the oracle computes the whole product in
   well under a second);
 * ELL, COO, DIA and HYB conversions byte-exact on the largest member of each
@@ -46,6 +47,12 @@ def test_spmv_set_member(ck, orc, spec):
     assert F.ints() == [int(v) for v in ints]
     assert np.array_equal(np.array(F.derived()).view(np.int64), der.view(np.int64))
     assert ck.select_stages(F) == orc.cascade(parse_model(MODEL), f15)
+    # the device-resident cascade reaches the same decision on the device
+    out = torch.full((8,), -9, dtype=torch.int32, device="cuda")
+    ck.select_device(Mx.handle, out)
+    dev = out.cpu().tolist()
+    assert dev[4:7] == orc.cascade(parse_model(MODEL), f15), (A.name, dev)
+    assert dev[7] == ck.config_id(ck.spmv_select(F)), (A.name, dev)
     # every configuration against the oracle product
     x = np.random.default_rng(spec[4]).uniform(-1, 1, A.ncols)
     ref = orc.spmv(A, x)

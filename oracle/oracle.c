@@ -426,9 +426,10 @@ int32_t orc_tree_eval(const int32_t *feature, const double *thr, const int32_t *
 }
 
 /* Cascade over three trees given as (feature, thr, left, right, cls) blocks.
- * Stage 1 picks the format (0 CSR, 1 ELL, 2 COO); only for CSR does stage 2
- * pick the CSR algorithm (0 scalar with row-block staging, 1 vector,
- * 2 merge-path); only for vector does stage 3 pick log2 of the lanes per row.
+ * Stage 1 picks the format (0 CSR, 1 ELL, 2 COO, 3 DIA, 4 HYB); only for CSR
+ * does stage 2 pick the CSR algorithm (0 scalar, 1 vector, 2 merge-path,
+ * 3 column panels); only for vector does stage 3 pick log2 of the lanes per
+ * row.
  * out[0..2] = the three decisions (-1 when a stage does not run). */
 void orc_cascade(const int32_t *f1, const double *t1, const int32_t *l1, const int32_t *r1,
                  const int32_t *c1, const int32_t *f2, const double *t2, const int32_t *l2,

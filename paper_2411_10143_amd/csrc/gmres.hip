@@ -1,23 +1,31 @@
 // GMRES(m) kernels (the solver of the paper's evaluation, Section IV).
 //
-// One Arnoldi step j after the SpMV w = A v_j (written straight into basis
-// column j+1) is classical Gram-Schmidt applied twice, in three fused passes
-// over the basis:
-//   pass 1: partials of V_j^T w                        -> finish: h1
-//   pass 2: w' = w - V_j h1, and in the same sweep partials of V_j^T w' (h2)
-//           and of ||w'||^2
-//   givens: one workgroup sums the pass-2 partials (h2, ||w'||^2), then
-//           h_{j+1,j} = sqrt(||w'||^2 - ||h2||^2) (Pythagoras: w' - V_j h2 is
-//           w' minus its projection on the orthonormal V_j), column j of the
-//           Hessenberg matrix (h1 + h2), previous Givens rotations, rotation
-//           j, residual estimate |g_{j+1}|, cycle stop decision
-//   pass 3: v_{j+1} = (w' - V_j h2) / h_{j+1,j}
+// One Arnoldi step j is classical Gram-Schmidt applied twice (CGS2):
+//   h1 = V_j^T w, w' = w - V_j h1, h2 = V_j^T w',
+//   h_{j+1,j} = ||w' - V_j h2|| = sqrt(||w'||^2 - ||h2||^2) (Pythagoras: the
+//   subtracted part is w''s projection on the orthonormal V_j),
+//   v_{j+1} = (w' - V_j h2) / h_{j+1,j},  column j of H = h1 + h2,
+// with w = A v_j.  Forming v_{j+1} would take a third sweep over the basis;
+// instead it is left for the next step, which applies the SpMV to w' itself
+// (z = A w', written to column j+2) and opens with one sweep that forms both
+// v_{j+1} = (w' - V_j h2) / h and A v_{j+1} = (z - V_{j+1} u) / h, where
+// u = Hbar_j h2 is A (V_j h2) expressed in the basis through the Arnoldi
+// relation A V_j = V_{j+1} Hbar_j, and that also sums the partials of
+// V_{j+1}^T A v_{j+1}.  So each step streams the basis twice:
+//   step 0:  pass 1 (partials of V_0^T w)               -> finish: h1
+//   step j:  pass 3+1 (v_j, A v_j in place, partials of V_j^T A v_j) -> h1
+//   then     pass 2: w' = w - V_j h1, partials of V_j^T w' (h2) and ||w'||^2
+//            givens: one workgroup sums the pass-2 partials, forms h_{j+1,j},
+//            H column j (kept unrotated for u, and rotated), the previous
+//            Givens rotations, rotation j, residual estimate |g_{j+1}|, the
+//            cycle stop decision, and u = Hbar_j h2 for the next step.
 // After the first projection h2 is of rounding size relative to w', so the
-// subtraction loses nothing that matters, and the norm needs no third
-// reduction.  Each pass streams the j+1 basis columns once; per-column sums
-// are reduced in a fixed order (wave butterfly, 4 waves, then block order),
-// so results are deterministic.  The least-squares solve and the solution update close the
-// cycle on the device; nothing returns to the host inside a cycle.
+// corrections through h2 and u change w' and z by rounding-size amounts.
+// The last step of a cycle needs no v_{j+1}: the update x += V_k y uses
+// v_0 .. v_{k-1}.  Per-column sums are reduced in a fixed order (wave
+// butterfly, 4 waves, then block order), so results are deterministic.  The
+// least-squares solve and the solution update close the cycle on the
+// device; nothing returns to the host inside a cycle.
 #include "solvers.hpp"
 
 using ck::GmDev;
@@ -118,6 +126,60 @@ __global__ __launch_bounds__(256) void gm_pass2(int64_t n, int64_t G, int ncols,
         partials[ncols * G + b] = nn;
 }
 
+// Step j >= 1 opens here: column j holds w' of step j - 1 (after its first
+// projection, not yet corrected by h2 nor normalised) and column j + 1 holds
+// z = A w'.  One sweep over V_{j-1} forms, in place, v_j = (w' - V_{j-1} h2)
+// * inv and A v_j = (z - V_{j-1} u_{0..j-1} - u_j v_j) * inv, and the
+// partials of V_j^T A v_j (columns 0..j).  h2, u and inv are step j - 1's.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void gm_pass31(int64_t n, int64_t G, int j,
+                                                 T *__restrict__ V, int64_t ldv,
+                                                 T *__restrict__ partials, const GmDev<T> *st) {
+    if (st->halt)
+        return;
+    const int64_t b = blockIdx.x;
+    const int nold = j;   // finished columns 0 .. j-1, read from memory (NC >= j + 1)
+    T h2[NC], u[NC], acc[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        h2[c] = c < nold ? st->h2[c] : T(0);
+        u[c] = c < nold ? st->u[c] : T(0);
+        acc[c] = 0;
+    }
+    const T uj = st->u[j];
+    const T inv = st->inv;
+    T *wv = V + (int64_t)j * ldv;         // w' in, v_j out
+    T *zw = V + (int64_t)(j + 1) * ldv;   // z in, A v_j out
+    T accj = 0;
+    for (int64_t i = b * 256 + threadIdx.x; i < n; i += G * 256) {
+        T a = wv[i], zz = zw[i];
+        T vv[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            vv[c] = V[clampc(c, nold) * ldv + i];
+        __builtin_amdgcn_sched_barrier(0);   // every load issued before the first use
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            a -= h2[c] * vv[c];
+            zz -= u[c] * vv[c];
+        }
+        const T vj = a * inv;
+        zz -= uj * vj;
+        const T wi = zz * inv;
+        wv[i] = vj;
+        zw[i] = wi;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+            acc[c] += vv[c] * wi;
+        accj += vj * wi;
+    }
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if (c == j)
+            acc[c] = accj;   // column j is v_j itself (the loop's acc[j] saw a reloaded column)
+    block_cols<T, NC>(acc, j + 1, partials, b, G);
+}
+
 // out[c] = sum_b partials[c*G + b]; block c reduces column c in block order
 template <typename T>
 __global__ __launch_bounds__(256) void gm_finish_cols(int64_t G, const T *__restrict__ partials,
@@ -129,33 +191,6 @@ __global__ __launch_bounds__(256) void gm_finish_cols(int64_t G, const T *__rest
     const T s = ck::sum_partials(partials + c * G, G, lds);
     if (threadIdx.x == 0)
         (which == 1 ? st->h1 : st->h2)[c] = s;
-}
-
-// v_{j+1} = (w' - V_j h2) * inv
-template <typename T, int NC>
-__global__ __launch_bounds__(256) void gm_pass3(int64_t n, int64_t G, int ncols,
-                                                const T *__restrict__ V, int64_t ldv,
-                                                T *__restrict__ w, const GmDev<T> *st) {
-    if (st->halt)
-        return;
-    const int64_t b = blockIdx.x;
-    T h[NC];
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-        h[c] = c < ncols ? st->h2[c] : T(0);
-    const T inv = st->inv;
-    for (int64_t i = b * 256 + threadIdx.x; i < n; i += G * 256) {
-        T wi = w[i];
-        T vv[NC];
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            vv[c] = V[clampc(c, ncols) * ldv + i];
-        __builtin_amdgcn_sched_barrier(0);   // every load issued before the first use
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-            wi -= h[c] * vv[c];
-        w[i] = wi * inv;
-    }
 }
 
 // Pass-2 finish and Givens step in one 1024-thread workgroup:
@@ -204,15 +239,32 @@ __global__ __launch_bounds__(1024) void gm_finish_givens(int64_t G, const T *__r
     __syncthreads();
     for (int c = threadIdx.x; c <= j; c += 1024)
         col[c] = st->h1[c] + h2[c];
+    __shared__ T hn_s;
+    if (threadIdx.x == 0) {
+        T proj = 0;
+        for (int c = 0; c <= j; ++c)
+            proj += h2[c] * h2[c];
+        const T nrm2 = h2[j + 1] - proj;
+        hn_s = nrm2 > T(0) ? sqrt(nrm2) : T(0);
+    }
     __syncthreads();
+    const T hn = hn_s;
+    // unrotated column j, then u = Hbar_j h2 (row i sums columns c >= i - 1)
+    T *Rj = st->Hraw + (int64_t)j * (m + 1);
+    for (int c = threadIdx.x; c <= j; c += 1024)
+        Rj[c] = col[c];
+    if (threadIdx.x == 0)
+        Rj[j + 1] = hn;
+    for (int i = threadIdx.x; i <= j + 1; i += 1024) {
+        T acc = 0;
+        for (int c = i > 0 ? i - 1 : 0; c < j; ++c)
+            acc += st->Hraw[(int64_t)c * (m + 1) + i] * h2[c];
+        acc += (i <= j ? col[i] : hn) * h2[j];
+        st->u[i] = acc;
+    }
     if (threadIdx.x != 0)
         return;
     T *Hj = st->H + (int64_t)j * (m + 1);
-    T proj = 0;
-    for (int c = 0; c <= j; ++c)
-        proj += h2[c] * h2[c];
-    const T nrm2 = h2[j + 1] - proj;
-    const T hn = nrm2 > T(0) ? sqrt(nrm2) : T(0);
     // previous rotations applied to (h_0j, ..., h_jj, hn); `a` carries entry i
     T a = col[0];
     for (int i = 0; i < j; ++i) {
@@ -386,19 +438,24 @@ ck_status launch_gm_cycle_start(int64_t n, const double *r64, T *v0, double *par
 }
 
 template <typename T, int NC>
-static void arnoldi_nc(int64_t n, int64_t G, int ncols, T *V, int64_t ldv, T *w, T *partials,
+static void arnoldi_nc(int64_t n, int64_t G, int j, T *V, int64_t ldv, T *w, T *partials,
                        GmDev<T> *st, hipStream_t s) {
-    hipLaunchKernelGGL((gm_pass1<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w,
-                       partials, st);
+    const int ncols = j + 1;
+    if (j == 0)
+        hipLaunchKernelGGL((gm_pass1<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w,
+                           partials, st);
+    else
+        hipLaunchKernelGGL((gm_pass31<T, NC>), dim3(G), dim3(256), 0, s, n, G, j, V, ldv,
+                           partials, st);
     hipLaunchKernelGGL((gm_finish_cols<T>), dim3(ncols), dim3(256), 0, s, G, partials, 1, st);
     hipLaunchKernelGGL((gm_pass2<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w,
                        partials, st);
     hipLaunchKernelGGL((gm_finish_givens<T>), dim3(1), dim3(1024), 0, s, G, partials, st);
-    hipLaunchKernelGGL((gm_pass3<T, NC>), dim3(G), dim3(256), 0, s, n, G, ncols, V, ldv, w, st);
 }
 
-// Orthogonalisation and normalisation of w = V[:, j+1] (the SpMV output)
-// against columns 0..j.
+// Step j after the SpMV of column j into column j+1 (column j is v_0 for
+// j = 0, else the previous step's w', see the file comment): ends with
+// w' of step j in column j+1 and h2, u, inv of step j in the state.
 template <typename T>
 ck_status launch_gm_arnoldi(int64_t n, int j, T *V, int64_t ldv, T *partials, GmDev<T> *st,
                             hipStream_t s) {
@@ -406,21 +463,21 @@ ck_status launch_gm_arnoldi(int64_t n, int j, T *V, int64_t ldv, T *partials, Gm
     const int ncols = j + 1;
     T *w = V + (int64_t)(j + 1) * ldv;
     if (ncols <= 8)
-        arnoldi_nc<T, 8>(n, G, ncols, V, ldv, w, partials, st, s);
+        arnoldi_nc<T, 8>(n, G, j, V, ldv, w, partials, st, s);
     else if (ncols <= 16)
-        arnoldi_nc<T, 16>(n, G, ncols, V, ldv, w, partials, st, s);
+        arnoldi_nc<T, 16>(n, G, j, V, ldv, w, partials, st, s);
     else if (ncols <= 24)
-        arnoldi_nc<T, 24>(n, G, ncols, V, ldv, w, partials, st, s);
+        arnoldi_nc<T, 24>(n, G, j, V, ldv, w, partials, st, s);
     else if (ncols <= 32)
-        arnoldi_nc<T, 32>(n, G, ncols, V, ldv, w, partials, st, s);
+        arnoldi_nc<T, 32>(n, G, j, V, ldv, w, partials, st, s);
     else if (ncols <= 40)
-        arnoldi_nc<T, 40>(n, G, ncols, V, ldv, w, partials, st, s);
+        arnoldi_nc<T, 40>(n, G, j, V, ldv, w, partials, st, s);
     else if (ncols <= 48)
-        arnoldi_nc<T, 48>(n, G, ncols, V, ldv, w, partials, st, s);
+        arnoldi_nc<T, 48>(n, G, j, V, ldv, w, partials, st, s);
     else if (ncols <= 56)
-        arnoldi_nc<T, 56>(n, G, ncols, V, ldv, w, partials, st, s);
+        arnoldi_nc<T, 56>(n, G, j, V, ldv, w, partials, st, s);
     else if (ncols <= 64)
-        arnoldi_nc<T, 64>(n, G, ncols, V, ldv, w, partials, st, s);
+        arnoldi_nc<T, 64>(n, G, j, V, ldv, w, partials, st, s);
     else
         return fail(CK_E_INVALID, "restart length above %d", kMaxRestart);
     CK_HIP(hipGetLastError());

@@ -47,8 +47,10 @@ struct GmDev {
     T cs[kMaxRestart], sn[kMaxRestart];
     T g[kMaxRestart + 1];
     T y[kMaxRestart];
+    T Hraw[(kMaxRestart + 1) * kMaxRestart];   // H before the rotations
     T h1[kMaxRestart + 1];      // first Gram-Schmidt pass
     T h2[kMaxRestart + 1];      // second pass
+    T u[kMaxRestart + 2];       // Hbar_j h2: A (V_j h2) = V_{j+1} u
     T inv;                      // 1 / h_{j+1,j}
     double beta;                // ||r|| at the cycle start (FP64 true residual)
     double inv_beta;            // 1 / beta

@@ -273,8 +273,10 @@ ck_status ck_default_config(ck_handle h, ck_config *out);
  * K = longest row, pitch = nrows rounded up to 64, padding column -1 and
  * value +0.0; refused with CK_E_UNSUPPORTED when K*pitch > 8*nnz.  COO: a
  * row-index array (column and value arrays are shared with CSR).  CSR-panel:
- * panel-major copy of the column and value arrays plus per-panel row
- * pointers (P*nrows + 1 int32).  DIA: the ndiag distinct offsets
+ * panel-major copy of the column and value arrays, P column panels of
+ * ceil(ncols/P) columns (see ck_panel_layout), with per-panel row pointers
+ * (P*nrows + 1 int32), or, when at most 3/4 of the P*nrows panel rows hold
+ * entries, pointers and matrix-row indices of the non-empty ones only.  DIA: the ndiag distinct offsets
  * col - row of the stored entries (int32, ascending) and ndiag*pitch values,
  * diagonal k of row i at k*pitch + i, +0.0 where no entry is stored
  * (pitch = nrows rounded up to 64); refused with CK_E_UNSUPPORTED when
@@ -384,6 +386,15 @@ ck_status ck_export_hyb(ck_handle h, int32_t *d_col, double *d_val, int32_t *d_r
 /* ck_export_coo_rows -- copy the COO row array (after spmv_convert to COO)
  * into d_row int32[nnz]. */
 ck_status ck_export_coo_rows(ck_handle h, int32_t *d_row, hipStream_t s);
+
+/* ck_panel_layout -- the CSR-panel copy's shape (after spmv_convert to
+ * CSR-panel), to host memory: *panels = P, *width = columns per panel,
+ * *stored_rows = panel rows kept (P*nrows in the dense layout, the number
+ * of non-empty panel rows in the row-list one).  P is 8q with at most 2 MB
+ * of FP64 x per panel, or 4 when x fits four slices of 2.5 MB, the longest
+ * row is at most 4x ceil(nnz/nrows) and more than 3/4 of the 4*nrows panel
+ * rows hold entries.  CK_E_INVALID without a CSR-panel copy. */
+ck_status ck_panel_layout(ck_handle h, int32_t *panels, int64_t *width, int64_t *stored_rows);
 
 /* ck_dot -- deterministic two-stage FP64 dot product of two device vectors
  * (the inner product kernel of the Krylov loop, Introduction); result to

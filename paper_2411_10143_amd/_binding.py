@@ -214,6 +214,7 @@ SIGNATURES = {
     "gmres_solve": (_i32, [_vp, _vp, _vp, C.POINTER(SolveOpts), C.POINTER(SolveResult), _vp]),
     "ck_export_ell": (_i32, [_vp, _vp, _vp, C.POINTER(_i64), C.POINTER(_i64), _vp]),
     "ck_export_coo_rows": (_i32, [_vp, _vp, _vp]),
+    "ck_panel_layout": (_i32, [_vp, C.POINTER(_i32), C.POINTER(_i64), C.POINTER(_i64)]),
     "ck_eval_stage": (_i32, [C.POINTER(Features), C.c_char_p, _i32, C.POINTER(_i32)]),
     "ck_overhead_gate": (_i32, [C.POINTER(Features), C.POINTER(Config), _i32, _dbl, _i32, _dbl,
                                 _dbl, C.POINTER(_dbl), C.POINTER(_dbl), C.POINTER(_i32)]),
@@ -536,6 +537,13 @@ def export_coo_rows(h, nnz, stream=None):
     row = torch.empty(nnz, dtype=torch.int32, device="cuda")
     _check(lib().ck_export_coo_rows(h, _ptr(row) if nnz else None, _stream(stream)))
     return row
+
+
+def panel_layout(h):
+    """(panels, columns per panel, stored panel rows) of the CSR-panel copy."""
+    P, W, R = _i32(), _i64(), _i64()
+    _check(lib().ck_panel_layout(h, C.byref(P), C.byref(W), C.byref(R)))
+    return P.value, W.value, R.value
 
 
 def dot(x, y, out, stream=None):

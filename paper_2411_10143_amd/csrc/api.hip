@@ -136,21 +136,27 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
     if (c.format == CK_FMT_CSR) {   // CSR-panel
         if (M.has_panel.load())
             return CK_OK;
-        const int P = panel_count_for(M.ncols, 8);
+        const int P8 = panel_count_for(M.ncols, 8);
+        const int64_t N8 = (int64_t)P8 * M.n;   // the most panel rows P can give
+        if (N8 + 1 > (int64_t)std::numeric_limits<int32_t>::max())
+            return fail(CK_E_UNSUPPORTED, "too many panel rows");
+        int *tmp = nullptr;
+        CK_TRY(mat_alloc(M, &tmp, N8 + 2 + panel_scan_tmp_elems(N8), s));
+        int P = P8;
+        ck_status st = panel_choose_count(M, tmp, s, &P);
         const int64_t W = ceil_div(std::max<int64_t>(M.ncols, 1), P);
         const int64_t N = (int64_t)P * M.n;
-        if (N + 1 > (int64_t)std::numeric_limits<int32_t>::max())
-            return fail(CK_E_UNSUPPORTED, "too many panel rows");
-        CK_TRY(mat_alloc(M, &M.panel_rp, N + 1, s));
-        CK_TRY(mat_alloc(M, &M.panel_col, M.nnz, s));
-        CK_TRY(mat_alloc(M, &M.panel_val, M.nnz, s));
-        if (M.val32)
-            CK_TRY(mat_alloc(M, &M.panel_val32, M.nnz, s));
-        int *tmp = nullptr;
-        const int64_t tmp_elems = N + panel_scan_tmp_elems(N);
-        CK_TRY(mat_alloc(M, &tmp, tmp_elems, s));
-        ck_status st = launch_to_panel(M, P, W, tmp, tmp + N, M.panel_rp, M.panel_col,
-                                       M.panel_val, M.panel_val32, s);
+        if (st == CK_OK)
+            st = mat_alloc(M, &M.panel_rp, N + 1, s);
+        if (st == CK_OK)
+            st = mat_alloc(M, &M.panel_col, M.nnz, s);
+        if (st == CK_OK)
+            st = mat_alloc(M, &M.panel_val, M.nnz, s);
+        if (st == CK_OK && M.val32)
+            st = mat_alloc(M, &M.panel_val32, M.nnz, s);
+        if (st == CK_OK)
+            st = launch_to_panel(M, P, W, tmp, tmp + N, M.panel_rp, M.panel_col, M.panel_val,
+                                 M.panel_val32, s);
         M.panel_P = P;
         M.panel_W = W;
         M.panel_rows = N;
@@ -673,6 +679,17 @@ ck_status ck_export_coo_rows(ck_handle h, int32_t *d_row, hipStream_t s) {
         return fail(CK_E_INVALID, "matrix has no COO copy");
     if (h->nnz)
         CK_HIP(hipMemcpyAsync(d_row, h->coo_row, h->nnz * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    return CK_OK;
+}
+
+ck_status ck_panel_layout(ck_handle h, int32_t *panels, int64_t *width, int64_t *stored_rows) {
+    if (!h || !panels || !width || !stored_rows)
+        return fail(CK_E_INVALID, "NULL argument");
+    if (!h->has_panel.load())
+        return fail(CK_E_INVALID, "matrix has no CSR-panel copy");
+    *panels = h->panel_P;
+    *width = h->panel_W;
+    *stored_rows = h->panel_rows;
     return CK_OK;
 }
 

@@ -14,6 +14,7 @@
 
 #include "matrix.hpp"
 #include "panel.hpp"
+#include "solvers.hpp"
 
 
 // cnt[p*n + i] = entries of row i whose column lies in panel p
@@ -42,7 +43,7 @@ __global__ __launch_bounds__(256) void panel_count(int64_t n, int P, int64_t W,
 }
 
 // Panel-major copy: row i's panel-p entries go to prp[p*n + i] onwards.
-// Eight lanes per row, lane l taking panels l, l + 8, ...: a row's entries
+// Eight lanes per row, lane l taking panels l, l + 8, ... (any P): a row's entries
 // of consecutive panels are consecutive (columns are sorted), so an
 // exclusive sum of the eight segment lengths gives each lane the start of its
 // segment, and the eight lanes read the row as one contiguous run.
@@ -60,9 +61,11 @@ __global__ __launch_bounds__(256) void panel_fill(int64_t n, int P, const int *_
         return;   // whole groups leave together (8 divides the wave)
     int base = rp[i];
     for (int p0 = 0; p0 < P; p0 += L) {
+        // lanes past the last panel (P not a multiple of 8) hold an empty segment
+        const bool has = p0 + lane < P;
         const int64_t at = (int64_t)(p0 + lane) * n + i;
-        const int dst0 = prp[at];
-        const int len = prp[at + 1] - dst0;
+        const int dst0 = has ? prp[at] : 0;
+        const int len = has ? prp[at + 1] - dst0 : 0;
         int ex = len;   // inclusive scan over the group's lanes, then exclusive
 #pragma unroll
         for (int off = 1; off < L; off <<= 1) {
@@ -127,6 +130,25 @@ __global__ __launch_bounds__(256) void scan_add(int64_t N, int *__restrict__ out
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (g < N)
         out[g] += offs[g / 2048];
+}
+
+// *total += number of nonzero counts (one atomic per block)
+__global__ __launch_bounds__(256) void count_nonzero(int64_t N, const int *__restrict__ cnt,
+                                                     unsigned long long *total) {
+    unsigned long long c = 0;
+    for (int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x; k < N;
+         k += (int64_t)gridDim.x * 256)
+        c += cnt[k] > 0 ? 1ull : 0ull;
+    __shared__ unsigned long long part[4];
+    c = ck::wave_sum(c);
+    if ((threadIdx.x & 63) == 0)
+        part[threadIdx.x >> 6] = c;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const unsigned long long t = part[0] + part[1] + part[2] + part[3];
+        if (t)
+            atomicAdd(total, t);
+    }
 }
 
 // flag[k] = 1 if panel row k holds entries (in place over the counts)
@@ -257,6 +279,57 @@ int panel_count_for(int64_t ncols, int value_bytes) {
     const int64_t per_panel = (2 << 20) / value_bytes;        // x slice <= 2 MB
     const int64_t q = std::max<int64_t>(1, ceil_div(ncols, 8 * per_panel));
     return (int)(8 * q);
+}
+
+// A matrix whose x fits four slices of at most 2.5 MB, whose rows are of
+// even length (the longest at most four times the mean) and have entries in
+// nearly every one of four panels, takes P = 4 (two XCDs share a panel): its
+// partial sums, kept dense, halve while each XCD's slice still stays in its
+// 4 MB L2 (uniform-random rows of 4-64 entries: 292 -> 253 us at n = 1.2M,
+// 185 -> 160 us at n = 0.76M).  Short-row matrices keep P = 8: their row
+// lists gain little from fewer panels and lose L2 hits (power-law n = 1.2M:
+// 272 -> 304 us with P = 4); so do hub-row graphs (14-31 % slower with P = 4
+// on the training graphs) and matrices with a larger x (uniform n = 2M, a
+// 4 MB slice: 465 -> 483 us).
+constexpr int64_t kSliceP4 = 5 * (int64_t(1) << 19);   // 2.5 MB
+
+ck_status launch_row_max(int64_t n, const int *rp, unsigned long long *out, hipStream_t s);
+
+ck_status panel_choose_count(const ck_matrix &M, int *tmp, hipStream_t s, int *P_out) {
+    const int P8 = panel_count_for(M.ncols, 8);
+    *P_out = P8;
+    if (P8 != 8 || M.n == 0 || M.ncols * 8 > 4 * kSliceP4)
+        return CK_OK;
+    // the longest row (known after the feature pass; else one pass over rowptr)
+    int64_t max_r = M.max_row;
+    if (max_r < 0) {
+        unsigned long long *d = (unsigned long long *)tmp;
+        unsigned long long h = 0;
+        CK_TRY(launch_fill<int>(2, (int *)d, 0, s));
+        CK_TRY(launch_row_max(M.n, M.rp, d, s));
+        CK_HIP(hipMemcpyAsync(&h, d, sizeof h, hipMemcpyDeviceToHost, s));
+        CK_HIP(hipStreamSynchronize(s));
+        max_r = (int64_t)h;
+    }
+    if (max_r > 4 * ceil_div(M.nnz, M.n))
+        return CK_OK;
+    const int64_t N4 = 4 * M.n;
+    const int64_t W4 = ceil_div(std::max<int64_t>(M.ncols, 1), 4);
+    // counts of the four panels, then the number of non-empty panel rows;
+    // the counter sits after the counts, 8-byte aligned (tmp holds >= 8n + 2 ints)
+    unsigned long long *total = (unsigned long long *)(tmp + ((N4 + 1) / 2) * 2);
+    CK_TRY(launch_fill<int>(2, (int *)total, 0, s));
+    hipLaunchKernelGGL(panel_count, dim3(ceil_div(M.n, 256)), dim3(256), 0, s, M.n, 4, W4, M.rp,
+                       M.col, tmp);
+    hipLaunchKernelGGL(count_nonzero, dim3(std::min<int64_t>(ceil_div(N4, 256), 1024)), dim3(256),
+                       0, s, N4, tmp, total);
+    CK_HIP(hipGetLastError());
+    unsigned long long ne = 0;
+    CK_HIP(hipMemcpyAsync(&ne, total, sizeof ne, hipMemcpyDeviceToHost, s));
+    CK_HIP(hipStreamSynchronize(s));
+    if (4 * (int64_t)ne > 3 * N4)   // the P = 4 layout would be dense
+        *P_out = 4;
+    return CK_OK;
 }
 
 int64_t panel_scan_tmp_elems(int64_t N) {

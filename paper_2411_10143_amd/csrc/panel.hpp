@@ -9,6 +9,10 @@ namespace ck {
 // panels for a vector of ncols entries of value_bytes each (x slice <= 2 MB)
 int panel_count_for(int64_t ncols, int value_bytes);
 int64_t panel_scan_tmp_elems(int64_t N);
+// The panel count of M's CSR-panel copy: panel_count_for(ncols, 8), or 4
+// (see panel.hip).  tmp: scratch of at least panel_count_for(ncols, 8) * n
+// + 2 ints; returns when decided.
+ck_status panel_choose_count(const ck_matrix &M, int *tmp, hipStream_t s, int *P_out);
 // Exclusive scan of N ints into N + 1 outputs (out[N] = total); tmp holds
 // panel_scan_tmp_elems(N) ints.
 ck_status launch_scan_exclusive(int64_t N, const int *in, int *out, int *tmp, hipStream_t s);

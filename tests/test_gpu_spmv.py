@@ -413,3 +413,62 @@ def test_converted_copy_serves_another_stream_at_once(ck, orc, cid):
     bound = spmv_bound(orc, A, x, 1.0, 0.0, None, U64, k_extra=4)
     assert np.all(np.abs(dy.cpu().numpy() - ref) <= bound)
     Mx.close()
+
+
+def _with_hub_row(A, length):
+    """A with row 0 replaced by `length` entries in columns 0, 1, ..."""
+    r0 = int(A.rp[1])
+    L = min(length, A.ncols)
+    col = np.concatenate([np.arange(L, dtype=np.int32), A.col[r0:]])
+    val = np.concatenate([np.linspace(0.5, 1.5, L), A.val[r0:]])
+    rp = np.concatenate([[0], A.rp[1:] - r0 + L]).astype(np.int32)
+    return M.CSR(A.n, A.ncols, rp, col, val, "hub").check()
+
+
+def _expected_panel_layout(A):
+    """The panel count and layout the conversion documents: P8 = 8q panels of
+    at most 2 MB of FP64 x; P = 4 when x fits four 2.5 MB slices, the longest
+    row is at most 4 ceil(nnz/n) and more than 3/4 of the 4n panel rows hold
+    entries; the row-list layout when at most 3/4 of the P n rows do."""
+    per = (2 << 20) // 8
+    P8 = 8 * max(1, -(-A.ncols // (8 * per)))
+    lengths = np.diff(A.rp.astype(np.int64))
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), lengths)
+
+    def nonempty(P):
+        W = -(-max(A.ncols, 1) // P)
+        return len(np.unique(rows * P + A.col.astype(np.int64) // W))
+
+    P = P8
+    if (P8 == 8 and A.n > 0 and A.ncols * 8 <= 4 * 5 * (1 << 19)
+            and lengths.max() <= 4 * (-(-A.nnz // A.n)) and 4 * nonempty(4) > 3 * 4 * A.n):
+        P = 4
+    ne = nonempty(P)
+    return P, -(-max(A.ncols, 1) // P), (P * A.n if 4 * ne > 3 * P * A.n else ne)
+
+
+@pytest.mark.parametrize("name", ["uniform", "uniform_hub", "powerlaw", "int_ragged", "banded27",
+                                  "column_runs", "single_row", "empty"])
+def test_panel_count_and_layout(ck, orc, name):
+    """Four panels only for even rows that fill them (uniform); a hub row, short
+    rows or sparse panel rows keep eight; the product agrees in both layouts."""
+    import torch
+    A = _with_hub_row(case("uniform"), 4 * 40) if name == "uniform_hub" else case(name)
+    want = _expected_panel_layout(A)
+    if name == "uniform":
+        assert want[0] == 4
+    if name in ("uniform_hub", "powerlaw"):
+        assert want[0] == 8
+    say(f"panel layout {name} n={A.n} nnz={A.nnz} expect P={want[0]} rows={want[2]}")
+    Mx = ck.Matrix.from_csr(A)
+    cfg = ck.config_from_id(ck.CONFIG_NAMES.index("csr-panel"))
+    ck.spmv_convert(Mx.handle, cfg)
+    assert ck.panel_layout(Mx.handle) == want
+    rng = np.random.default_rng(31)
+    x = rng.uniform(-1, 1, A.ncols)
+    y0 = rng.uniform(-1, 1, A.n)
+    dy = torch.from_numpy(y0).cuda()
+    ck.spmv_apply(Mx.handle, torch.from_numpy(x).cuda(), dy, 1.5, -0.5, cfg)
+    ref = orc.spmv(A, x, 1.5, -0.5, y0)
+    assert np.all(np.abs(dy.cpu().numpy() - ref) <= spmv_bound(orc, A, x, 1.5, -0.5, y0, U64))
+    Mx.close()

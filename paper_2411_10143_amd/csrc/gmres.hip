@@ -94,16 +94,20 @@ __global__ __launch_bounds__(256) void gm_pass2(int64_t n, int64_t G, int ncols,
                                                 const T *__restrict__ V, int64_t ldv,
                                                 T *__restrict__ w, T *__restrict__ partials,
                                                 const GmDev<T> *st) {
-    if (st->halt)
-        return;
-    const int64_t b = blockIdx.x;
+    // A halted solve runs no rows (and leaves zero partials, which no later
+    // kernel reads): the flag only sets the loop bound, so the coefficient
+    // loads are issued with it rather than after an early exit.  h1 holds
+    // kMaxRestart + 1 >= NC entries.
+    const int64_t nl = st->halt ? 0 : n;
     T h[NC], acc[NC], nn = 0;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        h[c] = c < ncols ? st->h1[c] : T(0);
+        const T hc = st->h1[c];   // unconditional: the loads merge
+        h[c] = c < ncols ? hc : T(0);
         acc[c] = 0;
     }
-    for (int64_t i = b * 256 + threadIdx.x; i < n; i += G * 256) {
+    const int64_t b = blockIdx.x;
+    for (int64_t i = b * 256 + threadIdx.x; i < nl; i += G * 256) {
         T vv[NC];
         T wi = w[i];
 #pragma unroll
@@ -135,23 +139,23 @@ template <typename T, int NC>
 __global__ __launch_bounds__(256) void gm_pass31(int64_t n, int64_t G, int j,
                                                  T *__restrict__ V, int64_t ldv,
                                                  T *__restrict__ partials, const GmDev<T> *st) {
-    if (st->halt)
-        return;
-    const int64_t b = blockIdx.x;
     const int nold = j;   // finished columns 0 .. j-1, read from memory (NC >= j + 1)
     T h2[NC], u[NC], acc[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
-        h2[c] = c < nold ? st->h2[c] : T(0);
-        u[c] = c < nold ? st->u[c] : T(0);
+        const T hc = st->h2[c], uc = st->u[c];   // unconditional: the loads merge
+        h2[c] = c < nold ? hc : T(0);
+        u[c] = c < nold ? uc : T(0);
         acc[c] = 0;
     }
     const T uj = st->u[j];
     const T inv = st->inv;
+    const int64_t nl = st->halt ? 0 : n;   // as in gm_pass2: no rows once halted
+    const int64_t b = blockIdx.x;
     T *wv = V + (int64_t)j * ldv;         // w' in, v_j out
     T *zw = V + (int64_t)(j + 1) * ldv;   // z in, A v_j out
     T accj = 0;
-    for (int64_t i = b * 256 + threadIdx.x; i < n; i += G * 256) {
+    for (int64_t i = b * 256 + threadIdx.x; i < nl; i += G * 256) {
         T a = wv[i], zz = zw[i];
         T vv[NC];
 #pragma unroll
@@ -185,11 +189,12 @@ template <typename T>
 __global__ __launch_bounds__(256) void gm_finish_cols(int64_t G, const T *__restrict__ partials,
                                                       int which, GmDev<T> *st) {
     __shared__ T lds[4];
-    if (st->halt)
-        return;
+    // the partials are read whether or not the solve has halted (they are
+    // always allocated); only the store depends on the flag
+    const int halt = st->halt;
     const int c = blockIdx.x;
     const T s = ck::sum_partials(partials + c * G, G, lds);
-    if (threadIdx.x == 0)
+    if (!halt && threadIdx.x == 0)
         (which == 1 ? st->h1 : st->h2)[c] = s;
 }
 
@@ -206,10 +211,14 @@ __global__ __launch_bounds__(1024) void gm_finish_givens(int64_t G, const T *__r
     constexpr int U = 8;
     __shared__ T col[ck::kMaxRestart], h2[ck::kMaxRestart + 1], cs[ck::kMaxRestart],
         sn[ck::kMaxRestart];
-    if (st->halt)
+    __shared__ T hr[ck::kMaxRestart * (ck::kMaxRestart + 1)];   // Hraw columns 0 .. j-1
+    const int halt = st->halt, m = st->m, j = st->j;   // one round trip
+    if (halt)
         return;
-    const int m = st->m;
-    const int j = st->j;
+    // one parallel load of the unrotated columns 0 .. j-1 for u below (each
+    // thread would otherwise wait on a chain of j global loads)
+    for (int k = threadIdx.x; k < j * (m + 1); k += 1024)
+        hr[k] = st->Hraw[k];
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int c = w; c <= j + 1; c += 16) {
         const T *pc = partials + (int64_t)c * G;
@@ -258,7 +267,7 @@ __global__ __launch_bounds__(1024) void gm_finish_givens(int64_t G, const T *__r
     for (int i = threadIdx.x; i <= j + 1; i += 1024) {
         T acc = 0;
         for (int c = i > 0 ? i - 1 : 0; c < j; ++c)
-            acc += st->Hraw[(int64_t)c * (m + 1) + i] * h2[c];
+            acc += hr[c * (m + 1) + i] * h2[c];
         acc += (i <= j ? col[i] : hn) * h2[j];
         st->u[i] = acc;
     }

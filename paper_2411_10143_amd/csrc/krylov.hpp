@@ -27,6 +27,8 @@ enum : int { RUN = 0, CONVERGED = 1, BREAKDOWN = 2, BUDGET = 3 };
 template <typename T>
 struct CgDev {
     T rho;            // r.r of the current residual
+    T rho_prev;       // rho as the sigma finish saw it (read by the x/p
+                      // update while its block 0 replaces rho)
     T sigma;          // p.Ap
     T alpha, beta;
     double bnorm;     // ||rhs|| of this (inner) solve
@@ -35,7 +37,8 @@ struct CgDev {
     int state;
     int iter;         // iterations completed
     int max_iter;
-    int pad;
+    int go;           // set by the sigma finish: 1 when this iteration's
+                      // x/p update runs (state RUN and sigma > 0)
 };
 
 // GMRES(m) cycle scalars (Givens form of the Hessenberg least squares).

@@ -103,29 +103,37 @@ __global__ __launch_bounds__(256) void cg_sigma(int64_t n, int64_t G, const T *_
         partials[b] = s;
 }
 
-// sigma = p.Ap; alpha = rho/sigma, or BREAKDOWN when sigma <= 0
+// sigma = p.Ap; alpha = rho/sigma, or BREAKDOWN when sigma <= 0.  `go`
+// tells the x/p update of this iteration whether to run.
 template <typename T>
 __global__ __launch_bounds__(256) void cg_sigma_finish(int64_t G, const T *__restrict__ partials,
                                                        CgDev<T> *cg) {
     __shared__ T lds[4];
-    if (cg->state != ck::RUN)
+    if (cg->state != ck::RUN) {
+        if (threadIdx.x == 0)
+            cg->go = 0;
         return;
+    }
     const T sigma = ck::sum_partials(partials, G, lds);
     if (threadIdx.x == 0) {
         cg->sigma = sigma;
-        if (!(sigma > T(0)))
+        cg->rho_prev = cg->rho;
+        if (!(sigma > T(0))) {
             cg->state = ck::BREAKDOWN;
-        else
+            cg->go = 0;
+        } else {
             cg->alpha = cg->rho / sigma;
+            cg->go = 1;
+        }
     }
 }
 
-// x += alpha p; r -= alpha q; partials of r.r
+// r -= alpha q; partials of r.r (x is updated with p in cg_rho_update_xp,
+// which reads p anyway)
 template <typename T>
-__global__ __launch_bounds__(256) void cg_update_xr(int64_t n, int64_t G, T *__restrict__ x,
-                                                    T *__restrict__ r, const T *__restrict__ p,
-                                                    const T *__restrict__ q,
-                                                    T *__restrict__ partials, const CgDev<T> *cg) {
+__global__ __launch_bounds__(256) void cg_update_r(int64_t n, int64_t G, T *__restrict__ r,
+                                                   const T *__restrict__ q,
+                                                   T *__restrict__ partials, const CgDev<T> *cg) {
     __shared__ T lds[4];
     if (cg->state != ck::RUN)
         return;
@@ -133,7 +141,6 @@ __global__ __launch_bounds__(256) void cg_update_xr(int64_t n, int64_t G, T *__r
     const int64_t b = blockIdx.x;
     T s = 0;
     for (int64_t i = b * 256 + threadIdx.x; i < n; i += G * 256) {
-        x[i] += alpha * p[i];
         const T ri = r[i] - alpha * q[i];
         r[i] = ri;
         s += ri * ri;
@@ -143,36 +150,56 @@ __global__ __launch_bounds__(256) void cg_update_xr(int64_t n, int64_t G, T *__r
         partials[b] = s;
 }
 
-// rho' = r.r; beta = rho'/rho; convergence test on sqrt(rho')/bnorm
+// The rho finish and the x and p updates in one kernel of G blocks (G = the
+// number of r.r partials): every block sums the G partials itself, in the
+// order a one-block finish would (same bits in every block), forms
+// rho' = r.r, the convergence test on sqrt(rho')/bnorm and
+// beta = rho'/rho_prev; it adds alpha p to its share of x and, unless
+// converged, sets p = r + beta p there.  Block 0 alone stores the scalars.
+// No block reads a field that block 0 stores: `go`, rho_prev and alpha were
+// set by the sigma finish.
 template <typename T>
-__global__ __launch_bounds__(256) void cg_rho_finish(int64_t G, const T *__restrict__ partials,
-                                                     CgDev<T> *cg) {
+__global__ __launch_bounds__(256) void cg_rho_update_xp(int64_t n, int64_t G,
+                                                        const T *__restrict__ partials,
+                                                        T *__restrict__ x, T *__restrict__ p,
+                                                        const T *__restrict__ r, CgDev<T> *cg) {
     __shared__ T lds[4];
-    if (cg->state != ck::RUN)
+    __shared__ T beta_s;
+    __shared__ int run_s;
+    if (!cg->go)
         return;
+    const T alpha = cg->alpha;
     const T rho_new = ck::sum_partials(partials, G, lds);
     if (threadIdx.x == 0) {
-        cg->beta = rho_new / cg->rho;
-        cg->rho = rho_new;
-        cg->iter += 1;
-        cg->relres = sqrt((double)rho_new) / cg->bnorm;
-        if (cg->relres <= cg->tol)
-            cg->state = ck::CONVERGED;
-        else if (cg->iter >= cg->max_iter)
-            cg->state = ck::BUDGET;
+        const double relres = sqrt((double)rho_new) / cg->bnorm;
+        const bool converged = relres <= cg->tol;
+        const T beta = rho_new / cg->rho_prev;
+        beta_s = beta;
+        run_s = !converged;
+        if (blockIdx.x == 0) {
+            const int iter = cg->iter + 1;
+            cg->beta = beta;
+            cg->rho = rho_new;
+            cg->iter = iter;
+            cg->relres = relres;
+            if (converged)
+                cg->state = ck::CONVERGED;
+            else if (iter >= cg->max_iter)
+                cg->state = ck::BUDGET;
+        }
     }
-}
-
-// p = r + beta p
-template <typename T>
-__global__ __launch_bounds__(256) void cg_update_p(int64_t n, T *__restrict__ p,
-                                                   const T *__restrict__ r, const CgDev<T> *cg) {
-    if (cg->state != ck::RUN)
-        return;
-    const T beta = cg->beta;
-    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * 256)
-        p[i] = r[i] + beta * p[i];
+    __syncthreads();
+    const T beta = beta_s;
+    if (run_s) {
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += G * 256) {
+            const T pi = p[i];
+            x[i] += alpha * pi;
+            p[i] = r[i] + beta * pi;
+        }
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += G * 256)
+            x[i] += alpha * p[i];
+    }
 }
 
 // ---- small elementwise helpers -----------------------------------------------
@@ -271,10 +298,9 @@ template <typename T>
 ck_status launch_cg_update(int64_t n, T *x, T *r, T *p, const T *q, T *partials, CgDev<T> *cg,
                            hipStream_t s) {
     const int64_t G = dot_blocks<T>(n);
-    hipLaunchKernelGGL((cg_update_xr<T>), dim3(G), dim3(256), 0, s, n, G, x, r, p, q, partials,
+    hipLaunchKernelGGL((cg_update_r<T>), dim3(G), dim3(256), 0, s, n, G, r, q, partials, cg);
+    hipLaunchKernelGGL((cg_rho_update_xp<T>), dim3(G), dim3(256), 0, s, n, G, partials, x, p, r,
                        cg);
-    hipLaunchKernelGGL((cg_rho_finish<T>), dim3(1), dim3(256), 0, s, G, partials, cg);
-    hipLaunchKernelGGL((cg_update_p<T>), dim3(stream_grid(n)), dim3(256), 0, s, n, p, r, cg);
     CK_HIP(hipGetLastError());
     return CK_OK;
 }

@@ -410,7 +410,10 @@ ck_status ck_config_from_id(int32_t id, ck_config *out);
 
 /* ck_kernel_name -- the device symbol of the SpMV kernel that a configuration
  * launches (for matching profiler output); fp32 selects the FP32 variant.
- * Writes a NUL-terminated string of at most cap bytes. */
+ * DIA's kernel is specialised for the matrix's diagonal count: its name ends
+ * in ", ND>", ND being 3, 5, 7, 9, 13, 15, 19 or 27, or 0 for any other
+ * count.  Writes a
+ * NUL-terminated string of at most cap bytes. */
 ck_status ck_kernel_name(const ck_config *cfg, int32_t fp32, char *buf, size_t cap);
 
 /* ck_spmv_bytes -- algorithmic bytes of one product on this matrix:

@@ -130,11 +130,14 @@ __global__ __launch_bounds__(256) void hyb_long_rows(int64_t n, const int *__res
 
 // ---- products ----------------------------------------------------------------
 
-// DIA: one lane per row, eight diagonals per step (their value loads and x
-// loads all in flight before the first use).  Diagonals past the last, and
-// columns outside [0, ncols), are masked; x[0] stands in for a masked load
-// (nd > 0 implies ncols > 0).
-template <typename T, bool BETA, bool DOT>
+// DIA: one lane per row.  ND > 0: exactly ND diagonals (the common
+// stencils and block diagonals), all value and x loads in flight before the
+// first use.  ND == 0:
+// any count, eight diagonals per step; slots past the last diagonal repeat
+// its loads (masked), which costs less than branching around them.  Columns
+// outside [0, ncols) are masked, x[0] standing in for their load (nd > 0
+// implies ncols > 0).
+template <typename T, bool BETA, bool DOT, int ND>
 __global__ __launch_bounds__(256) void spmv_dia(int n, int ncols, int64_t G, int nd,
                                                 int64_t pitch, const int *__restrict__ off,
                                                 const T *__restrict__ dv, T alpha,
@@ -151,16 +154,17 @@ __global__ __launch_bounds__(256) void spmv_dia(int n, int ncols, int64_t G, int
     for (int64_t g = b; g < groups; g += G) {
         const int64_t row = g * 256 + threadIdx.x;
         if (row < n) {
-            constexpr int S = 8;
+            constexpr int S = ND > 0 ? ND : 8;
+            const int steps = ND > 0 ? ND : nd;
             T sum = 0;
-            for (int d0 = 0; d0 < nd; d0 += S) {
+            for (int d0 = 0; d0 < steps; d0 += S) {
                 T v[S], xv[S];
                 bool ok[S];
 #pragma unroll
                 for (int u = 0; u < S; ++u) {
-                    const int d = min(d0 + u, nd - 1);
+                    const int d = ND > 0 ? u : min(d0 + u, nd - 1);
                     const int64_t j = row + off[d];
-                    ok[u] = d0 + u < nd && j >= 0 && j < ncols;
+                    ok[u] = (ND > 0 || d0 + u < nd) && j >= 0 && j < ncols;
                     v[u] = ld_stream(&dv[(int64_t)d * pitch + row]);
                     xv[u] = x[ok[u] ? j : 0];
                 }
@@ -370,9 +374,23 @@ ck_status convert_to_hyb(ck_matrix &M, hipStream_t s) {
 template <typename T, bool BETA, bool DOT>
 void launch_dia_spmv(const ck_matrix &M, int64_t G, const T *dv, const SpmvArgs<T> &a,
                      hipStream_t s) {
-    hipLaunchKernelGGL((spmv_dia<T, BETA, DOT>), dim3(xcd_grid(G)), dim3(256), 0, s, (int)M.n,
-                       (int)M.ncols, G, (int)M.dia_nd, M.dia_pitch, M.dia_off, dv, a.alpha, a.x,
-                       a.beta, a.y, a.skip, a.dot_partials);
+    const int nd = (int)M.dia_nd;
+    auto go = [&](auto kernel) {
+        hipLaunchKernelGGL(kernel, dim3(xcd_grid(G)), dim3(256), 0, s, (int)M.n, (int)M.ncols, G,
+                           nd, M.dia_pitch, M.dia_off, dv, a.alpha, a.x, a.beta, a.y, a.skip,
+                           a.dot_partials);
+    };
+    switch (nd) {   // stencils (2D: 3, 5, 9 points; 3D: 7, 13, 19, 27) and 8-wide blocks (15)
+    case 3: go(spmv_dia<T, BETA, DOT, 3>); break;
+    case 5: go(spmv_dia<T, BETA, DOT, 5>); break;
+    case 7: go(spmv_dia<T, BETA, DOT, 7>); break;
+    case 9: go(spmv_dia<T, BETA, DOT, 9>); break;
+    case 13: go(spmv_dia<T, BETA, DOT, 13>); break;
+    case 15: go(spmv_dia<T, BETA, DOT, 15>); break;
+    case 19: go(spmv_dia<T, BETA, DOT, 19>); break;
+    case 27: go(spmv_dia<T, BETA, DOT, 27>); break;
+    default: go(spmv_dia<T, BETA, DOT, 0>); break;
+    }
 }
 
 template <int L, typename T>

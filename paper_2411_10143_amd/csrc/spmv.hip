@@ -697,7 +697,7 @@ const char *kernel_name(const ck_config &c, bool fp32) {
     if (c.format == CK_FMT_ELL)
         return fp32 ? "spmv_ell<float, false, false>" : "spmv_ell<double, false, false>";
     if (c.format == CK_FMT_DIA)
-        return fp32 ? "spmv_dia<float, false, false>" : "spmv_dia<double, false, false>";
+        return fp32 ? "spmv_dia<float, false, false, ND>" : "spmv_dia<double, false, false, ND>";
     if (c.format == CK_FMT_HYB)
         return fp32 ? "spmv_hyb_ell<float, false>" : "spmv_hyb_ell<double, false>";
     if (c.format == CK_FMT_COO)

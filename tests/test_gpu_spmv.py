@@ -27,9 +27,14 @@ CASES = {
     "int_wide": lambda: M.random_integer(700, 9000, 2, density=0.01, empty_rows=0.0),
     "powerlaw": lambda: M.power_law_rows(20011, 1.6, 3),
     "banded27": lambda: M.banded_stencil(30011, 27, 4),
+    "banded9": lambda: M.banded_stencil(5003, 9, 5),
+    "banded13": lambda: M.banded_stencil(7001, 13, 6),
+    "banded19": lambda: M.banded_stencil(9001, 19, 7),
     "blockdiag": lambda: M.block_diagonal(10007, 5),
     "uniform": lambda: M.uniform_random(50003, 6),
+    "lap1d": lambda: M.laplacian_1d(5003),
     "lap2d_64": lambda: M.laplacian_2d(64),
+    "lap3d_12": lambda: M.laplacian_3d(12),
     "convdiff": lambda: M.convection_diffusion_2d(100, 10.0),
     "empty": lambda: M.from_dense(np.zeros((5, 7))),
     "one_by_one": lambda: M.from_dense(np.array([[3.0]])),
@@ -102,7 +107,8 @@ def test_spmv_all_configs_fp64(ck, orc, name):
 
 
 @pytest.mark.parametrize("name", ["int_ragged", "powerlaw", "banded27", "uniform", "empty",
-                                  "single_row"])
+                                  "single_row", "lap1d", "lap2d_64", "lap3d_12", "banded9",
+                                  "banded13", "banded19", "blockdiag"])
 def test_spmv_all_configs_fp32(ck, orc, name):
     import torch
     A = case(name)

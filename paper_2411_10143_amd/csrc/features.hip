@@ -72,6 +72,8 @@ __global__ void feat_init(FeatAcc *acc) {
 // Every pass folds its block's share in registers and LDS and writes one
 // slot of partial counts per block; feat_finish sums the slots (thousands of
 // blocks adding to the same global counters serialised at the memory side).
+// Slots are field-major (field f of block b at f * grid + b), so the finish
+// reads each field coalesced.
 constexpr int kRowFields = 21;   // sum r, sum r^2, span, max r, min r, histogram[16]
 // Rows longer than this go to the whole-workgroup passes (feat_long,
 // csr_validate_long), which take them from a list; at most nnz / 513 of them.
@@ -88,7 +90,7 @@ __global__ __launch_bounds__(256) void feat_rows(int64_t n, int64_t nnz,
                                                  const int *__restrict__ col,
                                                  unsigned long long *__restrict__ part_rows,
                                                  FeatAcc *acc, int *__restrict__ long_list) {
-    unsigned long long *slot = part_rows + (int64_t)blockIdx.x * kRowFields;
+    unsigned long long *slot = part_rows + blockIdx.x;   // field f at slot[f * gridDim.x]
     __shared__ unsigned long long h[16];
     __shared__ unsigned long long part[5][4];
     if (threadIdx.x < 16)
@@ -149,10 +151,10 @@ __global__ __launch_bounds__(256) void feat_rows(int64_t n, int64_t nnz,
             t[4] = part[4][v] < t[4] ? part[4][v] : t[4];
         }
         for (int f = 0; f < 5; ++f)
-            slot[f] = t[f];
+            slot[(int64_t)f * gridDim.x] = t[f];
     }
     if (threadIdx.x < 16)
-        slot[5 + threadIdx.x] = h[threadIdx.x];
+        slot[(int64_t)(5 + threadIdx.x) * gridDim.x] = h[threadIdx.x];
 }
 
 // Longest run of consecutive column indices in a row.  Entry k of a row
@@ -262,7 +264,7 @@ __device__ __forceinline__ void add_block_counts(unsigned long long cl, unsigned
     __syncthreads();
     if (threadIdx.x == 0) {
         slot[0] = part[0][0] + part[0][1] + part[0][2] + part[0][3];
-        slot[1] = part[1][0] + part[1][1] + part[1][2] + part[1][3];
+        slot[gridDim.x] = part[1][0] + part[1][1] + part[1][2] + part[1][3];
         if (part[2][0] + part[2][1] + part[2][2] + part[2][3])
             atomicAdd(&acc->asym, 1ull);
     }
@@ -325,7 +327,7 @@ __global__ __launch_bounds__(256) void feat_nnz(int64_t n, const int *__restrict
         if (lane == 0 && r > 0)
             cl += (unsigned long long)(st.best + 1);
     }
-    add_block_counts(cl, dcount, asym, acc, part_nnz + (int64_t)blockIdx.x * kNnzFields);
+    add_block_counts(cl, dcount, asym, acc, part_nnz + blockIdx.x);
 }
 
 // Rows longer than kLongRow (listed by feat_rows): a block runs each with
@@ -381,7 +383,7 @@ __global__ __launch_bounds__(256) void feat_long(int64_t n, const int *__restric
         if (tid == 0)
             cl += (unsigned long long)(st.best + 1);
     }
-    add_block_counts(cl, dcount, asym, acc, part_long + (int64_t)blockIdx.x * kNnzFields);
+    add_block_counts(cl, dcount, asym, acc, part_long + blockIdx.x);
 }
 
 // Counts the set flags, 16 bytes per lane (each byte is 0 or 1; bytes past
@@ -417,22 +419,23 @@ __global__ __launch_bounds__(1024) void feat_finish(FeatAcc *acc, const unsigned
     for (int f = 0; f < F; ++f)
         v[f] = f == 4 ? ~0ull : 0ull;
     for (int b = threadIdx.x; b < Gr; b += 1024) {
-        const unsigned long long *q = pr + (int64_t)b * kRowFields;
+        const unsigned long long *q = pr + b;   // field f at q[f * Gr]
         v[0] += q[0];
-        v[1] += q[1];
-        v[2] += q[2];
-        v[3] = q[3] > v[3] ? q[3] : v[3];
-        v[4] = q[4] < v[4] ? q[4] : v[4];
+        v[1] += q[Gr];
+        v[2] += q[2 * Gr];
+        v[3] = q[3 * Gr] > v[3] ? q[3 * Gr] : v[3];
+        v[4] = q[4 * Gr] < v[4] ? q[4 * Gr] : v[4];
+#pragma unroll
         for (int h = 0; h < 16; ++h)
-            v[5 + h] += q[5 + h];
+            v[5 + h] += q[(int64_t)(5 + h) * Gr];
     }
     for (int b = threadIdx.x; b < Gn; b += 1024) {
-        v[21] += pn[2 * b];
-        v[22] += pn[2 * b + 1];
+        v[21] += pn[b];
+        v[22] += pn[Gn + b];
     }
     for (int b = threadIdx.x; b < Gl; b += 1024) {
-        v[21] += pl[2 * b];
-        v[22] += pl[2 * b + 1];
+        v[21] += pl[b];
+        v[22] += pl[Gl + b];
     }
     for (int b = threadIdx.x; b < Gd; b += 1024)
         v[23] += pd[b];

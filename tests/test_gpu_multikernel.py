@@ -211,3 +211,24 @@ def test_gmres_mixed_multikernel(ck, orc, convdiff_160, mode):
     # one FP32 cycle per refinement step: the count stays near the FP64 one
     assert rm["iterations"] <= 1.5 * ref["iters"] + 30, (rm["iterations"], ref["iters"])
     Mx.close()
+
+
+@pytest.mark.parametrize("cid", [None, 11, 12])
+def test_cg_multikernel_breakdown_leaves_x(ck, orc, cid):
+    """A = -I with n > 16384 (the multi-kernel path): the first p.Ap is
+    negative, so CG stops with CK_E_BREAKDOWN before any x/p update and x is
+    still x0 (the oracle stops the same way)."""
+    n = 20000
+    A = M.CSR(n, n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32),
+              -np.ones(n), "neg_identity").check()
+    b = M.vector(n, 5)
+    x0 = M.vector(n, 6)
+    kw = {} if cid is None else {"config": ck.config_from_id(cid)}
+    say(f"cg multi-kernel breakdown config={cid}")
+    Mx = ck.Matrix.from_csr(A)
+    x, r = run(ck, ck.cg_solve, Mx, b, x0=x0, tol=1e-10, **kw)
+    assert r["status"] == ck.CK_E_BREAKDOWN, r
+    assert np.array_equal(x, x0)
+    ref = orc.cg(A, b, x0=x0, tol=1e-10)
+    assert np.array_equal(ref["x"], x0)
+    Mx.close()

@@ -215,10 +215,15 @@ __global__ __launch_bounds__(1024) void gm_finish_givens(int64_t G, const T *__r
     const int halt = st->halt, m = st->m, j = st->j;   // one round trip
     if (halt)
         return;
-    // one parallel load of the unrotated columns 0 .. j-1 for u below (each
-    // thread would otherwise wait on a chain of j global loads)
-    for (int k = threadIdx.x; k < j * (m + 1); k += 1024)
-        hr[k] = st->Hraw[k];
+    // Loads that do not depend on the partial sums are issued first, into
+    // registers, so that their latency overlaps the sums': the unrotated
+    // columns 0 .. j-1 (for u below; one entry per thread up to m = 31),
+    // the previous rotations and this column's first-pass coefficients.
+    const int t = threadIdx.x;
+    const int nh = j * (m + 1);
+    const T hr0 = t < nh ? st->Hraw[t] : T(0);
+    const T cs0 = t < j ? st->cs[t] : T(0), sn0 = t < j ? st->sn[t] : T(0);
+    const T h10 = t <= j ? st->h1[t] : T(0);
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     for (int c = w; c <= j + 1; c += 16) {
         const T *pc = partials + (int64_t)c * G;
@@ -241,13 +246,17 @@ __global__ __launch_bounds__(1024) void gm_finish_givens(int64_t G, const T *__r
             st->h2[c] = acc;   // pass 3 subtracts V h2
         }
     }
-    for (int c = threadIdx.x; c < j; c += 1024) {
-        cs[c] = st->cs[c];
-        sn[c] = st->sn[c];
+    if (t < nh)
+        hr[t] = hr0;
+    for (int k = t + 1024; k < nh; k += 1024)   // m > 31 only
+        hr[k] = st->Hraw[k];
+    if (t < j) {   // j < kMaxRestart <= 1024
+        cs[t] = cs0;
+        sn[t] = sn0;
     }
     __syncthreads();
-    for (int c = threadIdx.x; c <= j; c += 1024)
-        col[c] = st->h1[c] + h2[c];
+    if (t <= j)
+        col[t] = h10 + h2[t];
     __shared__ T hn_s;
     if (threadIdx.x == 0) {
         T proj = 0;

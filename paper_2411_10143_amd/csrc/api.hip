@@ -143,7 +143,8 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
         int *tmp = nullptr;
         CK_TRY(mat_alloc(M, &tmp, N8 + 2 + panel_scan_tmp_elems(N8), s));
         int P = P8;
-        ck_status st = panel_choose_count(M, tmp, s, &P);
+        bool counted = false;
+        ck_status st = panel_choose_count(M, tmp, s, &P, &counted);
         const int64_t W = ceil_div(std::max<int64_t>(M.ncols, 1), P);
         const int64_t N = (int64_t)P * M.n;
         if (st == CK_OK)
@@ -156,7 +157,7 @@ ck_status convert_format(ck_matrix &M, const ck_config &c, hipStream_t s) {
             st = mat_alloc(M, &M.panel_val32, M.nnz, s);
         if (st == CK_OK)
             st = launch_to_panel(M, P, W, tmp, tmp + N, M.panel_rp, M.panel_col, M.panel_val,
-                                 M.panel_val32, s);
+                                 M.panel_val32, counted, s);
         M.panel_P = P;
         M.panel_W = W;
         M.panel_rows = N;

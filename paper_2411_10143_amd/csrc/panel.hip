@@ -43,12 +43,17 @@ __global__ __launch_bounds__(256) void panel_count(int64_t n, int P, int64_t W,
 }
 
 // Panel-major copy: row i's panel-p entries go to prp[p*n + i] onwards.
-// Eight lanes per row, lane l taking panels l, l + 8, ... (any P): a row's entries
-// of consecutive panels are consecutive (columns are sorted), so an
-// exclusive sum of the eight segment lengths gives each lane the start of its
-// segment, and the eight lanes read the row as one contiguous run.
+// Eight lanes per row.  For panels p0 .. p0 + 7, lane l holds panel p0 + l's
+// destination and length; an exclusive sum over the eight lengths gives each
+// panel's first entry within the row (columns are sorted, so a row's entries
+// of consecutive panels are consecutive).  The eight lanes then copy the
+// row's entries of those panels together, lane l taking entries l, l + 8, ...
+// (coalesced loads): an entry's panel is its column / W, and the lane holding
+// that panel supplies the destination by a shuffle.  Every lane of a row runs
+// the same number of steps, so the shuffles always read active lanes.
 template <bool F32>
-__global__ __launch_bounds__(256) void panel_fill(int64_t n, int P, const int *__restrict__ rp,
+__global__ __launch_bounds__(256) void panel_fill(int64_t n, int P, int W,
+                                                  const int *__restrict__ rp,
                                                   const int *__restrict__ col,
                                                   const double *__restrict__ val,
                                                   const int *__restrict__ prp,
@@ -75,12 +80,21 @@ __global__ __launch_bounds__(256) void panel_fill(int64_t n, int P, const int *_
         }
         const int total = __shfl(ex, L - 1, L);
         ex -= len;
-        const int src = base + ex;
-        for (int t = 0; t < len; ++t) {
-            pcol[dst0 + t] = col[src + t];
-            pval[dst0 + t] = val[src + t];
-            if (F32)
-                pval32[dst0 + t] = (float)val[src + t];
+        for (int k0 = 0; k0 < total; k0 += L) {
+            const int k = k0 + lane;
+            const bool in = k < total;
+            const int c = in ? col[base + k] : p0 * W;
+            const int q = c / W - p0;   // 0 <= q < 8 for the row's entries of these panels
+            const int d0 = __shfl(dst0, q, L);
+            const int e0 = __shfl(ex, q, L);
+            if (in) {
+                const int dst = d0 + (k - e0);
+                const double v = val[base + k];
+                pcol[dst] = c;
+                pval[dst] = v;
+                if (F32)
+                    pval32[dst] = (float)v;
+            }
         }
         base += total;
     }
@@ -295,9 +309,11 @@ constexpr int64_t kSliceP4 = 5 * (int64_t(1) << 19);   // 2.5 MB
 
 ck_status launch_row_max(int64_t n, const int *rp, unsigned long long *out, hipStream_t s);
 
-ck_status panel_choose_count(const ck_matrix &M, int *tmp, hipStream_t s, int *P_out) {
+ck_status panel_choose_count(const ck_matrix &M, int *tmp, hipStream_t s, int *P_out,
+                             bool *counted) {
     const int P8 = panel_count_for(M.ncols, 8);
     *P_out = P8;
+    *counted = false;
     if (P8 != 8 || M.n == 0 || M.ncols * 8 > 4 * kSliceP4)
         return CK_OK;
     // the longest row (known after the feature pass; else one pass over rowptr)
@@ -327,8 +343,10 @@ ck_status panel_choose_count(const ck_matrix &M, int *tmp, hipStream_t s, int *P
     unsigned long long ne = 0;
     CK_HIP(hipMemcpyAsync(&ne, total, sizeof ne, hipMemcpyDeviceToHost, s));
     CK_HIP(hipStreamSynchronize(s));
-    if (4 * (int64_t)ne > 3 * N4)   // the P = 4 layout would be dense
+    if (4 * (int64_t)ne > 3 * N4) {   // the P = 4 layout would be dense
         *P_out = 4;
+        *counted = true;              // tmp[0 .. 4n) holds its counts
+    }
     return CK_OK;
 }
 
@@ -358,17 +376,19 @@ ck_status launch_scan_exclusive(int64_t N, const int *in, int *out, int *tmp, hi
 }
 
 ck_status launch_to_panel(const ck_matrix &M, int P, int64_t W, int *cnt, int *tmp, int *prp,
-                          int *pcol, double *pval, float *pval32, hipStream_t s) {
+                          int *pcol, double *pval, float *pval32, bool counted, hipStream_t s) {
     const int64_t g = ceil_div(M.n, 256);
-    hipLaunchKernelGGL(panel_count, dim3(g), dim3(256), 0, s, M.n, P, W, M.rp, M.col, cnt);
+    if (!counted)   // else cnt already holds this P's counts (panel_choose_count)
+        hipLaunchKernelGGL(panel_count, dim3(g), dim3(256), 0, s, M.n, P, W, M.rp, M.col, cnt);
     CK_TRY(launch_scan_exclusive((int64_t)P * M.n, cnt, prp, tmp, s));
     const int64_t g8 = ceil_div(M.n, 256 / 8);
+    const int Wi = (int)W;   // W <= ncols < 2^31
     if (pval32)
-        hipLaunchKernelGGL((panel_fill<true>), dim3(g8), dim3(256), 0, s, M.n, P, M.rp, M.col,
-                           M.val, prp, pcol, pval, pval32);
+        hipLaunchKernelGGL((panel_fill<true>), dim3(g8), dim3(256), 0, s, M.n, P, Wi, M.rp,
+                           M.col, M.val, prp, pcol, pval, pval32);
     else
-        hipLaunchKernelGGL((panel_fill<false>), dim3(g8), dim3(256), 0, s, M.n, P, M.rp, M.col,
-                           M.val, prp, pcol, pval, pval32);
+        hipLaunchKernelGGL((panel_fill<false>), dim3(g8), dim3(256), 0, s, M.n, P, Wi, M.rp,
+                           M.col, M.val, prp, pcol, pval, pval32);
     CK_HIP(hipGetLastError());
     return CK_OK;
 }

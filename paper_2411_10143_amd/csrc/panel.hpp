@@ -11,13 +11,15 @@ int panel_count_for(int64_t ncols, int value_bytes);
 int64_t panel_scan_tmp_elems(int64_t N);
 // The panel count of M's CSR-panel copy: panel_count_for(ncols, 8), or 4
 // (see panel.hip).  tmp: scratch of at least panel_count_for(ncols, 8) * n
-// + 2 ints; returns when decided.
-ck_status panel_choose_count(const ck_matrix &M, int *tmp, hipStream_t s, int *P_out);
+// + 2 ints; returns when decided.  *counted: tmp[0 .. P n) already holds the
+// chosen P's per-row panel counts (true when P = 4 was chosen).
+ck_status panel_choose_count(const ck_matrix &M, int *tmp, hipStream_t s, int *P_out,
+                             bool *counted);
 // Exclusive scan of N ints into N + 1 outputs (out[N] = total); tmp holds
 // panel_scan_tmp_elems(N) ints.
 ck_status launch_scan_exclusive(int64_t N, const int *in, int *out, int *tmp, hipStream_t s);
 ck_status launch_to_panel(const ck_matrix &M, int P, int64_t W, int *cnt, int *tmp, int *prp,
-                          int *pcol, double *pval, float *pval32, hipStream_t s);
+                          int *pcol, double *pval, float *pval32, bool counted, hipStream_t s);
 // After launch_to_panel (cnt = its per-panel-row counts, M.panel_rp the
 // dense row pointers): switch M to the row-list layout when at most 3/4 of
 // the P*n panel rows are non-empty (cnt is overwritten).  Returns when done.

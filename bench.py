@@ -6,8 +6,9 @@ families x twelve sizes, n = 1e4 .. 2e6).  One step runs the method's whole
 SpMV path on every matrix: ingest (copy + validate), GPU features, cascaded
 prediction, format conversion when the prediction asks for it, then 200
 products with the predicted kernel (the paper times configurations as the
-mean of 200 runs).  value = algorithmic bytes of all those products / step
-time, in GB/s.
+mean of 200 runs).  The next matrix is prepared on a second stream while the
+current one's products run; the sequential step is reported beside it.
+value = algorithmic bytes of all those products / step time, in GB/s.
 
 Untimed, the same run measures every configuration on every matrix (warm,
 200 products each) to report predicted vs exhaustive-best vs default CSR-vector,
@@ -154,28 +155,56 @@ def bench_spmv_set(args):
 
     # ---- timed steps: ingest -> features -> select -> convert -> R products ---
     # every device block of the step's handles from torch's caching allocator
-    # (the binding's default), or from the library's own cache
+    # (the binding's default), or from the library's own cache.  Pipelined
+    # (the default): a worker thread prepares matrix m + 1 (ingest, features,
+    # cascade, conversion) on a second stream while matrix m's products run
+    # on the main stream -- the paper's overlap of preprocessing with
+    # execution, across the batch.  Sequential: the same calls one after the
+    # other on the main stream.
+    from concurrent.futures import ThreadPoolExecutor
     alloc = None if args.allocator == "library" else "torch"
     phase_ms = dict(ingest=0.0, features=0.0, select=0.0, convert=0.0, products=0.0,
-                    release=0.0)
+                    release=0.0, exposed_prep=0.0)
+    side = torch.cuda.Stream()          # default priority
+    pool = ThreadPoolExecutor(max_workers=1)
 
-    def one_step(record):
+    def prepare(m, stream):
+        A, d = mats[m], dev[m]
+        clk = time.perf_counter
+        t0 = clk()
+        Mx = ck.Matrix(d["rp"], d["col"], d["val"], A.ncols, stream=stream, allocator=alloc)
+        t1 = clk()
+        F = ck.spmv_features(Mx.handle, stream=stream, symmetry=False)   # the cascade's inputs
+        t2 = clk()
+        cfg = ck.spmv_select(F)
+        t3 = clk()
+        try:
+            ck.spmv_convert(Mx.handle, cfg, stream=stream)
+        except ck.CkError as e:
+            if e.status != ck.CK_E_UNSUPPORTED:
+                raise
+            cfg = ck.default_config(Mx.handle)   # refused conversion: keep the default
+        if stream is not None:
+            stream.synchronize()             # all the products read is complete
+        t4 = clk()
+        return Mx, cfg, (t0, t1, t2, t3, t4)
+
+    def prepare_side(m):
+        with torch.cuda.stream(side):
+            return prepare(m, side)
+
+    def one_step(record, pipelined=True):
         picks, spmv_us = [], 0.0
         clk = time.perf_counter
+        fut = pool.submit(prepare_side, 0) if pipelined else None
         for m, (A, d) in enumerate(zip(mats, dev)):
-            t0 = clk()
-            Mx = ck.Matrix(d["rp"], d["col"], d["val"], A.ncols, allocator=alloc)
-            t1 = clk()
-            F = ck.spmv_features(Mx.handle, symmetry=False)   # the cascade's inputs only
-            t2 = clk()
-            cfg = ck.spmv_select(F)
-            t3 = clk()
-            try:
-                ck.spmv_convert(Mx.handle, cfg)
-            except ck.CkError as e:
-                if e.status != ck.CK_E_UNSUPPORTED:
-                    raise
-                cfg = ck.default_config(Mx.handle)   # refused conversion: keep the default
+            tw = clk()
+            if pipelined:
+                Mx, cfg, tp = fut.result()
+                if m + 1 < len(mats):
+                    fut = pool.submit(prepare_side, m + 1)
+            else:
+                Mx, cfg, tp = prepare(m, None)
             t4 = clk()
             us = ck.time_spmv(Mx.handle, cfg, d["x"], d["y"], warmup=0, reps=R)
             t5 = clk()
@@ -185,9 +214,11 @@ def bench_spmv_set(args):
             picks.append(ck.config_id(cfg))
             Mx.close()
             t6 = clk()
-            if record:   # host wall time per phase (asynchronous work lands in the next blocking call)
-                for k, a, b in (("ingest", t0, t1), ("features", t1, t2), ("select", t2, t3),
-                                ("convert", t3, t4), ("products", t4, t5), ("release", t5, t6)):
+            if record:   # host wall time per phase (the preparation overlaps when pipelined)
+                for k, a, b in (("ingest", tp[0], tp[1]), ("features", tp[1], tp[2]),
+                                ("select", tp[2], tp[3]), ("convert", tp[3], tp[4]),
+                                ("products", t4, t5), ("release", t5, t6),
+                                ("exposed_prep", tw, t4)):
                     phase_ms[k] += (b - a) * 1e3
         return picks, spmv_us
 
@@ -203,6 +234,15 @@ def bench_spmv_set(args):
         step_times.append(time.perf_counter() - ts)
         spmv_totals.append(spmv_us)
         log(f"[step {s + 1}/{args.steps}] {step_times[-1] * 1e3:.1f} ms")
+    # the same step without the overlap, for comparison (not the bench value)
+    seq_times = []
+    for s in range(max(2, args.steps // 4)):
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        one_step(False, pipelined=False)
+        torch.cuda.synchronize()
+        seq_times.append(time.perf_counter() - ts)
+    pool.shutdown()
     bytes_step = R * sum(nbytes)
     value = bytes_step * len(step_times) / sum(step_times) / 1e9
 
@@ -285,7 +325,8 @@ def bench_spmv_set(args):
         "data": "synthetic",
         "config": {"workload": f"spmv_set_{len(mats)}: banded/power-law/block-diagonal/"
                                f"uniform-random FP64, n 1e4-2e6, int32 CSR; per matrix ingest + "
-                               f"GPU features + cascade + conversion + {R} products",
+                               f"GPU features + cascade + conversion + {R} products, the next "
+                               f"matrix prepared on a second stream during the products",
                    "matrices": len(mats), "products_per_matrix": R,
                    "algorithmic_GB_per_step": round(bytes_step / 1e9, 3)},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(ks["achieved_GBs"], 1),
@@ -297,6 +338,9 @@ def bench_spmv_set(args):
         "spmv": {
             "kernel_GBs_in_steps": round(bytes_step / (np.mean(spmv_totals) * 1e3), 1),
             "step_phase_ms": {k: round(v / len(step_times), 2) for k, v in phase_ms.items()},
+            "sequential_step": {"GBs": round(R * sum(nbytes) * len(seq_times) / sum(seq_times) / 1e9, 1),
+                                "ms_per_step": round(1e3 * sum(seq_times) / len(seq_times), 3),
+                                "steps": len(seq_times)},
             "copy_GBs": round(copy_gbs, 1),
             "kernels_in_steps": {k: dict(launches=v[0], avg_us=round(v[1] / v[0], 3))
                                  for k, v in sorted(ledger.k.items())},

@@ -45,8 +45,12 @@ struct WgCgOut {
     int status, iter, restarts, pad;
     double relres;   // true relative residual at exit
 };
+// Rows of at most this many entries are copied column-major once per solve
+// into ccol / cval (kWgCgColMajorK * kWgCgMaxN entries each).
+constexpr int kWgCgColMajorK = 16;
 ck_status launch_cg_wg(int n, const int *rp, const int *col, const double *val, const double *b,
-                       double *x, double tol, int max_iter, WgCgOut *out, hipStream_t s);
+                       double *x, double tol, int max_iter, int *ccol, double *cval,
+                       WgCgOut *out, hipStream_t s);
 
 // elements (of the inner type) of a slot's `work`
 int64_t bslot_work_elems(int kind, int64_t n, int m);

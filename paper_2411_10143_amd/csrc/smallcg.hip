@@ -5,9 +5,13 @@
 // solve in one launch: thread t owns rows t, t + 1024, ... (R <= 4 of them);
 // x, r, p and q of its rows live in registers, p also in LDS (the product
 // gathers it from there), and only the matrix (L2-resident after the first
-// step) and, at the rare residual steps, b are read from memory.  The product
-// sums each row with one lane in ascending entry order; the loads of all R
-// rows' next entries are issued together.  Dot products reduce in a fixed
+// step) and, at the rare residual steps, b are read from memory.  When no
+// row has more than 16 entries the matrix is first copied column-major into
+// a scratch buffer, so that each product reads it in whole cache lines (the
+// row-major arrays, read one entry per lane per step, re-fetched partly used
+// lines at every step).  The product sums each row with one lane in
+// ascending entry order; the loads of all R rows' next entries are issued
+// together.  Dot products reduce in a fixed
 // order (wave butterfly, then the 16 wave sums in order), so the result is
 // deterministic.  (Eight rows per thread would spill registers.)
 //
@@ -70,20 +74,57 @@ __device__ __forceinline__ void wg_matvec(const int (&kb)[R], const int (&ke)[R]
     }
 }
 
+// The same product from the column-major copy (slot s of local row i at
+// s * RW + i): a step's loads are consecutive across the lanes, so each
+// iteration reads the matrix once, whole cache lines, instead of re-fetching
+// partly used lines of the row-major arrays at every step.  Entries are
+// summed in the same order, so the result is the same.
+template <int R>
+__device__ __forceinline__ void wg_matvec_cm(const int (&len)[R], int K,
+                                             const int *__restrict__ ccol,
+                                             const double *__restrict__ cval, const double *v,
+                                             double (&q)[R]) {
+    constexpr int RW = R * kWgThreads;
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+        q[u] = 0;
+    for (int s = 0; s < K; ++s) {
+        int cc[R];
+        double vv[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const int i = threadIdx.x + u * kWgThreads;
+            cc[u] = ccol[s * RW + i];
+            vv[u] = cval[s * RW + i];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+            if (s < len[u])
+                q[u] += vv[u] * v[cc[u]];
+    }
+}
+
 }  // namespace
 
+// ccol / cval: scratch of kWgCgColMajorK * R * 1024 entries for the
+// column-major copy, used when no row has more than kWgCgColMajorK entries.
 template <int R>
 __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict__ rp,
                                                     const int *__restrict__ col,
                                                     const double *__restrict__ val,
                                                     const double *__restrict__ b,
                                                     double *__restrict__ x, double tol,
-                                                    int max_iter, ck::WgCgOut *out) {
+                                                    int max_iter, int *__restrict__ ccol,
+                                                    double *__restrict__ cval,
+                                                    ck::WgCgOut *out) {
+    constexpr int RW = R * kWgThreads;
     __shared__ double v[kWgThreads * R];   // p (or x while forming the residual)
     __shared__ double red[2 * kWgWaves];
+    __shared__ int kmax[kWgWaves];
     int parity = 0;
     const int t = threadIdx.x;
-    int kb[R], ke[R];
+    int kb[R], ke[R], len[R];
     double xr[R], rr[R], pr[R], q[R];
     int trips = 0;
     double bb = 0;
@@ -93,10 +134,39 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
         const bool in = i < n;
         kb[u] = in ? rp[i] : 0;
         ke[u] = in ? rp[i + 1] : 0;
+        len[u] = ke[u] - kb[u];
         const double bi = in ? b[i] : 0.0;
         xr[u] = in ? x[i] : 0.0;
         trips = max(trips, ke[u] - kb[u]);
         bb += bi * bi;
+    }
+    // longest row of the system; at most kWgCgColMajorK entries: build the
+    // column-major copy (once per solve) and run every product from it
+    int K = trips;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        K = max(K, __shfl_xor(K, off, 64));
+    if ((t & 63) == 0)
+        kmax[t >> 6] = K;
+    __syncthreads();
+    K = 0;
+#pragma unroll
+    for (int w = 0; w < kWgWaves; ++w)
+        K = max(K, kmax[w]);
+    const bool cm = K <= ck::kWgCgColMajorK;
+    if (cm) {
+        for (int s = 0; s < K; ++s) {
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                const int i = t + u * kWgThreads;
+                const bool in = s < len[u];   // rows past n have len 0
+                ccol[s * RW + i] = in ? col[kb[u] + s] : 0;
+                cval[s * RW + i] = in ? val[kb[u] + s] : 0.0;
+            }
+        }
+        // the copy is read by other waves of this workgroup: the barrier
+        // below (in the first workgroup sum) orders it
+        __threadfence_block();
     }
     const double bnorm = sqrt(wg_sum_1024(bb, red, parity));
     int status = ck::BUDGET, iters = 0, restarts = 0;
@@ -114,7 +184,10 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
                 if (t + u * kWgThreads < n)
                     v[t + u * kWgThreads] = xr[u];
             __syncthreads();
-            wg_matvec<R>(kb, ke, trips, col, val, v, q);
+            if (cm)
+                wg_matvec_cm<R>(len, K, ccol, cval, v, q);
+            else
+                wg_matvec<R>(kb, ke, trips, col, val, v, q);
             double rho = 0;
 #pragma unroll
             for (int u = 0; u < R; ++u) {
@@ -140,7 +213,10 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
                     if (t + u * kWgThreads < n)
                         v[t + u * kWgThreads] = pr[u];
                 __syncthreads();
-                wg_matvec<R>(kb, ke, trips, col, val, v, q);
+                if (cm)
+                    wg_matvec_cm<R>(len, K, ccol, cval, v, q);
+                else
+                    wg_matvec<R>(kb, ke, trips, col, val, v, q);
                 double pq = 0;
 #pragma unroll
                 for (int u = 0; u < R; ++u)
@@ -180,7 +256,10 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
                 if (t + u * kWgThreads < n)
                     v[t + u * kWgThreads] = xr[u];
             __syncthreads();
-            wg_matvec<R>(kb, ke, trips, col, val, v, q);
+            if (cm)
+                wg_matvec_cm<R>(len, K, ccol, cval, v, q);
+            else
+                wg_matvec<R>(kb, ke, trips, col, val, v, q);
             double tr = 0;
 #pragma unroll
             for (int u = 0; u < R; ++u) {
@@ -216,16 +295,20 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
 namespace ck {
 
 ck_status launch_cg_wg(int n, const int *rp, const int *col, const double *val, const double *b,
-                       double *x, double tol, int max_iter, WgCgOut *out, hipStream_t s) {
+                       double *x, double tol, int max_iter, int *ccol, double *cval,
+                       WgCgOut *out, hipStream_t s) {
     if (n < 1 || n > kWgCgMaxN)
         return fail(CK_E_INVALID, "single-workgroup CG takes 1..%d rows, got %d", kWgCgMaxN, n);
     const dim3 grid(1), block(kWgThreads);
     if (n <= kWgThreads)
-        hipLaunchKernelGGL((cg_wg<1>), grid, block, 0, s, n, rp, col, val, b, x, tol, max_iter, out);
+        hipLaunchKernelGGL((cg_wg<1>), grid, block, 0, s, n, rp, col, val, b, x, tol, max_iter,
+                           ccol, cval, out);
     else if (n <= 2 * kWgThreads)
-        hipLaunchKernelGGL((cg_wg<2>), grid, block, 0, s, n, rp, col, val, b, x, tol, max_iter, out);
+        hipLaunchKernelGGL((cg_wg<2>), grid, block, 0, s, n, rp, col, val, b, x, tol, max_iter,
+                           ccol, cval, out);
     else
-        hipLaunchKernelGGL((cg_wg<4>), grid, block, 0, s, n, rp, col, val, b, x, tol, max_iter, out);
+        hipLaunchKernelGGL((cg_wg<4>), grid, block, 0, s, n, rp, col, val, b, x, tol, max_iter,
+                           ccol, cval, out);
     CK_HIP(hipGetLastError());
     return CK_OK;
 }

@@ -744,9 +744,14 @@ constexpr int64_t kSmallN = 16384;
 ck_status wg_cg_solve(SolveCtx &c, const double *b, double *x) {
     Workspace ws(c.M, c.s);
     WgCgOut *out;
+    int *ccol;
+    double *cval;
     CK_TRY(ws.get(&out, 1));
+    CK_TRY(ws.get(&ccol, (int64_t)kWgCgColMajorK * kWgCgMaxN));
+    CK_TRY(ws.get(&cval, (int64_t)kWgCgColMajorK * kWgCgMaxN));
     const int max_iter = c.o.max_iter > 0 ? c.o.max_iter : 100000;
-    CK_TRY(launch_cg_wg((int)c.M.n, c.M.rp, c.M.col, c.M.val, b, x, c.o.tol, max_iter, out, c.s));
+    CK_TRY(launch_cg_wg((int)c.M.n, c.M.rp, c.M.col, c.M.val, b, x, c.o.tol, max_iter, ccol, cval,
+                        out, c.s));
     WgCgOut h{};
     CK_HIP(hipMemcpyAsync(&h, out, sizeof h, hipMemcpyDeviceToHost, c.s));
     CK_HIP(hipStreamSynchronize(c.s));

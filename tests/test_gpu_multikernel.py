@@ -213,6 +213,23 @@ def test_gmres_mixed_multikernel(ck, orc, convdiff_160, mode):
     Mx.close()
 
 
+def test_gmres_mixed_odd_rows(ck, orc):
+    """Mixed GMRES at an odd n > 16384 (the multi-kernel path, the basis
+    columns padded past n): true residual within 1e-10 by the oracle."""
+    A = M.convection_diffusion_2d(131, 10.0)      # n = 17,161
+    assert A.n % 2 == 1 and A.n > 16384
+    xs, b = problem(orc, A, 33)
+    Mx = ck.Matrix.from_csr(A, keep_fp32=True)
+    say("gmres mixed multi-kernel convdiff_131 (odd n)")
+    xm, rm = run(ck, ck.gmres_solve, Mx, b, tol=1e-10, precision=ck.CK_PREC_MIXED)
+    assert rm["status"] == ck.CK_OK, rm
+    rr = orc.relres(A, b, xm)
+    assert rr <= 1e-10 and abs(rr - rm["true_relres"]) <= 1e-3 * rr
+    ref = orc.gmres(A, b, m=30, tol=1e-10)
+    assert rm["iterations"] <= 1.5 * ref["iters"] + 30, (rm["iterations"], ref["iters"])
+    Mx.close()
+
+
 @pytest.mark.parametrize("cid", [None, 11, 12])
 def test_cg_multikernel_breakdown_leaves_x(ck, orc, cid):
     """A = -I with n > 16384 (the multi-kernel path): the first p.Ap is

@@ -45,11 +45,12 @@ struct WgCgOut {
     int status, iter, restarts, pad;
     double relres;   // true relative residual at exit
 };
-// Rows of at most this many entries are copied column-major once per solve
-// into ccol / cval (kWgCgColMajorK * kWgCgMaxN entries each).
+// Rows of at most this many entries (even) are copied column-major once per
+// solve into cm_col / cm_val: kWgCgColMajorK * kWgCgMaxN ints and doubles,
+// 16-byte aligned.
 constexpr int kWgCgColMajorK = 16;
 ck_status launch_cg_wg(int n, const int *rp, const int *col, const double *val, const double *b,
-                       double *x, double tol, int max_iter, int *ccol, double *cval,
+                       double *x, double tol, int max_iter, void *cm_col, void *cm_val,
                        WgCgOut *out, hipStream_t s);
 
 // elements (of the inner type) of a slot's `work`

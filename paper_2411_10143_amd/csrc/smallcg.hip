@@ -74,40 +74,45 @@ __device__ __forceinline__ void wg_matvec(const int (&kb)[R], const int (&ke)[R]
     }
 }
 
-// The same product from the column-major copy (slot s of local row i at
-// s * RW + i): a step's loads are consecutive across the lanes, so each
-// iteration reads the matrix once, whole cache lines, instead of re-fetching
-// partly used lines of the row-major arrays at every step.  Entries are
-// summed in the same order, so the result is the same.
+// The same product from the column-major copy, slots in pairs: slots 2q and
+// 2q + 1 of local row i are the int2 / double2 at q * RW + i.  A step's loads
+// are consecutive across the lanes and bring two slots of every row, so each
+// product reads the matrix once, in whole cache lines, in ceil(K / 2) rounds
+// (the row-major arrays, read one entry per lane per step, re-fetched partly
+// used lines at every step).  Entries are summed in the same order, so the
+// result is the same.
 template <int R>
 __device__ __forceinline__ void wg_matvec_cm(const int (&len)[R], int K,
-                                             const int *__restrict__ ccol,
-                                             const double *__restrict__ cval, const double *v,
+                                             const int2 *__restrict__ ccol,
+                                             const double2 *__restrict__ cval, const double *v,
                                              double (&q)[R]) {
     constexpr int RW = R * kWgThreads;
 #pragma unroll
     for (int u = 0; u < R; ++u)
         q[u] = 0;
-    for (int s = 0; s < K; ++s) {
-        int cc[R];
-        double vv[R];
+    for (int s = 0; s < K; s += 2) {
+        int2 cc[R];
+        double2 vv[R];
 #pragma unroll
         for (int u = 0; u < R; ++u) {
             const int i = threadIdx.x + u * kWgThreads;
-            cc[u] = ccol[s * RW + i];
-            vv[u] = cval[s * RW + i];
+            cc[u] = ccol[(s >> 1) * RW + i];
+            vv[u] = cval[(s >> 1) * RW + i];
         }
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int u = 0; u < R; ++u)
+        for (int u = 0; u < R; ++u) {
             if (s < len[u])
-                q[u] += vv[u] * v[cc[u]];
+                q[u] += vv[u].x * v[cc[u].x];
+            if (s + 1 < len[u])
+                q[u] += vv[u].y * v[cc[u].y];
+        }
     }
 }
 
 }  // namespace
 
-// ccol / cval: scratch of kWgCgColMajorK * R * 1024 entries for the
+// ccol / cval: scratch of kWgCgColMajorK / 2 * R * 1024 pairs for the
 // column-major copy, used when no row has more than kWgCgColMajorK entries.
 template <int R>
 __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict__ rp,
@@ -115,8 +120,8 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
                                                     const double *__restrict__ val,
                                                     const double *__restrict__ b,
                                                     double *__restrict__ x, double tol,
-                                                    int max_iter, int *__restrict__ ccol,
-                                                    double *__restrict__ cval,
+                                                    int max_iter, int2 *__restrict__ ccol,
+                                                    double2 *__restrict__ cval,
                                                     ck::WgCgOut *out) {
     constexpr int RW = R * kWgThreads;
     __shared__ double v[kWgThreads * R];   // p (or x while forming the residual)
@@ -155,13 +160,15 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
         K = max(K, kmax[w]);
     const bool cm = K <= ck::kWgCgColMajorK;
     if (cm) {
-        for (int s = 0; s < K; ++s) {
+        for (int s = 0; s < K; s += 2) {
 #pragma unroll
             for (int u = 0; u < R; ++u) {
                 const int i = t + u * kWgThreads;
-                const bool in = s < len[u];   // rows past n have len 0
-                ccol[s * RW + i] = in ? col[kb[u] + s] : 0;
-                cval[s * RW + i] = in ? val[kb[u] + s] : 0.0;
+                const bool in0 = s < len[u], in1 = s + 1 < len[u];   // rows past n: len 0
+                ccol[(s >> 1) * RW + i] = make_int2(in0 ? col[kb[u] + s] : 0,
+                                                    in1 ? col[kb[u] + s + 1] : 0);
+                cval[(s >> 1) * RW + i] = make_double2(in0 ? val[kb[u] + s] : 0.0,
+                                                       in1 ? val[kb[u] + s + 1] : 0.0);
             }
         }
         // the copy is read by other waves of this workgroup: the barrier
@@ -295,8 +302,10 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
 namespace ck {
 
 ck_status launch_cg_wg(int n, const int *rp, const int *col, const double *val, const double *b,
-                       double *x, double tol, int max_iter, int *ccol, double *cval,
+                       double *x, double tol, int max_iter, void *cm_col, void *cm_val,
                        WgCgOut *out, hipStream_t s) {
+    int2 *ccol = (int2 *)cm_col;
+    double2 *cval = (double2 *)cm_val;
     if (n < 1 || n > kWgCgMaxN)
         return fail(CK_E_INVALID, "single-workgroup CG takes 1..%d rows, got %d", kWgCgMaxN, n);
     const dim3 grid(1), block(kWgThreads);

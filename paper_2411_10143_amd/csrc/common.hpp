@@ -61,6 +61,41 @@ __device__ __forceinline__ T wave_sum(T v) {
     return v;
 }
 
+// v moved across lanes by the DPP control CTRL (row_mask RM, bank_mask BM);
+// lanes with no source, or masked out, read 0.  A double moves as its two
+// 32-bit halves.
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ double dpp_read(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int l = __builtin_amdgcn_update_dpp(0, lo, CTRL, RM, BM, true);
+    const int h = __builtin_amdgcn_update_dpp(0, hi, CTRL, RM, BM, true);
+    return __hiloint2double(h, l);
+}
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ float dpp_read(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RM, BM, true));
+}
+
+// Sum over the 64 lanes of a wave, valid in lane 63 only, by data-parallel-
+// primitive moves between registers (no LDS permute, so a step costs a few
+// cycles instead of an LDS round trip): within each row of 16 lanes, lane i
+// adds lanes i-1, i-2, i-3 (row_shr 1..3), then lane i-4 (row_shr 4, lanes
+// 4..15) and lane i-8 (row_shr 8, lanes 8..15), so lane 15 of each row holds
+// the row's sum; rows 1 and 3 then add lane 15 of the row before (row_bcast
+// 15), and rows 2 and 3 add lane 31 (row_bcast 31).  Fixed order:
+// deterministic.
+template <typename T>
+__device__ __forceinline__ T wave_sum_last(T v) {
+    T t = v + dpp_read<0x111, 0xf, 0xf>(v);
+    t += dpp_read<0x112, 0xf, 0xf>(v);
+    t += dpp_read<0x113, 0xf, 0xf>(v);
+    t += dpp_read<0x114, 0xf, 0xe>(t);
+    t += dpp_read<0x118, 0xf, 0xc>(t);
+    t += dpp_read<0x142, 0xa, 0xf>(t);
+    t += dpp_read<0x143, 0xc, 0xf>(t);
+    return t;
+}
+
 // Sum over groups of L consecutive lanes (L a power of two <= 64); every lane
 // of a group ends with the group total.  Fixed butterfly order: deterministic.
 template <int L, typename T>

@@ -40,7 +40,9 @@ namespace {
 // before it.
 __device__ __forceinline__ int64_t clampc(int c, int ncols) { return c < ncols ? c : ncols - 1; }
 
-// partials[c*G + b] = block b's sum of acc[c]  (c < ncols)
+// partials[c*G + b] = block b's sum of acc[c]  (c < ncols).  The NC wave
+// sums run back to back at the end of the pass, so they use register-to-
+// register (DPP) moves, valid in lane 63.
 template <typename T, int NC>
 __device__ __forceinline__ void block_cols(const T (&acc)[NC], int ncols, T *partials, int64_t b,
                                            int64_t G) {
@@ -49,8 +51,8 @@ __device__ __forceinline__ void block_cols(const T (&acc)[NC], int ncols, T *par
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         if (c < ncols) {
-            const T v = ck::wave_sum(acc[c]);
-            if (lane == 0)
+            const T v = ck::wave_sum_last(acc[c]);
+            if (lane == 63)
                 lds[w][c] = v;
         }
     }
@@ -240,8 +242,8 @@ __global__ __launch_bounds__(1024) void gm_finish_givens(int64_t G, const T *__r
                 if (b0 + 64 * u < G)
                     acc += v[u];
         }
-        acc = ck::wave_sum(acc);
-        if (lane == 0) {
+        acc = ck::wave_sum_last(acc);   // valid in lane 63
+        if (lane == 63) {
             h2[c] = acc;
             st->h2[c] = acc;   // pass 3 subtracts V h2
         }

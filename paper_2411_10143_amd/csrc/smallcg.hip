@@ -27,35 +27,6 @@ namespace {
 constexpr int kWgThreads = 1024;
 constexpr int kWgWaves = kWgThreads / 64;
 
-// v shifted across lanes by the DPP control CTRL (row_mask RM, bank_mask
-// BM); lanes with no source, or masked out, read 0.  A double moves as its
-// two 32-bit halves.
-template <int CTRL, int RM, int BM>
-__device__ __forceinline__ double dpp_read(double v) {
-    const int lo = __double2loint(v), hi = __double2hiint(v);
-    const int l = __builtin_amdgcn_update_dpp(0, lo, CTRL, RM, BM, true);
-    const int h = __builtin_amdgcn_update_dpp(0, hi, CTRL, RM, BM, true);
-    return __hiloint2double(h, l);
-}
-
-// Sum over the 64 lanes of a wave, valid in lane 63, by data-parallel-
-// primitive moves between registers (no LDS permute): within each row of 16
-// lanes, lane i adds lanes i-1, i-2, i-3 (row_shr 1..3), then lane i-4
-// (row_shr 4, lanes 4..15) and lane i-8 (row_shr 8, lanes 8..15), so lane 15
-// of each row holds the row's sum; rows 1 and 3 then add lane 15 of the row
-// before (row_bcast 15), and rows 2 and 3 add lane 31 (row_bcast 31).  The
-// order is fixed, so the sum is deterministic.
-__device__ __forceinline__ double wave_sum_dpp(double v) {
-    double t = v + dpp_read<0x111, 0xf, 0xf>(v);
-    t += dpp_read<0x112, 0xf, 0xf>(v);
-    t += dpp_read<0x113, 0xf, 0xf>(v);
-    t += dpp_read<0x114, 0xf, 0xe>(t);
-    t += dpp_read<0x118, 0xf, 0xc>(t);
-    t += dpp_read<0x142, 0xa, 0xf>(t);
-    t += dpp_read<0x143, 0xc, 0xf>(t);
-    return t;
-}
-
 // sum over the workgroup, returned to every thread (fixed order).  Successive
 // calls alternate between the two halves of `red` (2 x kWgWaves doubles), so
 // one barrier per call suffices: a half is rewritten only two calls later,
@@ -64,7 +35,7 @@ __device__ __forceinline__ double wave_sum_dpp(double v) {
 __device__ __forceinline__ double wg_sum_1024(double v, double *red, int &parity) {
     double *buf = red + parity * kWgWaves;
     parity ^= 1;
-    v = wave_sum_dpp(v);
+    v = ck::wave_sum_last(v);   // valid in lane 63
     if ((threadIdx.x & 63) == 63)
         buf[threadIdx.x >> 6] = v;
     __syncthreads();

@@ -25,9 +25,9 @@ namespace {
 // sum over the workgroup of BS threads, returned to every thread (fixed order)
 template <int BS, typename T>
 __device__ __forceinline__ T wg_sum(T v, T *lds) {
-    v = ck::wave_sum(v);
+    v = ck::wave_sum_last(v);   // valid in lane 63
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0)
+    if ((threadIdx.x & 63) == 63)
         lds[w] = v;
     __syncthreads();
     T r = (lds[0] + lds[1]) + (lds[2] + lds[3]);
@@ -346,8 +346,8 @@ __global__ __launch_bounds__(BS) void batched_chunk(ck::BSlot *slots, ck::BStat 
 #pragma unroll
                 for (int c = 0; c <= ck::kBMaxM; ++c)
                     if (c <= j) {
-                        const T v = ck::wave_sum(acc[c]);
-                        if ((tid & 63) == 0)
+                        const T v = ck::wave_sum_last(acc[c]);   // valid in lane 63
+                        if ((tid & 63) == 63)
                             wred[tid >> 6][c] = v;
                     }
                 __syncthreads();

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <mutex>
 #include <string>
+#include <type_traits>
 
 #include "../../include/caskrylov.h"
 
@@ -107,11 +108,19 @@ __device__ __forceinline__ T group_sum(T v) {
 }
 
 // Block (256 threads) sum, result valid in thread 0.  Fixed order.
+// Floating-point sums use the DPP wave sum (its total sits in lane 63).
 template <typename T>
 __device__ __forceinline__ T block_sum(T v, T *lds4) {
-    v = wave_sum(v);
+    constexpr bool fp = std::is_same<T, double>::value || std::is_same<T, float>::value;
+    int src = 0;
+    if constexpr (fp) {
+        v = wave_sum_last(v);
+        src = kWave - 1;
+    } else {
+        v = wave_sum(v);
+    }
     const int w = threadIdx.x / kWave;
-    if ((threadIdx.x & (kWave - 1)) == 0)
+    if ((int)(threadIdx.x & (kWave - 1)) == src)
         lds4[w] = v;
     __syncthreads();
     T r = 0;

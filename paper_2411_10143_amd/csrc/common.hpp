@@ -97,6 +97,29 @@ __device__ __forceinline__ T wave_sum_last(T v) {
     return t;
 }
 
+// Sum over groups of L consecutive lanes (L a power of two <= 64) by DPP
+// register moves, valid in lane L - 1 of each group (for L <= 16 in every
+// lane of the group): lanes exchange with lane ^ 1 and lane ^ 2 (quad
+// permutes), then add the mirrored half row (8) and the mirrored row (16);
+// rows 1 and 3 add lane 15 of the row before (32), rows 2 and 3 add lane 31
+// (64).  Fixed order: deterministic.
+template <int L, typename T>
+__device__ __forceinline__ T group_sum_last(T v) {
+    if constexpr (L >= 2)
+        v += dpp_read<0xb1, 0xf, 0xf>(v);    // quad_perm [1, 0, 3, 2]
+    if constexpr (L >= 4)
+        v += dpp_read<0x4e, 0xf, 0xf>(v);    // quad_perm [2, 3, 0, 1]
+    if constexpr (L >= 8)
+        v += dpp_read<0x141, 0xf, 0xf>(v);   // row_half_mirror
+    if constexpr (L >= 16)
+        v += dpp_read<0x140, 0xf, 0xf>(v);   // row_mirror
+    if constexpr (L >= 32)
+        v += dpp_read<0x142, 0xa, 0xf>(v);   // row_bcast 15 into rows 1, 3
+    if constexpr (L >= 64)
+        v += dpp_read<0x143, 0xc, 0xf>(v);   // row_bcast 31 into rows 2, 3
+    return v;
+}
+
 // Sum over groups of L consecutive lanes (L a power of two <= 64); every lane
 // of a group ends with the group total.  Fixed butterfly order: deterministic.
 template <int L, typename T>

@@ -191,7 +191,7 @@ __global__ __launch_bounds__(256) void spmv_dia(int n, int ncols, int64_t G, int
 }
 
 // HYB remainder: L lanes per long row t, entries rp[i] + K .. rp[i+1] - 1 of
-// row i = rows[t], two accumulators per lane, a butterfly over the L lanes;
+// row i = rows[t], two accumulators per lane, a DPP sum over the L lanes;
 // y[i] += alpha * sum (the ELL pass has already written y[i]).
 template <int L, typename T>
 __global__ __launch_bounds__(256) void spmv_hyb_tail(int64_t nt, int64_t G, int K,
@@ -226,8 +226,8 @@ __global__ __launch_bounds__(256) void spmv_hyb_tail(int64_t nt, int64_t G, int 
                 s0 += ld_stream(&val[k]) * x[ld_stream(&col[k])];
             sum = s0 + s1;
         }
-        sum = ck::group_sum<L>(sum);
-        if (lane == 0 && t < nt)
+        sum = ck::group_sum_last<L>(sum);   // valid in lane L - 1
+        if (lane == L - 1 && t < nt)
             y[i] += alpha * sum;
     }
 }

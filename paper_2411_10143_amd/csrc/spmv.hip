@@ -5,7 +5,7 @@
 // for CSR-vector.  On MI355X the kernels are written for wave64:
 //
 //   spmv_csr_vector<L>  L lanes (1..64) share one row, strided over its
-//                       entries; a butterfly over the L lanes sums them
+//                       entries; a DPP sum over the L lanes adds them
 //                       (Bell & Garland's CSR-vector; the paper's TpV).
 //   spmv_csr_scalar     one lane per row; the workgroup first forms the
 //                       products of its 256-row block in LDS with coalesced
@@ -90,8 +90,8 @@ __global__ __launch_bounds__(256) void spmv_csr_vector(int n, int64_t G,
                 s0 += ld_stream(&val[k]) * x[ld_stream(&col[k])];
             sum = s0 + s1;
         }
-        sum = ck::group_sum<L>(sum);
-        if (lane == 0 && row < n) {
+        sum = ck::group_sum_last<L>(sum);   // valid in lane L - 1
+        if (lane == L - 1 && row < n) {
             T out = alpha * sum;
             if (BETA)
                 out += beta * y[row];

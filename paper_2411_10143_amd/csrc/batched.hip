@@ -51,9 +51,24 @@ constexpr int kVec = 4;   // vector elements in flight per thread
 template <int BS>
 constexpr int rows_in_flight() { return BS >= 1024 ? 8 : 4; }
 
+// Sum over the L lanes of a row (L a run-time power of two, uniform over
+// the workgroup) by DPP moves, valid in lane L - 1 of each row's lanes.
+template <typename T>
+__device__ __forceinline__ T lanes_sum(T a, int L) {
+    switch (L) {
+    case 1: return a;
+    case 2: return ck::group_sum_last<2>(a);
+    case 4: return ck::group_sum_last<4>(a);
+    case 8: return ck::group_sum_last<8>(a);
+    case 16: return ck::group_sum_last<16>(a);
+    case 32: return ck::group_sum_last<32>(a);
+    default: return ck::group_sum_last<64>(a);
+    }
+}
+
 // y[i] = s1 * (A x)[i] + s0 * z[i] with L lanes per row (runtime power of
 // two).  Per row the lanes sum entries start + lane, start + lane + L, ...
-// in order, then butterfly over the L lanes.
+// in order, then a DPP sum over the L lanes.
 template <int BS, typename TV, typename TX, typename TA>
 __device__ void wg_spmv(int n, int L, const int *__restrict__ rp, const int *__restrict__ col,
                         const TV *__restrict__ val, const TX *__restrict__ x, TA s1, TA s0,
@@ -97,11 +112,9 @@ __device__ void wg_spmv(int n, int L, const int *__restrict__ rp, const int *__r
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            TA a = acc[u];
-            for (int off = L >> 1; off > 0; off >>= 1)
-                a += __shfl_xor(a, off, 64);
+            const TA a = lanes_sum(acc[u], L);   // valid in lane L - 1 of the row's lanes
             const int row = r0 + u * rpp + threadIdx.x / L;
-            if (lane == 0 && row < n)
+            if (lane == L - 1 && row < n)
                 y[row] = z ? s1 * a + s0 * z[row] : s1 * a;
         }
     }

@@ -77,6 +77,15 @@ __device__ __forceinline__ float dpp_read(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RM, BM, true));
 }
 
+template <int CTRL, int RM, int BM>
+__device__ __forceinline__ unsigned long long dpp_read(unsigned long long v) {
+    const unsigned l = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)v, CTRL, RM, BM,
+                                                             true);
+    const unsigned h = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(v >> 32), CTRL,
+                                                             RM, BM, true);
+    return ((unsigned long long)h << 32) | l;
+}
+
 // Sum over the 64 lanes of a wave, valid in lane 63 only, by data-parallel-
 // primitive moves between registers (no LDS permute, so a step costs a few
 // cycles instead of an LDS round trip): within each row of 16 lanes, lane i
@@ -95,6 +104,24 @@ __device__ __forceinline__ T wave_sum_last(T v) {
     t += dpp_read<0x142, 0xa, 0xf>(t);
     t += dpp_read<0x143, 0xc, 0xf>(t);
     return t;
+}
+
+// Maximum over the 64 lanes of a wave (unsigned: lanes without a source
+// read 0, the identity), valid in lane 63, in the steps of wave_sum_last.
+__device__ __forceinline__ unsigned long long wave_max_last(unsigned long long v) {
+    auto mx = [](unsigned long long a, unsigned long long b) { return a > b ? a : b; };
+    unsigned long long t = mx(v, dpp_read<0x111, 0xf, 0xf>(v));
+    t = mx(t, dpp_read<0x112, 0xf, 0xf>(v));
+    t = mx(t, dpp_read<0x113, 0xf, 0xf>(v));
+    t = mx(t, dpp_read<0x114, 0xf, 0xe>(t));
+    t = mx(t, dpp_read<0x118, 0xf, 0xc>(t));
+    t = mx(t, dpp_read<0x142, 0xa, 0xf>(t));
+    t = mx(t, dpp_read<0x143, 0xc, 0xf>(t));
+    return t;
+}
+// Minimum: the maximum of the complements, complemented.
+__device__ __forceinline__ unsigned long long wave_min_last(unsigned long long v) {
+    return ~wave_max_last(~v);
 }
 
 // Sum over groups of L consecutive lanes (L a power of two <= 64) by DPP

@@ -31,25 +31,6 @@ __device__ __forceinline__ int hist_bin(long long r) {
     return b < 15 ? b : 15;
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_max_u64(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const T o = __shfl_xor(v, off, 64);
-        v = o > v ? o : v;
-    }
-    return v;
-}
-template <typename T>
-__device__ __forceinline__ T wave_min_u64(T v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        const T o = __shfl_xor(v, off, 64);
-        v = o < v ? o : v;
-    }
-    return v;
-}
-
 }  // namespace
 
 // Clears n16 16-byte words.
@@ -123,17 +104,18 @@ __global__ __launch_bounds__(256) void feat_rows(int64_t n, int64_t nnz,
     }
 #pragma unroll
     for (int b = 0; b < 16; ++b) {
-        const unsigned long long t = ck::wave_sum((unsigned long long)hc[b]);
-        if ((threadIdx.x & 63) == 0 && t)
+        const unsigned long long t = ck::wave_sum_last((unsigned long long)hc[b]);
+        if ((threadIdx.x & 63) == 63 && t)
             atomicAdd(&h[b], t);
     }
-    r = ck::wave_sum(r);
-    r2 = ck::wave_sum(r2);
-    span = ck::wave_sum(span);
-    mx = wave_max_u64(mx);
-    mn = wave_min_u64(mn);
+    // wave totals in lane 63 (DPP moves; integer sums, max and min are exact)
+    r = ck::wave_sum_last(r);
+    r2 = ck::wave_sum_last(r2);
+    span = ck::wave_sum_last(span);
+    mx = ck::wave_max_last(mx);
+    mn = ck::wave_min_last(mn);
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
+    if ((threadIdx.x & 63) == 63) {
         part[0][w] = r;
         part[1][w] = r2;
         part[2][w] = span;
@@ -252,11 +234,11 @@ __device__ __forceinline__ void add_block_counts(unsigned long long cl, unsigned
                                                  unsigned long long asym, FeatAcc *acc,
                                                  unsigned long long *__restrict__ slot) {
     __shared__ unsigned long long part[3][4];
-    cl = ck::wave_sum(cl);
-    dcount = ck::wave_sum(dcount);
-    asym = ck::wave_sum(asym);
+    cl = ck::wave_sum_last(cl);   // wave totals in lane 63
+    dcount = ck::wave_sum_last(dcount);
+    asym = ck::wave_sum_last(asym);
     const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
+    if ((threadIdx.x & 63) == 63) {
         part[0][w] = cl;
         part[1][w] = dcount;
         part[2][w] = asym;
@@ -399,8 +381,8 @@ __global__ __launch_bounds__(256) void feat_ndiag(int64_t n16, const uint4 *__re
              ((w.z * 0x01010101u) >> 24) + ((w.w * 0x01010101u) >> 24);
     }
     __shared__ unsigned long long part[4];
-    c = ck::wave_sum(c);
-    if ((threadIdx.x & 63) == 0)
+    c = ck::wave_sum_last(c);   // valid in lane 63
+    if ((threadIdx.x & 63) == 63)
         part[threadIdx.x >> 6] = c;
     __syncthreads();
     if (threadIdx.x == 0)
@@ -444,13 +426,13 @@ __global__ __launch_bounds__(1024) void feat_finish(FeatAcc *acc, const unsigned
 #pragma unroll
     for (int f = 0; f < F; ++f) {
         unsigned long long t;
-        if (f == 3)
-            t = wave_max_u64(v[f]);
+        if (f == 3)   // wave results in lane 63
+            t = ck::wave_max_last(v[f]);
         else if (f == 4)
-            t = wave_min_u64(v[f]);
+            t = ck::wave_min_last(v[f]);
         else
-            t = ck::wave_sum(v[f]);
-        if ((threadIdx.x & 63) == 0)
+            t = ck::wave_sum_last(v[f]);
+        if ((threadIdx.x & 63) == 63)
             part[f][w] = t;
     }
     __syncthreads();
@@ -601,8 +583,8 @@ __global__ __launch_bounds__(256) void row_max(int64_t n, const int *__restrict_
                                                unsigned long long *out) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     unsigned long long r = i < n ? (unsigned long long)(rp[i + 1] - rp[i]) : 0ull;
-    r = wave_max_u64(r);
-    if ((threadIdx.x & 63) == 0)
+    r = ck::wave_max_last(r);   // valid in lane 63
+    if ((threadIdx.x & 63) == 63)
         atomicMax(out, r);
 }
 

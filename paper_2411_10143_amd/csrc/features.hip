@@ -281,23 +281,27 @@ __global__ __launch_bounds__(256) void feat_nnz(int64_t n, const int *__restrict
             if (r > kLongRow)
                 r = 0;                      // feat_long's row
         }
-        int rmax = r;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-            rmax = max(rmax, __shfl_xor(rmax, off, 64));
+        // the wave's longest row (every lane runs the steps below together,
+        // so the DPP moves always read active lanes)
+        const int rmax = (int)__builtin_amdgcn_readlane(
+            (int)ck::wave_max_last((unsigned long long)r), 63);
         Stretch st{0, 0};
         int prev_last = 0;
         for (int t = 0; t < rmax; t += L) {
             const bool in = t + lane < r;
             const int k = k0 + t + lane;
             const int c = in ? col[k] : 0;
-            int cprev = __shfl_up(c, 1, L);
+            // previous lane's column (row shift by 1; a group's first lane
+            // takes the previous step's last column instead)
+            int cprev = __builtin_amdgcn_update_dpp(0, c, 0x111, 0xf, 0xf, true);
             if (lane == 0)
                 cprev = prev_last;
             const bool cont = in && t + lane > 0 && c == cprev + 1;
             const unsigned long long bal = __ballot(cont);
             fold_step<L>(st, bal >> gbase);
-            prev_last = __shfl(c, gbase + L - 1, 64);
+            // the group's last column, for its first lane (half-row mirror:
+            // lane 0 of each eight reads lane 7)
+            prev_last = __builtin_amdgcn_update_dpp(0, c, 0x141, 0xf, 0xf, true);
             if (in) {
                 memo.mark((int64_t)c - i + (n - 1), diag_flag);
                 if (c == i)

@@ -124,6 +124,34 @@ __device__ __forceinline__ unsigned long long wave_min_last(unsigned long long v
     return ~wave_max_last(~v);
 }
 
+// Inclusive scan of v over the lanes of a wave, restarted wherever key
+// changes: a lane gets the sum of v over the lanes of its run up to itself.
+// Lanes with equal keys must form one contiguous run, except key -1, whose
+// lanes may get any value.  DPP moves only: within each row of 16 lanes,
+// lane i adds lane i-1, then i-2, i-4, i-8 (row_shr, each only if that
+// lane has the same key), so every lane holds its run's sum within its row;
+// rows 1 and 3 then add lane 15 of the row before (row_bcast 15) and rows 2
+// and 3 lane 31 (row_bcast 31), again only on equal keys.  Keys move as
+// key + 2, so a lane with no source (which reads 0) never matches.  Fixed
+// order: deterministic.
+template <int CTRL, int RM, typename T>
+__device__ __forceinline__ void seg_scan_step(T &v, int k) {
+    const int ku = __builtin_amdgcn_update_dpp(0, k, CTRL, RM, 0xf, true);
+    const T vu = dpp_read<CTRL, RM, 0xf>(v);
+    v = ku == k ? v + vu : v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_seg_scan(T v, int key) {
+    const int k = key + 2;
+    seg_scan_step<0x111, 0xf>(v, k);
+    seg_scan_step<0x112, 0xf>(v, k);
+    seg_scan_step<0x114, 0xf>(v, k);
+    seg_scan_step<0x118, 0xf>(v, k);
+    seg_scan_step<0x142, 0xa>(v, k);
+    seg_scan_step<0x143, 0xc>(v, k);
+    return v;
+}
+
 // Sum over groups of L consecutive lanes (L a power of two <= 64) by DPP
 // register moves, valid in lane L - 1 of each group (for L <= 16 in every
 // lane of the group): lanes exchange with lane ^ 1 and lane ^ 2 (quad

@@ -251,24 +251,42 @@ __global__ __launch_bounds__(256) void spmv_hyb_ell(int n, int64_t G, int K, int
 }
 
 // ---- carry completion shared by merge-path and COO -------------------------
-// Every active thread left in LDS: the row it ended inside (crow, -1 if
-// none) with its partial (cval), and the first row it completed (frow, -1 if
-// none) with its own part of that row (fval).  The first completed row of a
-// thread started in earlier threads: add their carries (ascending order).
-// Thread 0 then records the block's own carry-out for carry_fixup.
+// Every thread passes the row it ended inside (crow, -1 if none) with its
+// partial (cval), and the first row it completed (frow, -1 if none) with its
+// own part of that row (fval).  Across the workgroup, equal crow values form
+// one contiguous run of threads (rows only grow with the thread index).  The
+// first completed row of a thread started in the run just before it: add
+// that run's partials.  Thread 0 then records the block's own carry-out (the
+// run ending at the last active thread) for carry_fixup.  The run sums come
+// from a segmented scan: within each wave by DPP moves, then across the four
+// waves through LDS, so a row spanning the whole workgroup costs a few steps
+// instead of one LDS round trip per thread.
 template <typename T, bool BETA>
-__device__ __forceinline__ void finish_carries(int *s_crow, T *s_cval, int frow, T fval,
-                                               int last_active, int64_t b, T alpha, T beta,
-                                               T *__restrict__ y, int *__restrict__ crow_g,
+__device__ __forceinline__ void finish_carries(int *s_crow, T *s_cval, int crow, T cval,
+                                               int frow, T fval, int last_active, int64_t b,
+                                               T alpha, T beta, T *__restrict__ y,
+                                               int *__restrict__ crow_g,
                                                T *__restrict__ cval_g) {
     const int tid = threadIdx.x;
+    s_crow[tid] = crow;
+    s_cval[tid] = ck::wave_seg_scan(cval, crow);
+    __syncthreads();
+    // sum of the partials of the run ending at thread p: its wave's part,
+    // then the runs ending each earlier wave while the run goes on
+    auto run_to = [&](int p) {
+        const int key = s_crow[p];
+        T tot = s_cval[p];
+        for (int u = (p >> 6) - 1; u >= 0; --u) {
+            if (s_crow[64 * u + 63] != key)
+                break;
+            tot += s_cval[64 * u + 63];
+            if (s_crow[64 * u] != key)
+                break;
+        }
+        return tot;
+    };
     if (frow >= 0) {
-        int s = tid - 1;
-        while (s >= 0 && s_crow[s] == frow)
-            --s;
-        T tot = 0;
-        for (int u = s + 1; u < tid; ++u)
-            tot += s_cval[u];
+        T tot = tid > 0 && s_crow[tid - 1] == frow ? run_to(tid - 1) : T(0);
         tot += fval;
         T out = alpha * tot;
         if (BETA)
@@ -277,16 +295,8 @@ __device__ __forceinline__ void finish_carries(int *s_crow, T *s_cval, int frow,
     }
     if (tid == 0) {
         const int R = last_active >= 0 ? s_crow[last_active] : -1;
-        T tot = 0;
-        if (R >= 0) {
-            int s = last_active;
-            while (s >= 0 && s_crow[s] == R)
-                --s;
-            for (int u = s + 1; u <= last_active; ++u)
-                tot += s_cval[u];
-        }
         crow_g[b] = R;
-        cval_g[b] = tot;
+        cval_g[b] = R >= 0 ? run_to(last_active) : T(0);
     }
 }
 
@@ -426,14 +436,11 @@ __device__ __forceinline__ void merge_rows(int n, int nnz, int64_t G, const int 
         crow = i0 + a < n ? i0 + a : -1;
         cval = acc;
     }
-    s_crow[tid] = crow;
-    s_cval[tid] = cval;
-    __syncthreads();
     const int64_t first_d = b * 256 * kMergeIPT;
     const int last_active =
         (int)min<int64_t>(255, (P - first_d + kMergeIPT - 1) / kMergeIPT - 1);
-    finish_carries<T, BETA>(s_crow, s_cval, frow, fval, last_active, b, alpha, beta, y, crow_g,
-                            cval_g);
+    finish_carries<T, BETA>(s_crow, s_cval, crow, cval, frow, fval, last_active, b, alpha, beta,
+                            y, crow_g, cval_g);
 }
 
 template <typename T, bool BETA>
@@ -554,17 +561,16 @@ __global__ __launch_bounds__(256) void spmv_coo(int n, int nnz, int64_t G,
             cval = acc;
         }
     }
-    s_crow[tid] = crow;
-    s_cval[tid] = cval;
-    __syncthreads();
     const int64_t first_k = b * 256 * kCooIPT;
     const int last_active = (int)min<int64_t>(255, (nnz - first_k + kCooIPT - 1) / kCooIPT - 1);
-    finish_carries<T, BETA>(s_crow, s_cval, frow, fval, last_active, b, alpha, beta, y, crow_g,
-                            cval_g);
+    finish_carries<T, BETA>(s_crow, s_cval, crow, cval, frow, fval, last_active, b, alpha, beta,
+                            y, crow_g, cval_g);
 }
 
 // Rows cut by a workgroup boundary: each run of equal carry rows is summed in
-// block order by the run's first entry and added once.
+// block order by the run's first entry and added once.  The carries are read
+// eight at a time (loads issued together, indexes clamped to the array), so a
+// row spanning many workgroups does not wait one load latency per workgroup.
 template <typename T>
 __global__ __launch_bounds__(256) void carry_fixup(int64_t G, const int *__restrict__ crow,
                                                    const T *__restrict__ cval, T alpha,
@@ -579,8 +585,25 @@ __global__ __launch_bounds__(256) void carry_fixup(int64_t G, const int *__restr
     if (R < 0 || (b > 0 && crow[b - 1] == R))
         return;
     T tot = 0;
-    for (int64_t e = b; e < G && crow[e] == R; ++e)
-        tot += cval[e];
+    for (int64_t e0 = b; e0 < G; e0 += 8) {
+        int r[8];
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int64_t e = min<int64_t>(e0 + u, G - 1);
+            r[u] = crow[e];
+            v[u] = cval[e];
+        }
+        bool more = true;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            more = more && e0 + u < G && r[u] == R;
+            if (more)
+                tot += v[u];
+        }
+        if (!more)
+            break;
+    }
     y[R] += alpha * tot;
 }
 

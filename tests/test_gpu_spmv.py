@@ -25,6 +25,10 @@ CASES = {
     "int_ragged": lambda: M.random_integer(3001, 2800, 1, density=0.004, empty_rows=0.2,
                                            long_rows=3, long_len=2500),
     "int_wide": lambda: M.random_integer(700, 9000, 2, density=0.01, empty_rows=0.0),
+    # four rows of 20,000 entries: each spans about ten merge-path workgroups
+    # and every wave of them (the carry runs across waves and workgroups)
+    "int_hub": lambda: M.random_integer(2000, 40000, 9, density=0.0005, empty_rows=0.1,
+                                        long_rows=4, long_len=20000),
     "powerlaw": lambda: M.power_law_rows(20011, 1.6, 3),
     "banded27": lambda: M.banded_stencil(30011, 27, 4),
     "banded9": lambda: M.banded_stencil(5003, 9, 5),
@@ -106,8 +110,8 @@ def test_spmv_all_configs_fp64(ck, orc, name):
     Mx.close()
 
 
-@pytest.mark.parametrize("name", ["int_ragged", "powerlaw", "banded27", "uniform", "empty",
-                                  "single_row", "lap1d", "lap2d_64", "lap3d_12", "banded9",
+@pytest.mark.parametrize("name", ["int_ragged", "int_hub", "powerlaw", "banded27", "uniform",
+                                  "empty", "single_row", "lap1d", "lap2d_64", "lap3d_12", "banded9",
                                   "banded13", "banded19", "blockdiag"])
 def test_spmv_all_configs_fp32(ck, orc, name):
     import torch
@@ -178,7 +182,7 @@ def test_dia_and_hyb_layouts_bit_exact(ck, orc, name):
     Mx.close()
 
 
-@pytest.mark.parametrize("name", ["int_ragged", "int_wide", "powerlaw", "banded27", "blockdiag",
+@pytest.mark.parametrize("name", ["int_ragged", "int_wide", "int_hub", "powerlaw", "banded27", "blockdiag",
                                   "uniform", "lap2d_64", "convdiff", "empty", "one_by_one",
                                   "single_row", "single_col", "column_runs"])
 def test_features_bit_exact(ck, orc, name):

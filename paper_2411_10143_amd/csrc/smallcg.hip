@@ -6,7 +6,10 @@
 // x, r, p and q of its rows live in registers, p also in LDS (the product
 // gathers it from there), and only the matrix (L2-resident after the first
 // step) and, at the rare residual steps, b are read from memory.  When no
-// row has more than 16 entries the matrix is first copied column-major into
+// row has more than 5 entries (1D and 2D stencils, convection-diffusion) the
+// matrix itself is loaded into registers once per solve and every product
+// only gathers p from LDS.  Otherwise, when no
+// row has more than 16 entries, the matrix is first copied column-major into
 // a scratch buffer, so that each product reads it in whole cache lines (the
 // row-major arrays, read one entry per lane per step, re-fetched partly used
 // lines at every step).  The product sums each row with one lane in
@@ -26,6 +29,7 @@ namespace {
 
 constexpr int kWgThreads = 1024;
 constexpr int kWgWaves = kWgThreads / 64;
+constexpr int kWgCgRegK = 5;   // longest row kept in registers
 
 // sum over the workgroup, returned to every thread (fixed order).  Successive
 // calls alternate between the two halves of `red` (2 x kWgWaves doubles), so
@@ -110,56 +114,91 @@ __device__ __forceinline__ void wg_matvec_cm(const int (&len)[R], int K,
     }
 }
 
+// The product with the matrix in registers: slot k of local row u holds
+// rv[k][u] and its column, the 16-bit half k % 2 of rcp[k / 2][u] (columns
+// are below 4096), loaded once per solve.  Slots past the row's length hold
+// value 0 and column 0: p[0] is finite while the solve runs (a non-finite
+// p.q ends it first) and q starts at +0, so adding 0 * p[0] leaves q's bits
+// unchanged, and every row's sum equals, bit for bit, the other forms' sum
+// of its entries in the same order.
+constexpr int kWgRegPairs = (kWgCgRegK + 1) / 2;
+template <int R>
+__device__ __forceinline__ void wg_matvec_reg(const unsigned (&rcp)[kWgRegPairs][R],
+                                              const double (&rv)[kWgCgRegK][R], const double *v,
+                                              double (&q)[R]) {
+#pragma unroll
+    for (int u = 0; u < R; ++u)
+        q[u] = 0;
+    // gathers in rounds of G slots (all rows' loads of a round in flight
+    // together; more at once would spill registers at four rows per lane)
+    constexpr int G = R >= 4 ? 1 : kWgCgRegK;
+#pragma unroll
+    for (int k0 = 0; k0 < kWgCgRegK; k0 += G) {
+        double g[G][R];
+#pragma unroll
+        for (int k = k0; k < k0 + G && k < kWgCgRegK; ++k)
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+                // an empty statement that claims to change w: the columns are
+                // unpacked here, at each use, instead of being hoisted out of
+                // the CG loop as 20 loop-invariant registers
+                unsigned w = rcp[k >> 1][u];
+                asm volatile("" : "+v"(w));
+                g[k - k0][u] = v[(k & 1) ? (w >> 16) : (w & 0xffffu)];
+            }
+#pragma unroll
+        for (int k = k0; k < k0 + G && k < kWgCgRegK; ++k)
+#pragma unroll
+            for (int u = 0; u < R; ++u)
+                q[u] += rv[k][u] * g[k - k0][u];
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
 }  // namespace
 
-// ccol / cval: scratch of kWgCgColMajorK / 2 * R * 1024 pairs for the
-// column-major copy, used when no row has more than kWgCgColMajorK entries.
-template <int R>
-__global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict__ rp,
-                                                    const int *__restrict__ col,
-                                                    const double *__restrict__ val,
-                                                    const double *__restrict__ b,
-                                                    double *__restrict__ x, double tol,
-                                                    int max_iter, int2 *__restrict__ ccol,
-                                                    double2 *__restrict__ cval,
-                                                    ck::WgCgOut *out) {
+// The solve after the prologue, one instantiation per product form (the
+// form is fixed for the whole solve, so each keeps only its own state live):
+// the matrix in registers, the column-major copy, or the row-major arrays.
+enum { kWgRows = 0, kWgColMajor = 1, kWgReg = 2 };
+template <int R, int MODE>
+__device__ __forceinline__ void cg_wg_run(int n, const int (&kb)[R], const int (&ke)[R],
+                                          const int (&len)[R], int trips, int K,
+                                          double (&xr)[R], double bb,
+                                          const int *__restrict__ col,
+                                          const double *__restrict__ val,
+                                          const double *__restrict__ b, double *__restrict__ x,
+                                          double tol, int max_iter, int2 *__restrict__ ccol,
+                                          double2 *__restrict__ cval, ck::WgCgOut *out,
+                                          double *v, double *red, int parity) {
     constexpr int RW = R * kWgThreads;
-    __shared__ double v[kWgThreads * R];   // p (or x while forming the residual)
-    __shared__ double red[2 * kWgWaves];
-    __shared__ int kmax[kWgWaves];
-    int parity = 0;
     const int t = threadIdx.x;
-    int kb[R], ke[R], len[R];
-    double xr[R], rr[R], pr[R], q[R];
-    int trips = 0;
-    double bb = 0;
+    double rr[R], pr[R], q[R];
+    constexpr bool reg = MODE == kWgReg, cm = MODE == kWgColMajor;
+    unsigned rcp[kWgRegPairs][R];
+    double rv[kWgCgRegK][R];
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
-        const int i = t + u * kWgThreads;
-        const bool in = i < n;
-        kb[u] = in ? rp[i] : 0;
-        ke[u] = in ? rp[i + 1] : 0;
-        len[u] = ke[u] - kb[u];
-        const double bi = in ? b[i] : 0.0;
-        xr[u] = in ? x[i] : 0.0;
-        trips = max(trips, ke[u] - kb[u]);
-        bb += bi * bi;
-    }
-    // longest row of the system; at most kWgCgColMajorK entries: build the
-    // column-major copy (once per solve) and run every product from it
-    int K = trips;
+    for (int u = 0; u < R; ++u)
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1)
-        K = max(K, __shfl_xor(K, off, 64));
-    if ((t & 63) == 0)
-        kmax[t >> 6] = K;
-    __syncthreads();
-    K = 0;
+        for (int k = 0; k < kWgRegPairs; ++k)
+            rcp[k][u] = 0;
 #pragma unroll
-    for (int w = 0; w < kWgWaves; ++w)
-        K = max(K, kmax[w]);
-    const bool cm = K <= ck::kWgCgColMajorK;
-    if (cm) {
+    for (int k = 0; k < kWgCgRegK; ++k)
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+            const bool in = reg && k < len[u];
+            rcp[k >> 1][u] |= (in ? (unsigned)col[kb[u] + k] : 0u) << (16 * (k & 1));
+            rv[k][u] = in ? val[kb[u] + k] : 0.0;
+        }
+    auto matvec = [&]() {
+        if constexpr (reg)
+            wg_matvec_reg<R>(rcp, rv, v, q);
+        else if constexpr (cm)
+            wg_matvec_cm<R>(len, K, ccol, cval, v, q);
+        else
+            wg_matvec<R>(kb, ke, trips, col, val, v, q);
+    };
+    if constexpr (cm) {
         for (int s = 0; s < K; s += 2) {
 #pragma unroll
             for (int u = 0; u < R; ++u) {
@@ -191,10 +230,7 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
                 if (t + u * kWgThreads < n)
                     v[t + u * kWgThreads] = xr[u];
             __syncthreads();
-            if (cm)
-                wg_matvec_cm<R>(len, K, ccol, cval, v, q);
-            else
-                wg_matvec<R>(kb, ke, trips, col, val, v, q);
+            matvec();
             double rho = 0;
 #pragma unroll
             for (int u = 0; u < R; ++u) {
@@ -220,10 +256,7 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
                     if (t + u * kWgThreads < n)
                         v[t + u * kWgThreads] = pr[u];
                 __syncthreads();
-                if (cm)
-                    wg_matvec_cm<R>(len, K, ccol, cval, v, q);
-                else
-                    wg_matvec<R>(kb, ke, trips, col, val, v, q);
+                matvec();
                 double pq = 0;
 #pragma unroll
                 for (int u = 0; u < R; ++u)
@@ -263,10 +296,7 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
                 if (t + u * kWgThreads < n)
                     v[t + u * kWgThreads] = xr[u];
             __syncthreads();
-            if (cm)
-                wg_matvec_cm<R>(len, K, ccol, cval, v, q);
-            else
-                wg_matvec<R>(kb, ke, trips, col, val, v, q);
+            matvec();
             double tr = 0;
 #pragma unroll
             for (int u = 0; u < R; ++u) {
@@ -297,6 +327,61 @@ __global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict
         out->restarts = restarts;
         out->relres = relres;
     }
+}
+
+// ccol / cval: scratch of kWgCgColMajorK / 2 * R * 1024 pairs for the
+// column-major copy, used when no row has more than kWgCgColMajorK entries.
+template <int R>
+__global__ __launch_bounds__(kWgThreads) void cg_wg(int n, const int *__restrict__ rp,
+                                                    const int *__restrict__ col,
+                                                    const double *__restrict__ val,
+                                                    const double *__restrict__ b,
+                                                    double *__restrict__ x, double tol,
+                                                    int max_iter, int2 *__restrict__ ccol,
+                                                    double2 *__restrict__ cval,
+                                                    ck::WgCgOut *out) {
+    __shared__ double v[kWgThreads * R];   // p (or x while forming the residual)
+    __shared__ double red[2 * kWgWaves];
+    __shared__ int kmax[kWgWaves];
+    int parity = 0;
+    const int t = threadIdx.x;
+    int kb[R], ke[R], len[R];
+    double xr[R];
+    int trips = 0;
+    double bb = 0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        const int i = t + u * kWgThreads;
+        const bool in = i < n;
+        kb[u] = in ? rp[i] : 0;
+        ke[u] = in ? rp[i + 1] : 0;
+        len[u] = ke[u] - kb[u];
+        const double bi = in ? b[i] : 0.0;
+        xr[u] = in ? x[i] : 0.0;
+        trips = max(trips, ke[u] - kb[u]);
+        bb += bi * bi;
+    }
+    // longest row of the system: it picks the product form for the solve
+    int K = trips;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        K = max(K, __shfl_xor(K, off, 64));
+    if ((t & 63) == 0)
+        kmax[t >> 6] = K;
+    __syncthreads();
+    K = 0;
+#pragma unroll
+    for (int w = 0; w < kWgWaves; ++w)
+        K = max(K, kmax[w]);
+    if (K <= kWgCgRegK)
+        cg_wg_run<R, kWgReg>(n, kb, ke, len, trips, K, xr, bb, col, val, b, x, tol, max_iter,
+                             ccol, cval, out, v, red, parity);
+    else if (K <= ck::kWgCgColMajorK)
+        cg_wg_run<R, kWgColMajor>(n, kb, ke, len, trips, K, xr, bb, col, val, b, x, tol,
+                                  max_iter, ccol, cval, out, v, red, parity);
+    else
+        cg_wg_run<R, kWgRows>(n, kb, ke, len, trips, K, xr, bb, col, val, b, x, tol, max_iter,
+                              ccol, cval, out, v, red, parity);
 }
 
 namespace ck {

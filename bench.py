@@ -477,14 +477,15 @@ def bench_cg_lap2d(args):
     _solve_json(args, len(lat) / total, "solves/s", 1e3 * total / args.steps,
                 "cg_lap2d_64: FP64 CG, 2D 5-point Laplacian 64x64 (n=4096), tol 1e-10; "
                 "the library's default path for n <= 4096: the whole solve in one "
-                "single-workgroup launch (CSR-vector product, one lane per row)",
+                "single-workgroup launch (CSR-vector product, one lane per row, the "
+                "matrix held in registers)",
                 {"latency_ms": {"p50": round(1e3 * float(np.percentile(lat, 50)), 3),
                                 "p99": round(1e3 * float(np.percentile(lat, 99)), 3)},
                  "iterations": int(np.median(iters)), "solves": len(lat)},
                 {"bound": "hbm", "kernel": "cg_wg<4> (single-workgroup CG)",
                  "achieved": round(eff, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                  "frac": round(eff / HBM_PEAK_GBS, 5), "traffic": None,
-                 "note": "n=4096: the whole system sits in one CU's share of L2 and LDS; "
+                 "note": "n=4096: the whole system sits in one CU's registers and LDS; "
                          "latency-bound, not an HBM roofline claim"}, cpu)
 
 
@@ -834,7 +835,7 @@ def solver_summary(args):
     lat, r, x = _timed_solves(ck, ck.cg_solve, Mx, b, 100, 5, tol=1e-10)
     assert oracle.relres(A, b.cpu().numpy(), x.cpu().numpy()) <= 1e-10
     row = {"default_path": {**_lat(lat), "iterations": r["iterations"],
-                            "kernel": "cg_wg<4>: whole solve in one workgroup, one lane per row"}}
+                            "kernel": "cg_wg<4>: whole solve in one workgroup, one lane per row, matrix in registers"}}
     cfg = ck.default_config(Mx.handle)
     lat, r, x = _timed_solves(ck, ck.cg_solve, Mx, b, 100, 5, tol=1e-10, config=cfg)
     assert oracle.relres(A, b.cpu().numpy(), x.cpu().numpy()) <= 1e-10

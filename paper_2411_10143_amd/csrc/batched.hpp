@@ -45,9 +45,10 @@ struct WgCgOut {
     int status, iter, restarts, pad;
     double relres;   // true relative residual at exit
 };
-// Rows of at most this many entries (even) are copied column-major once per
-// solve into cm_col / cm_val: kWgCgColMajorK * kWgCgMaxN ints and doubles,
-// 16-byte aligned.
+// When the longest row has 6 to this many entries (even), the matrix is
+// copied column-major once per solve into cm_col / cm_val: kWgCgColMajorK *
+// kWgCgMaxN ints and doubles, 16-byte aligned (rows of at most 5 entries are
+// held in registers instead, and longer ones read in place).
 constexpr int kWgCgColMajorK = 16;
 ck_status launch_cg_wg(int n, const int *rp, const int *col, const double *val, const double *b,
                        double *x, double tol, int max_iter, void *cm_col, void *cm_val,

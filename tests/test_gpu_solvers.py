@@ -83,6 +83,49 @@ def test_cg_single_workgroup_path(ck, orc, name):
     Mx.close()
 
 
+def _pad_row_with_zeros(A, extra):
+    """A copy of A with `extra` stored zeros appended to its middle row, at
+    columns after the row's last one: every row sum keeps its bits, while
+    the longest row, which picks the single-workgroup CG's product form
+    (registers up to 5 entries, a column-major copy up to 16, else the
+    row-major arrays), grows to len + extra."""
+    i = A.n // 2
+    k0, k1 = A.rp[i], A.rp[i + 1]
+    last = A.col[k1 - 1]
+    assert last + extra < A.ncols
+    cols = np.concatenate([A.col[:k1], np.arange(last + 1, last + 1 + extra, dtype=A.col.dtype),
+                           A.col[k1:]])
+    vals = np.concatenate([A.val[:k1], np.zeros(extra), A.val[k1:]])
+    rp = A.rp.copy()
+    rp[i + 1:] += extra
+    return M.CSR(A.n, A.ncols, rp, cols, vals)
+
+
+@pytest.mark.parametrize("name", ["lap2d_32", "lap1d_1025", "lap2d_64"])
+def test_cg_single_workgroup_forms_agree_bitwise(ck, orc, name):
+    """The three product forms of the single-workgroup CG sum each row's
+    entries in the same order, so the same system solved through each gives
+    the same iterates to the last bit (one, two and four rows per lane)."""
+    A = {"lap2d_32": lambda: M.laplacian_2d(32), "lap1d_1025": lambda: M.laplacian_1d(1025),
+         "lap2d_64": lambda: M.laplacian_2d(64)}[name]()
+    xs, b = problem(orc, A, 12)
+    i = A.n // 2
+    L = int(A.rp[i + 1] - A.rp[i])
+    assert int(np.max(np.diff(A.rp))) <= 5
+    outs = []
+    for extra in (0, 6 - L, 17 - L):   # longest row <= 5, then 6, then 17
+        B = _pad_row_with_zeros(A, extra) if extra else A
+        say(f"cg single-workgroup forms {name} extra zeros={extra} nnz={B.nnz}")
+        Mx = ck.Matrix.from_csr(B)
+        x, r = run(ck, ck.cg_solve, Mx, b, tol=1e-10)
+        Mx.close()
+        assert r["status"] == ck.CK_OK and orc.relres(A, b, x) <= 1e-10, (extra, r)
+        outs.append((x, r["iterations"]))
+    for x, it in outs[1:]:
+        assert it == outs[0][1]
+        assert np.array_equal(x.view(np.int64), outs[0][0].view(np.int64))
+
+
 def test_cg_above_single_workgroup_limit(ck, orc):
     A = M.laplacian_1d(4097)
     xs, b = problem(orc, A, 10)
